@@ -1,0 +1,182 @@
+"""Python access to the plain FP64 CPU oracle (``oracle/oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.  It shares no code
+with the GPU path.  Arrays are per-trajectory rows (``[n][d]``, ``[n][P]``),
+the natural layout for a one-trajectory-at-a-time reference.
+
+What each call follows in the paper:
+  record  -- the adaptive solve with embedded error estimate, RMS acceptance
+             test and step-size controller (Section 2.1), keeping the accepted
+             mesh (Section 3.1) and the states at requested times, each
+             reached by one extra step (Section 3.4).
+  replay  -- the fixed chain of eq. (replay) on a frozen mesh, in double,
+             dual numbers (forward mode) or complex arithmetic (complex step).
+  adjoint -- the reverse sweep of that chain with the mesh held fixed
+             (Section 3.1, the sg[h] convention).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+LORENZ, VDP, ROBERTSON, HIRES, LV_UDE, LINEAR = 1, 2, 3, 4, 5, 6
+TSIT5, VERN7, RODAS = 1, 2, 3
+ST_OK, ST_MAX_STEPS, ST_DT_UNDERFLOW, ST_NONFINITE, ST_NOSPACE = 0, 1, 2, 3, 4
+LOSS_SUMSQ, LOSS_MSE_TARGET, LOSS_COTANGENT = 0, 1, 2
+
+_lib = None
+
+_d = C.POINTER(C.c_double)
+_i32 = C.POINTER(C.c_int32)
+_i64 = C.POINTER(C.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = C.CDLL(LIB_PATH)
+        I, L, D = C.c_int, C.c_int64, C.c_double
+        lib.oracle_dims.argtypes = [I, C.POINTER(I), C.POINTER(I)]
+        lib.oracle_erk_tableau.argtypes = [I, _d, _d, _d, _d, C.POINTER(I), C.POINTER(I)]
+        lib.oracle_rhs.argtypes = [I, _d, _d, _d]
+        lib.oracle_vjp.argtypes = [I, _d, _d, _d, _d, _d]
+        lib.oracle_record.argtypes = [I, I, I, I, _d, _d, D, D, D, D, D, L, I, _d, L,
+                                      _d, _i32, _i32, _i32, _d, _d, _i64]
+        lib.oracle_replay.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d, _d]
+        lib.oracle_replay_dual.argtypes = [I, I, I, _d, _d, _d, _d, L, _d, _i32, I,
+                                           _i32, _d, _d, _d]
+        lib.oracle_replay_complex.argtypes = [I, I, I, _d, _d, _d, _d, D, L, _d, _i32,
+                                              I, _i32, _d, _d, _d]
+        lib.oracle_adjoint.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d,
+                                       I, _d, D, _d, _d, _d]
+        for f in ("oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp",
+                  "oracle_record", "oracle_replay", "oracle_replay_dual",
+                  "oracle_replay_complex", "oracle_adjoint"):
+            getattr(lib, f).restype = I
+        _lib = lib
+    return _lib
+
+
+def _p(a, t=_d):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def dims(system):
+    d, p = C.c_int(), C.c_int()
+    if _load().oracle_dims(system, C.byref(d), C.byref(p)) != 0:
+        raise ValueError(f"unknown system {system}")
+    return d.value, p.value
+
+
+def erk_tableau(method):
+    c = np.zeros(16); a = np.zeros(256); b = np.zeros(16); ew = np.zeros(16)
+    o, q = C.c_int(), C.c_int()
+    s = _load().oracle_erk_tableau(method, _p(c), _p(a), _p(b), _p(ew), C.byref(o), C.byref(q))
+    if s < 0:
+        raise ValueError(f"no explicit tableau for method {method}")
+    return dict(s=s, c=c[:s].copy(), A=a[: s * s].reshape(s, s).copy(), b=b[:s].copy(),
+                ew=ew[:s].copy(), order=o.value, q_emb=q.value)
+
+
+def rhs(system, y, p):
+    y, p = _f64(y), _f64(p)
+    f = np.zeros_like(y)
+    _load().oracle_rhs(system, _p(y), _p(p), _p(f))
+    return f
+
+
+def vjp(system, y, p, w):
+    y, p, w = _f64(y), _f64(p), _f64(w)
+    gy = np.zeros_like(y)
+    gp = np.zeros_like(p)
+    _load().oracle_vjp(system, _p(y), _p(p), _p(w), _p(gy), _p(gp))
+    return gy, gp
+
+
+def record(system, method, y0, p, t0, t1, rtol, atol, save_t=None, h0=0.0,
+           max_steps=100000, cap=None, params_shared=False):
+    """Adaptive record.  Returns a dict with the mesh and the save states."""
+    y0, p = _f64(y0), _f64(p)
+    n, d = y0.shape
+    save_t = np.array([t1] if save_t is None else save_t, dtype=np.float64)
+    ns = len(save_t)
+    if cap is None:
+        cap = 4096
+    h = np.zeros((n, cap)); S = np.zeros(n, np.int32); st = np.zeros(n, np.int32)
+    sidx = np.zeros((n, ns), np.int32); sdt = np.zeros((n, ns)); ys = np.zeros((n, ns, d))
+    ntr = np.zeros(n, np.int64)
+    rc = _load().oracle_record(system, method, n, int(params_shared), _p(y0), _p(p), t0, t1,
+                               rtol, atol, h0, max_steps, ns, _p(save_t), cap, _p(h),
+                               _p(S, _i32), _p(st, _i32), _p(sidx, _i32), _p(sdt), _p(ys),
+                               _p(ntr, _i64))
+    if rc != 0:
+        raise ValueError("oracle_record rejected its arguments")
+    return dict(h=h, S=S, status=st, save_idx=sidx, save_dt=sdt, y_save=ys, n_trial=ntr,
+                save_t=save_t, system=system, method=method)
+
+
+def _mesh(mesh):
+    h = _f64(mesh["h"])
+    return (h, h.shape[1], np.ascontiguousarray(mesh["S"], np.int32),
+            np.ascontiguousarray(mesh["save_idx"], np.int32), _f64(mesh["save_dt"]))
+
+
+def replay(system, method, y0, p, mesh, params_shared=False):
+    y0, p = _f64(y0), _f64(p)
+    h, cap, S, sidx, sdt = _mesh(mesh)
+    n, d = y0.shape
+    ns = sidx.shape[1]
+    ys = np.zeros((n, ns, d))
+    _load().oracle_replay(system, method, n, int(params_shared), _p(y0), _p(p), cap, _p(h),
+                          _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(ys))
+    return ys
+
+
+def replay_dual(system, method, y0, p, dy0, dp, mesh):
+    y0, p, dy0, dp = _f64(y0), _f64(p), _f64(dy0), _f64(dp)
+    h, cap, S, sidx, sdt = _mesh(mesh)
+    n, d = y0.shape
+    ns = sidx.shape[1]
+    ys = np.zeros((n, ns, d)); dys = np.zeros((n, ns, d))
+    _load().oracle_replay_dual(system, method, n, _p(y0), _p(p), _p(dy0), _p(dp), cap, _p(h),
+                               _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(ys), _p(dys))
+    return ys, dys
+
+
+def replay_complex(system, method, y0, p, dy0, dp, eps, mesh):
+    y0, p, dy0, dp = _f64(y0), _f64(p), _f64(dy0), _f64(dp)
+    h, cap, S, sidx, sdt = _mesh(mesh)
+    n, d = y0.shape
+    ns = sidx.shape[1]
+    re = np.zeros((n, ns, d)); im = np.zeros((n, ns, d))
+    _load().oracle_replay_complex(system, method, n, _p(y0), _p(p), _p(dy0), _p(dp), eps, cap,
+                                  _p(h), _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(re),
+                                  _p(im))
+    return re, im
+
+
+def adjoint(system, method, y0, p, mesh, loss_kind=LOSS_SUMSQ, loss_data=None, scale=1.0,
+            params_shared=False):
+    """Discrete adjoint on a frozen mesh: (grad_p [n][P], grad_y0 [n][d], loss [n])."""
+    y0, p = _f64(y0), _f64(p)
+    h, cap, S, sidx, sdt = _mesh(mesh)
+    n, d = y0.shape
+    ns = sidx.shape[1]
+    np_ = dims(system)[1]
+    gp = np.zeros((n, np_)); gy = np.zeros((n, d)); ll = np.zeros(n)
+    ld = _f64(loss_data) if loss_data is not None else None
+    _load().oracle_adjoint(system, method, n, int(params_shared), _p(y0), _p(p), cap, _p(h),
+                           _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), loss_kind,
+                           _p(ld) if ld is not None else None, scale, _p(gp), _p(gy), _p(ll))
+    return gp, gy, ll

@@ -1,0 +1,812 @@
+// Plain FP64 CPU oracle for record-and-replay exact gradients of ODE ensembles.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+// calls this file; only the test suite, the smoke check and the CPU-baseline
+// leg of the benchmark do.  It shares no code, header or table with the GPU
+// path: every coefficient and formula below is typed here on its own.
+//
+// What it computes (paper, Sections 2.1 and 3.1):
+//  * record  -- the adaptive solve of each trajectory (eq. stages, eq. update,
+//               the embedded error estimate and the RMS acceptance test of
+//               Section 2.1), keeping the accepted step sizes h_1..h_S and the
+//               states at requested save times, each reached by one extra
+//               step from the preceding mesh point (Section 3.4).
+//  * replay  -- the chain y_i = Phi(y_{i-1}; h_i, theta) of eq. (replay) on a
+//               given (frozen) mesh, templated on the scalar type so that the
+//               same code runs in double, in forward-mode dual numbers and in
+//               complex arithmetic (complex-step derivatives).
+//  * adjoint -- the discrete adjoint (reverse sweep) of the replay with the
+//               mesh held fixed (the sg[h] convention of Section 3.1), written
+//               out by hand stage by stage.
+//
+// Arithmetic convention.  Every linear combination sum_j c_j v_j is formed in
+// index order as acc = c_1 v_1, then acc = fma(c_j, v_j, acc); zero
+// coefficients are skipped.  A stage input is fma(h, acc, y).  The right-hand
+// sides and their vector-Jacobian products are written with the fma
+// placement documented beside each one.  This fixes the rounding of every
+// quantity, so an independent implementation that evaluates the same
+// formulas in the same order reproduces the oracle bit for bit.
+//
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -shared -fPIC.
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace orc {
+
+// ---------------------------------------------------------------- scalars --
+// Forward-mode dual number with one tangent direction.
+struct Dual {
+  double v, d;
+  Dual(double x = 0.0) : v(x), d(0.0) {}
+  Dual(double x, double dx) : v(x), d(dx) {}
+};
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) {
+  return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)};
+}
+inline Dual fma(Dual a, Dual b, Dual c) {
+  return {std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d};
+}
+inline Dual tanh(Dual a) {
+  double t = std::tanh(a.v);
+  return {t, a.d * (1.0 - t * t)};
+}
+
+using Cplx = std::complex<double>;
+inline Cplx fma(Cplx a, Cplx b, Cplx c) { return a * b + c; }
+
+inline double fma(double a, double b, double c) { return std::fma(a, b, c); }
+inline double tanh(double a) { return std::tanh(a); }
+
+inline double value_of(double x) { return x; }
+inline double value_of(Dual x) { return x.v; }
+inline double value_of(Cplx x) { return x.real(); }
+
+// --------------------------------------------------------------- tableaux --
+// Explicit Runge-Kutta pairs.  c, a (strictly lower), b and ew = b - bhat
+// (the weights of the embedded error estimate, up to a sign that the RMS
+// norm ignores).
+struct ERK {
+  int s;        // stages
+  int order;    // order of b
+  int q_emb;    // order of bhat (controller exponent -1/(q_emb+1))
+  bool fsal;    // last stage input equals the new state
+  int s_used;   // stages with b_j != 0 (the replay needs only these)
+  double c[10];
+  double a[10][10];
+  double b[10];
+  double ew[10];
+};
+
+// Tsit5: Tsitouras (2011), 5(4) pair, 7 stages, first-same-as-last.
+static ERK make_tsit5() {
+  ERK t{};
+  t.s = 7; t.order = 5; t.q_emb = 4; t.fsal = true; t.s_used = 6;
+  const double c[7] = {0.0, 0.161, 0.327, 0.9, 0.9800255409045097, 1.0, 1.0};
+  for (int i = 0; i < 7; ++i) t.c[i] = c[i];
+  t.a[1][0] = 0.161;
+  t.a[2][0] = -0.008480655492356989;
+  t.a[2][1] = 0.335480655492357;
+  t.a[3][0] = 2.897153057105493;
+  t.a[3][1] = -6.359448489975075;
+  t.a[3][2] = 4.3622954328695815;
+  t.a[4][0] = 5.325864828439257;
+  t.a[4][1] = -11.748883564062828;
+  t.a[4][2] = 7.4955393428898365;
+  t.a[4][3] = -0.09249506636175525;
+  t.a[5][0] = 5.86145544294642;
+  t.a[5][1] = -12.92096931784711;
+  t.a[5][2] = 8.159367898576159;
+  t.a[5][3] = -0.071584973281401;
+  t.a[5][4] = -0.028269050394068383;
+  t.a[6][0] = 0.09646076681806523;
+  t.a[6][1] = 0.01;
+  t.a[6][2] = 0.4798896504144996;
+  t.a[6][3] = 1.379008574103742;
+  t.a[6][4] = -3.290069515436081;
+  t.a[6][5] = 2.324710524099774;
+  for (int j = 0; j < 6; ++j) t.b[j] = t.a[6][j];
+  t.b[6] = 0.0;
+  const double ew[7] = {-0.00178001105222577714, -0.0008164344596567469,
+                        0.007880878010261995,    -0.1447110071732629,
+                        0.5823571654525552,      -0.45808210592918697,
+                        0.015151515151515152};
+  for (int j = 0; j < 7; ++j) t.ew[j] = ew[j];
+  return t;
+}
+
+// Vern7: Verner (2010), 7(6) pair, 10 stages, not first-same-as-last.
+static ERK make_vern7() {
+  ERK t{};
+  t.s = 10; t.order = 7; t.q_emb = 6; t.fsal = false; t.s_used = 9;
+  const double c[10] = {0.0, 0.005, 0.10888888888888888, 0.16333333333333333,
+                        0.4555, 0.6095094489978381, 0.884, 0.925, 1.0, 1.0};
+  for (int i = 0; i < 10; ++i) t.c[i] = c[i];
+  t.a[1][0] = 0.005;
+  t.a[2][0] = -1.07679012345679;
+  t.a[2][1] = 1.185679012345679;
+  t.a[3][0] = 0.04083333333333333;
+  t.a[3][2] = 0.1225;
+  t.a[4][0] = 0.6389139236255726;
+  t.a[4][2] = -2.455672638223657;
+  t.a[4][3] = 2.272258714598084;
+  t.a[5][0] = -2.6615773750187572;
+  t.a[5][2] = 10.804513886456137;
+  t.a[5][3] = -8.3539146573962;
+  t.a[5][4] = 0.820487594956657;
+  t.a[6][0] = 6.067741434696772;
+  t.a[6][2] = -24.711273635911088;
+  t.a[6][3] = 20.427517930788895;
+  t.a[6][4] = -1.9061579788166472;
+  t.a[6][5] = 1.006172249242068;
+  t.a[7][0] = 12.054670076253203;
+  t.a[7][2] = -49.75478495046899;
+  t.a[7][3] = 41.142888638604674;
+  t.a[7][4] = -4.461760149974004;
+  t.a[7][5] = 2.042334822239175;
+  t.a[7][6] = -0.09834843665406107;
+  t.a[8][0] = 10.138146522881808;
+  t.a[8][2] = -42.6411360317175;
+  t.a[8][3] = 35.76384003992257;
+  t.a[8][4] = -4.3480228403929075;
+  t.a[8][5] = 2.0098622683770357;
+  t.a[8][6] = 0.3487490460338272;
+  t.a[8][7] = -0.27143900510483127;
+  t.a[9][0] = -45.030072034298676;
+  t.a[9][2] = 187.3272437654589;
+  t.a[9][3] = -154.02882369350186;
+  t.a[9][4] = 18.56465306347536;
+  t.a[9][5] = -7.141809679295079;
+  t.a[9][6] = 1.3088085781613787;
+  const double b[10] = {0.04715561848627222, 0.0, 0.0, 0.25750564298434153,
+                        0.26216653977412624, 0.15216092656738558,
+                        0.4939969170032485, -0.29430311714032503,
+                        0.08131747232495111, 0.0};
+  for (int j = 0; j < 10; ++j) t.b[j] = b[j];
+  const double ew[10] = {0.0025470118799348416, 0.0, 0.0,
+                         -0.009658394872807551, 0.04206470975642573,
+                         -0.06668224374695614,  0.26500974646213266,
+                         -0.29430311714032503,  0.08131747232495111,
+                         -0.020295184663355476};
+  for (int j = 0; j < 10; ++j) t.ew[j] = ew[j];
+  return t;
+}
+
+static const ERK TSIT5 = make_tsit5();
+static const ERK VERN7 = make_vern7();
+
+static const ERK* erk_of(int method) {
+  if (method == 1) return &TSIT5;
+  if (method == 2) return &VERN7;
+  return nullptr;
+}
+
+// ---------------------------------------------------------------- systems --
+enum { SYS_LORENZ = 1, SYS_VDP = 2, SYS_LINEAR = 6 };
+
+static int sys_dim(int sys) {
+  switch (sys) {
+    case SYS_LORENZ: return 3;
+    case SYS_VDP: return 2;
+    case SYS_LINEAR: return 2;
+  }
+  return -1;
+}
+static int sys_np(int sys) {
+  switch (sys) {
+    case SYS_LORENZ: return 3;
+    case SYS_VDP: return 1;
+    case SYS_LINEAR: return 2;
+  }
+  return -1;
+}
+
+// Right-hand sides f(y, p) of the autonomous systems (paper, Appendix A).
+//  Lorenz  p = (sigma, rho, beta):
+//    f0 = sigma*(y1 - y0);  f1 = fma(y0, rho - y2, -y1);  f2 = fma(y0, y1, -(beta*y2))
+//  Van der Pol  p = (mu):
+//    f0 = y1;  f1 = mu * fma(fma(-y0, y0, 1), y1, -y0)
+//  Linear (damped rotation y' = A y, A = [[-a, -w], [w, -a]])  p = (a, w):
+//    f0 = -fma(a, y0, w*y1);  f1 = fma(w, y0, -(a*y1))
+template <class T, class P>
+static void rhs(int sys, const T* y, const P* p, T* f) {
+  switch (sys) {
+    case SYS_LORENZ: {
+      f[0] = p[0] * (y[1] - y[0]);
+      f[1] = fma(y[0], p[1] - y[2], -y[1]);
+      f[2] = fma(y[0], y[1], -(p[2] * y[2]));
+    } break;
+    case SYS_VDP: {
+      f[0] = y[1];
+      f[1] = p[0] * fma(fma(-y[0], y[0], T(1.0)), y[1], -y[0]);
+    } break;
+    case SYS_LINEAR: {
+      f[0] = -fma(p[0], y[0], p[1] * y[1]);
+      f[1] = fma(p[1], y[0], -(p[0] * y[1]));
+    } break;
+  }
+}
+
+// Vector-Jacobian products at y: gy = (df/dy)^T w (overwritten) and
+// gp += (df/dp)^T w (accumulated).
+//  Lorenz:
+//    gy0 = fma(y1, w2, fma(rho - y2, w1, -(sigma*w0)))
+//    gy1 = fma(y0, w2, fma(sigma, w0, -w1))
+//    gy2 = -fma(y0, w1, beta*w2)
+//    gp0 = fma(y1 - y0, w0, gp0);  gp1 = fma(y0, w1, gp1);  gp2 = fma(-y2, w2, gp2)
+//  Van der Pol (u = mu*w1, q = fma(-y0, y0, 1)):
+//    gy0 = u * fma(-2*y0, y1, -1);  gy1 = fma(u, q, w0)
+//    gp0 = fma(w1, fma(q, y1, -y0), gp0)
+//  Linear:
+//    gy0 = fma(w, w1, -(a*w0));  gy1 = -fma(w, w0, a*w1)
+//    gp0 = gp0 - fma(y0, w0, y1*w1);  gp1 = gp1 + fma(y0, w1, -(y1*w0))
+static void vjp(int sys, const double* y, const double* p, const double* w,
+                double* gy, double* gp) {
+  switch (sys) {
+    case SYS_LORENZ: {
+      gy[0] = fma(y[1], w[2], fma(p[1] - y[2], w[1], -(p[0] * w[0])));
+      gy[1] = fma(y[0], w[2], fma(p[0], w[0], -w[1]));
+      gy[2] = -fma(y[0], w[1], p[2] * w[2]);
+      gp[0] = fma(y[1] - y[0], w[0], gp[0]);
+      gp[1] = fma(y[0], w[1], gp[1]);
+      gp[2] = fma(-y[2], w[2], gp[2]);
+    } break;
+    case SYS_VDP: {
+      double u = p[0] * w[1];
+      double q = fma(-y[0], y[0], 1.0);
+      gy[0] = u * fma(-2.0 * y[0], y[1], -1.0);
+      gy[1] = fma(u, q, w[0]);
+      gp[0] = fma(w[1], fma(q, y[1], -y[0]), gp[0]);
+    } break;
+    case SYS_LINEAR: {
+      gy[0] = fma(p[1], w[1], -(p[0] * w[0]));
+      gy[1] = -fma(p[1], w[0], p[0] * w[1]);
+      gp[0] = gp[0] - fma(y[0], w[0], y[1] * w[1]);
+      gp[1] = gp[1] + fma(y[0], w[1], -(y[1] * w[0]));
+    } break;
+  }
+}
+
+// ------------------------------------------------------------ one ERK step --
+constexpr int DMAX = 8;
+constexpr int SMAX = 10;
+
+// Stage values k_1..k_s of one explicit step from y with step h (eq. stages),
+// given k_1 = f(y).  Also returns each stage input Y_j.  n_st stages are
+// formed (the replay needs only the stages with nonzero b).
+template <class T, class P>
+static void erk_stages(const ERK& m, int sys, int d, const T* y, const P* p,
+                       T h, int n_st, T k[SMAX][DMAX], T Y[SMAX][DMAX]) {
+  for (int c = 0; c < d; ++c) Y[0][c] = y[c];
+  for (int i = 1; i < n_st; ++i) {
+    for (int c = 0; c < d; ++c) {
+      T acc = T(0.0);
+      bool first = true;
+      for (int j = 0; j < i; ++j) {
+        if (m.a[i][j] == 0.0) continue;
+        if (first) { acc = T(m.a[i][j]) * k[j][c]; first = false; }
+        else acc = fma(T(m.a[i][j]), k[j][c], acc);
+      }
+      Y[i][c] = fma(h, acc, y[c]);
+    }
+    rhs(sys, Y[i], p, k[i]);
+  }
+}
+
+// y_new = y + h * sum_j b_j k_j (eq. update), combination over stages with
+// nonzero b in index order.
+template <class T>
+static void erk_update(const ERK& m, int d, const T* y, T h, T k[SMAX][DMAX],
+                       T* ynew) {
+  for (int c = 0; c < d; ++c) {
+    T acc = T(0.0);
+    bool first = true;
+    for (int j = 0; j < m.s; ++j) {
+      if (m.b[j] == 0.0) continue;
+      if (first) { acc = T(m.b[j]) * k[j][c]; first = false; }
+      else acc = fma(T(m.b[j]), k[j][c], acc);
+    }
+    ynew[c] = fma(h, acc, y[c]);
+  }
+}
+
+// One replay step Phi(y; h) (eq. replay).  For a first-same-as-last pair the
+// last stage input equals the update, so both are formed by the same
+// expression.
+template <class T, class P>
+static void erk_phi(const ERK& m, int sys, int d, const T* y, const P* p, T h,
+                    T* ynew) {
+  T k[SMAX][DMAX], Y[SMAX][DMAX];
+  rhs(sys, y, p, k[0]);
+  erk_stages(m, sys, d, y, p, h, m.s_used, k, Y);
+  erk_update(m, d, y, h, k, ynew);
+}
+
+// ----------------------------------------------------------------- record --
+enum { ST_OK = 0, ST_MAX_STEPS = 1, ST_DT_UNDERFLOW = 2, ST_NONFINITE = 3,
+       ST_NOSPACE = 4 };
+
+struct RecordArgs {
+  int sys, method, n, d, np, params_shared;
+  const double* y0;      // [n][d]
+  const double* p;       // [n][np] or [np]
+  double t0, t1, rtol, atol, h0;
+  int64_t max_steps;
+  int n_save;
+  const double* save_t;  // [n_save], ascending, in [t0, t1]
+  int64_t cap;           // mesh capacity per lane
+  double* h_out;         // [n][cap]
+  int32_t* S_out;        // [n]
+  int32_t* status_out;   // [n]
+  int32_t* save_idx;     // [n][n_save]  base index i(s)
+  double* save_dt;       // [n][n_save]  side-step size t_s - t_i(s)
+  double* y_save;        // [n][n_save][d]
+  int64_t* n_trial;      // [n] trials (accepted + rejected)
+};
+
+// Scaled RMS norm of v against the scales sc (paper, Section 2.1):
+// sqrt(mean_c (v_c / sc_c)^2), the squares summed with fma in index order.
+static double rms_norm(int d, const double* v, const double* sc) {
+  double r = v[0] / sc[0];
+  double ss = r * r;
+  for (int c = 1; c < d; ++c) {
+    r = v[c] / sc[c];
+    ss = fma(r, r, ss);
+  }
+  return std::sqrt(ss / (double)d);
+}
+
+// Starting step: Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4, with
+// the same scaled RMS norm (scale atol + rtol*|y0|).
+static double initial_step(const ERK& m, int sys, int d, const double* y0,
+                           const double* p, const double* f0, double t0,
+                           double t1, double rtol, double atol) {
+  double sc[DMAX] = {}, tmp[DMAX] = {}, y1[DMAX] = {}, f1[DMAX] = {};
+  for (int c = 0; c < d; ++c) sc[c] = fma(rtol, std::fabs(y0[c]), atol);
+  double d0 = rms_norm(d, y0, sc);
+  double d1 = rms_norm(d, f0, sc);
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
+  h0 = std::fmin(h0, t1 - t0);
+  for (int c = 0; c < d; ++c) y1[c] = fma(h0, f0[c], y0[c]);
+  rhs(sys, y1, p, f1);
+  for (int c = 0; c < d; ++c) tmp[c] = f1[c] - f0[c];
+  double d2 = rms_norm(d, tmp, sc) / h0;
+  double dm = std::fmax(d1, d2);
+  double h1 = (dm <= 1e-15) ? std::fmax(1e-6, h0 * 1e-3)
+                            : std::pow(0.01 / dm, 1.0 / (double)(m.order + 1));
+  return std::fmin(std::fmin(100.0 * h0, h1), t1 - t0);
+}
+
+static void record_lane(const RecordArgs& A, int lane) {
+  const ERK& m = *erk_of(A.method);
+  const int d = A.d, sys = A.sys;
+  const double* p = A.params_shared ? A.p : A.p + (int64_t)lane * A.np;
+  double y[DMAX], k1[DMAX];
+  for (int c = 0; c < d; ++c) y[c] = A.y0[(int64_t)lane * d + c];
+  double* hrow = A.h_out + (int64_t)lane * A.cap;
+  int32_t* sidx = A.save_idx + (int64_t)lane * A.n_save;
+  double* sdt = A.save_dt + (int64_t)lane * A.n_save;
+  double* ysv = A.y_save + (int64_t)lane * A.n_save * d;
+  for (int s = 0; s < A.n_save; ++s) {
+    sidx[s] = -1;
+    sdt[s] = NAN;
+    for (int c = 0; c < d; ++c) ysv[s * d + c] = NAN;
+  }
+
+  rhs(sys, y, p, k1);
+  int status = ST_OK;
+  for (int c = 0; c < d; ++c)
+    if (!std::isfinite(y[c]) || !std::isfinite(k1[c])) status = ST_NONFINITE;
+  double t = A.t0;
+  double h = A.h0 > 0.0 ? std::fmin(A.h0, A.t1 - A.t0)
+                        : initial_step(m, sys, d, y, p, k1, A.t0, A.t1, A.rtol,
+                                       A.atol);
+  const double expo = -1.0 / (double)(m.q_emb + 1);
+  int64_t S = 0, trials = 0;
+  int next_save = 0;
+  bool prev_rejected = false;
+
+  while (status == ST_OK && t < A.t1) {
+    if (trials >= A.max_steps) { status = ST_MAX_STEPS; break; }
+    // a proposed step too small to advance t ends the lane
+    if (h < 16.0 * 2.220446049250313e-16 * std::fmax(std::fabs(t), 1.0)) {
+      status = ST_DT_UNDERFLOW;
+      break;
+    }
+    ++trials;
+    bool last = false;
+    if (t + h >= A.t1) { h = A.t1 - t; last = true; }
+
+    double k[SMAX][DMAX], Y[SMAX][DMAX], ynew[DMAX];
+    for (int c = 0; c < d; ++c) k[0][c] = k1[c];
+    erk_stages(m, sys, d, y, p, h, m.s, k, Y);
+    if (m.fsal) {
+      for (int c = 0; c < d; ++c) ynew[c] = Y[m.s - 1][c];
+    } else {
+      erk_update(m, d, y, h, k, ynew);
+    }
+    // error estimate e = h * sum_j ew_j k_j and its scaled RMS norm
+    double e[DMAX], sc[DMAX];
+    for (int c = 0; c < d; ++c) {
+      double acc = 0.0;
+      bool first = true;
+      for (int j = 0; j < m.s; ++j) {
+        if (m.ew[j] == 0.0) continue;
+        if (first) { acc = m.ew[j] * k[j][c]; first = false; }
+        else acc = fma(m.ew[j], k[j][c], acc);
+      }
+      e[c] = h * acc;
+      sc[c] = fma(A.rtol, std::fmax(std::fabs(y[c]), std::fabs(ynew[c])), A.atol);
+    }
+    double err = rms_norm(d, e, sc);
+
+    if (err <= 1.0) {
+      if (S >= A.cap) { status = ST_NOSPACE; break; }
+      hrow[S] = h;
+      double tnew = last ? A.t1 : t + h;
+      // saves strictly inside this step: one extra step from y (the base
+      // state of this step) to each save time.
+      while (next_save < A.n_save && A.save_t[next_save] < tnew) {
+        double dt = A.save_t[next_save] - t;
+        double ys[DMAX];
+        double ks[SMAX][DMAX], Ys[SMAX][DMAX];
+        for (int c = 0; c < d; ++c) ks[0][c] = k1[c];
+        erk_stages(m, sys, d, y, p, dt, m.s_used, ks, Ys);
+        erk_update(m, d, y, dt, ks, ys);
+        sidx[next_save] = (int32_t)S;
+        sdt[next_save] = dt;
+        for (int c = 0; c < d; ++c) ysv[next_save * d + c] = ys[c];
+        ++next_save;
+      }
+      ++S;
+      t = tnew;
+      for (int c = 0; c < d; ++c) y[c] = ynew[c];
+      if (m.fsal) {
+        for (int c = 0; c < d; ++c) k1[c] = k[m.s - 1][c];
+      } else {
+        rhs(sys, y, p, k1);
+      }
+      double fac;
+      if (err == 0.0) fac = 10.0;
+      else fac = 0.9 * std::pow(err, expo);
+      fac = std::fmax(0.2, std::fmin(prev_rejected ? 1.0 : 10.0, fac));
+      h = h * fac;
+      prev_rejected = false;
+    } else {
+      double fac = std::fmax(0.2, 0.9 * std::pow(err, expo));
+      h = h * fac;
+      prev_rejected = true;
+    }
+  }
+  // saves at or after the last mesh point (t_s == t_S): side step of size 0,
+  // i.e. the state itself.
+  if (status == ST_OK) {
+    while (next_save < A.n_save) {
+      sidx[next_save] = (int32_t)S;
+      sdt[next_save] = A.save_t[next_save] - t;
+      double ys[DMAX];
+      erk_phi(m, sys, d, y, p, sdt[next_save], ys);
+      for (int c = 0; c < d; ++c) ysv[next_save * d + c] = ys[c];
+      ++next_save;
+    }
+  }
+  A.S_out[lane] = (int32_t)S;
+  A.status_out[lane] = status;
+  A.n_trial[lane] = trials;
+}
+
+// ----------------------------------------------------------------- replay --
+struct MeshArgs {
+  int sys, method, n, d, np, params_shared;
+  int64_t cap;
+  const double* h;        // [n][cap]
+  const int32_t* S;       // [n]
+  int n_save;
+  const int32_t* save_idx;  // [n][n_save]
+  const double* save_dt;    // [n][n_save]
+};
+
+// Replay one lane in scalar type T; writes the save-time states.
+template <class T>
+static void replay_lane(const MeshArgs& M, int lane, const T* y0, const T* p,
+                        T* ysave /*[n_save][d]*/) {
+  const ERK& m = *erk_of(M.method);
+  const int d = M.d;
+  const double* hrow = M.h + (int64_t)lane * M.cap;
+  const int32_t* sidx = M.save_idx + (int64_t)lane * M.n_save;
+  const double* sdt = M.save_dt + (int64_t)lane * M.n_save;
+  const int S = M.S[lane];
+  T y[DMAX];
+  for (int c = 0; c < d; ++c) y[c] = y0[c];
+  int s = 0;
+  for (int i = 0; i <= S; ++i) {
+    // saves whose base is y_i
+    while (s < M.n_save && sidx[s] == i) {
+      erk_phi(m, M.sys, d, y, p, T(sdt[s]), ysave + s * d);
+      ++s;
+    }
+    if (i == S) break;
+    T yn[DMAX];
+    erk_phi(m, M.sys, d, y, p, T(hrow[i]), yn);
+    for (int c = 0; c < d; ++c) y[c] = yn[c];
+  }
+}
+
+// ---------------------------------------------------------------- adjoint --
+enum { LOSS_SUMSQ = 0, LOSS_MSE_TARGET = 1, LOSS_COTANGENT = 2 };
+
+// Reverse sweep through one step Phi(y; h) with output cotangent lam.
+// Returns the input cotangent lam + sum_j Ybar_j (accumulated in descending
+// j) and accumulates gp += sum_j (df/dp)^T kbar_j, where for j = s'..1
+//   kbar_j = h * (b_j lam + sum_{l>j} a_lj Ybar_l),  Ybar_j = (df/dy)^T kbar_j.
+static void erk_step_vjp(const ERK& m, int sys, int d, const double* y,
+                         const double* p, double h, const double* lam,
+                         double* lam_in, double* gp) {
+  double k[SMAX][DMAX], Y[SMAX][DMAX];
+  rhs(sys, y, p, k[0]);
+  const int su = m.s_used;
+  erk_stages(m, sys, d, y, p, h, su, k, Y);
+  double Yb[SMAX][DMAX];
+  for (int c = 0; c < d; ++c) lam_in[c] = lam[c];
+  for (int j = su - 1; j >= 0; --j) {
+    double kb[DMAX];
+    for (int c = 0; c < d; ++c) {
+      double acc = 0.0;
+      bool first = true;
+      if (m.b[j] != 0.0) { acc = m.b[j] * lam[c]; first = false; }
+      for (int l = j + 1; l < su; ++l) {
+        if (m.a[l][j] == 0.0) continue;
+        if (first) { acc = m.a[l][j] * Yb[l][c]; first = false; }
+        else acc = fma(m.a[l][j], Yb[l][c], acc);
+      }
+      kb[c] = h * acc;
+    }
+    vjp(sys, Y[j], p, kb, Yb[j], gp);
+    for (int c = 0; c < d; ++c) lam_in[c] = lam_in[c] + Yb[j][c];
+  }
+}
+
+struct LossArgs {
+  int kind;
+  const double* data;  // [n][n_save][d]: targets (MSE) or cotangents
+  double scale;
+};
+
+// Discrete adjoint of one lane: gradient of the lane's loss with respect to
+// its parameters (gp, accumulated) and its initial state (gy0).  Returns the
+// lane's loss.
+static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
+                           const double* y0, const double* p, double* gp,
+                           double* gy0) {
+  const ERK& m = *erk_of(M.method);
+  const int d = M.d;
+  const int S = M.S[lane];
+  const double* hrow = M.h + (int64_t)lane * M.cap;
+  const int32_t* sidx = M.save_idx + (int64_t)lane * M.n_save;
+  const double* sdt = M.save_dt + (int64_t)lane * M.n_save;
+  const double* ldat = L.data ? L.data + (int64_t)lane * M.n_save * d : nullptr;
+
+  // forward states y_0..y_S (the replay in double)
+  std::vector<double> ys((size_t)(S + 1) * d);
+  for (int c = 0; c < d; ++c) ys[c] = y0[c];
+  for (int i = 0; i < S; ++i)
+    erk_phi(m, M.sys, d, &ys[(size_t)i * d], p, hrow[i], &ys[(size_t)(i + 1) * d]);
+
+  // save-time states (one extra step from the base mesh point)
+  std::vector<double> ysave((size_t)M.n_save * d);
+  for (int s = 0; s < M.n_save; ++s)
+    erk_phi(m, M.sys, d, &ys[(size_t)sidx[s] * d], p, sdt[s], &ysave[(size_t)s * d]);
+
+  // loss and save-time cotangents
+  double loss = 0.0;
+  std::vector<double> wbar((size_t)M.n_save * d);
+  const double two_scale = 2.0 * L.scale;
+  for (int s = 0; s < M.n_save; ++s) {
+    for (int c = 0; c < d; ++c) {
+      double v = ysave[s * d + c];
+      if (L.kind == LOSS_SUMSQ) {
+        loss = fma(v, v, loss);
+        wbar[s * d + c] = two_scale * v;
+      } else if (L.kind == LOSS_MSE_TARGET) {
+        double r = v - ldat[s * d + c];
+        loss = fma(r, r, loss);
+        wbar[s * d + c] = two_scale * r;
+      } else {
+        wbar[s * d + c] = ldat[s * d + c];
+      }
+    }
+  }
+  loss = L.scale * loss;
+
+  double lam[DMAX];
+  for (int c = 0; c < d; ++c) lam[c] = 0.0;
+  int s = M.n_save - 1;
+  for (int i = S; i >= 0; --i) {
+    while (s >= 0 && sidx[s] == i) {
+      double li[DMAX];
+      erk_step_vjp(m, M.sys, d, &ys[(size_t)i * d], p, sdt[s], &wbar[s * d], li, gp);
+      for (int c = 0; c < d; ++c) lam[c] = lam[c] + li[c];
+      --s;
+    }
+    if (i == 0) break;
+    double li[DMAX];
+    erk_step_vjp(m, M.sys, d, &ys[(size_t)(i - 1) * d], p, hrow[i - 1], lam, li, gp);
+    for (int c = 0; c < d; ++c) lam[c] = li[c];
+  }
+  for (int c = 0; c < d; ++c) gy0[c] = lam[c];
+  return loss;
+}
+
+}  // namespace orc
+
+// ============================================================== C entry ==
+using namespace orc;
+
+extern "C" {
+
+int oracle_dims(int sys, int* dim, int* np) {
+  *dim = sys_dim(sys);
+  *np = sys_np(sys);
+  return (*dim > 0) ? 0 : -1;
+}
+
+// Export a tableau: c[s], a[s*s] (row-major), b[s], ew[s]; returns s.
+int oracle_erk_tableau(int method, double* c, double* a, double* b, double* ew,
+                       int* order, int* q_emb) {
+  const ERK* m = erk_of(method);
+  if (!m) return -1;
+  for (int i = 0; i < m->s; ++i) {
+    c[i] = m->c[i];
+    b[i] = m->b[i];
+    ew[i] = m->ew[i];
+    for (int j = 0; j < m->s; ++j) a[i * m->s + j] = m->a[i][j];
+  }
+  *order = m->order;
+  *q_emb = m->q_emb;
+  return m->s;
+}
+
+int oracle_rhs(int sys, const double* y, const double* p, double* f) {
+  if (sys_dim(sys) < 0) return -1;
+  rhs(sys, y, p, f);
+  return 0;
+}
+
+int oracle_vjp(int sys, const double* y, const double* p, const double* w,
+               double* gy, double* gp) {
+  if (sys_dim(sys) < 0) return -1;
+  vjp(sys, y, p, w, gy, gp);
+  return 0;
+}
+
+int oracle_record(int sys, int method, int n, int params_shared,
+                  const double* y0, const double* p, double t0, double t1,
+                  double rtol, double atol, double h0, int64_t max_steps,
+                  int n_save, const double* save_t, int64_t cap, double* h_out,
+                  int32_t* S_out, int32_t* status_out, int32_t* save_idx,
+                  double* save_dt, double* y_save, int64_t* n_trial) {
+  if (sys_dim(sys) < 0 || !erk_of(method) || n < 0 || n_save < 1 ||
+      n_save > 64)
+    return -1;
+  RecordArgs A{sys, method, n, sys_dim(sys), sys_np(sys), params_shared,
+               y0, p, t0, t1, rtol, atol, h0, max_steps, n_save, save_t, cap,
+               h_out, S_out, status_out, save_idx, save_dt, y_save, n_trial};
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int l = 0; l < n; ++l) record_lane(A, l);
+  return 0;
+}
+
+static MeshArgs mesh_args(int sys, int method, int n, int params_shared,
+                          int64_t cap, const double* h, const int32_t* S,
+                          int n_save, const int32_t* save_idx,
+                          const double* save_dt) {
+  return MeshArgs{sys, method, n, sys_dim(sys), sys_np(sys), params_shared,
+                  cap, h, S, n_save, save_idx, save_dt};
+}
+
+// Replay on a frozen mesh in double.
+int oracle_replay(int sys, int method, int n, int params_shared,
+                  const double* y0, const double* p, int64_t cap,
+                  const double* h, const int32_t* S, int n_save,
+                  const int32_t* save_idx, const double* save_dt,
+                  double* y_save) {
+  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  MeshArgs M = mesh_args(sys, method, n, params_shared, cap, h, S, n_save,
+                         save_idx, save_dt);
+  const int d = M.d, np = M.np;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int l = 0; l < n; ++l) {
+    const double* pl = params_shared ? p : p + (int64_t)l * np;
+    replay_lane<double>(M, l, y0 + (int64_t)l * d, pl,
+                        y_save + (int64_t)l * n_save * d);
+  }
+  return 0;
+}
+
+// Forward-mode (dual number) replay: tangent of the save states along the
+// direction (dy0 [n][d], dp [n][np]); per-lane parameters only.
+int oracle_replay_dual(int sys, int method, int n, const double* y0,
+                       const double* p, const double* dy0, const double* dp,
+                       int64_t cap, const double* h, const int32_t* S,
+                       int n_save, const int32_t* save_idx,
+                       const double* save_dt, double* y_save, double* dy_save) {
+  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  MeshArgs M = mesh_args(sys, method, n, 0, cap, h, S, n_save, save_idx, save_dt);
+  const int d = M.d, np = M.np;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int l = 0; l < n; ++l) {
+    Dual y[DMAX], pp[DMAX], out[64 * DMAX];
+    for (int c = 0; c < d; ++c)
+      y[c] = Dual(y0[(int64_t)l * d + c], dy0[(int64_t)l * d + c]);
+    for (int c = 0; c < np; ++c)
+      pp[c] = Dual(p[(int64_t)l * np + c], dp[(int64_t)l * np + c]);
+    replay_lane<Dual>(M, l, y, pp, out);
+    for (int i = 0; i < n_save * d; ++i) {
+      y_save[(int64_t)l * n_save * d + i] = out[i].v;
+      dy_save[(int64_t)l * n_save * d + i] = out[i].d;
+    }
+  }
+  return 0;
+}
+
+// Complex-step replay: inputs y0 + i*eps*dy0, p + i*eps*dp; returns the real
+// and imaginary parts of the save states (per-lane parameters only).
+int oracle_replay_complex(int sys, int method, int n, const double* y0,
+                          const double* p, const double* dy0, const double* dp,
+                          double eps, int64_t cap, const double* h,
+                          const int32_t* S, int n_save, const int32_t* save_idx,
+                          const double* save_dt, double* re, double* im) {
+  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  MeshArgs M = mesh_args(sys, method, n, 0, cap, h, S, n_save, save_idx, save_dt);
+  const int d = M.d, np = M.np;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int l = 0; l < n; ++l) {
+    Cplx y[DMAX], pp[DMAX], out[64 * DMAX];
+    for (int c = 0; c < d; ++c)
+      y[c] = Cplx(y0[(int64_t)l * d + c], eps * dy0[(int64_t)l * d + c]);
+    for (int c = 0; c < np; ++c)
+      pp[c] = Cplx(p[(int64_t)l * np + c], eps * dp[(int64_t)l * np + c]);
+    replay_lane<Cplx>(M, l, y, pp, out);
+    for (int i = 0; i < n_save * d; ++i) {
+      re[(int64_t)l * n_save * d + i] = out[i].real();
+      im[(int64_t)l * n_save * d + i] = out[i].imag();
+    }
+  }
+  return 0;
+}
+
+// Discrete adjoint on a frozen mesh.  grad_p is [n][np] (per lane; for shared
+// parameters each lane's contribution is returned separately and the caller
+// sums them); grad_y0 is [n][d]; loss_lane is [n].
+int oracle_adjoint(int sys, int method, int n, int params_shared,
+                   const double* y0, const double* p, int64_t cap,
+                   const double* h, const int32_t* S, int n_save,
+                   const int32_t* save_idx, const double* save_dt,
+                   int loss_kind, const double* loss_data,
+                   double loss_scale, double* grad_p, double* grad_y0,
+                   double* loss_lane) {
+  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  MeshArgs M = mesh_args(sys, method, n, params_shared, cap, h, S, n_save,
+                         save_idx, save_dt);
+  LossArgs L{loss_kind, loss_data, loss_scale};
+  const int d = M.d, np = M.np;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int l = 0; l < n; ++l) {
+    const double* pl = params_shared ? p : p + (int64_t)l * np;
+    double* gp = grad_p + (int64_t)l * np;
+    for (int c = 0; c < np; ++c) gp[c] = 0.0;
+    loss_lane[l] = adjoint_lane(M, L, l, y0 + (int64_t)l * d, pl, gp,
+                                grad_y0 + (int64_t)l * d);
+  }
+  return 0;
+}
+
+}  // extern "C"

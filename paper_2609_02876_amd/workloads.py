@@ -1,0 +1,72 @@
+"""Seeded synthetic ensembles (inputs only; no solver arithmetic here).
+
+Both the GPU path and the CPU oracle are fed from these generators, so the
+two sides see the same float64 arrays.  Shapes follow the paper's problem
+statement (Section 2: n trajectories of y' = f(t, y, theta), theta per
+trajectory) with the parameter spreads of the workloads this library is
+measured on.  Arrays are per-trajectory rows: y0 [n, d], params [n, P].
+"""
+import numpy as np
+
+LORENZ_Y0 = (1.0, 0.0, 0.0)
+VDP_Y0 = (2.0, 0.0)
+
+
+def save_times(t0, t1, k=20):
+    """k evenly spaced save times t0 + (t1 - t0) s / k, s = 1..k; the last is t1 exactly."""
+    t = [t0 + (t1 - t0) * s / k for s in range(1, k + 1)]
+    t[-1] = t1
+    return np.array(t, dtype=np.float64)
+
+
+def lorenz(n, seed=0):
+    """Lorenz ensemble: y0 = (1,0,0); sigma ~ U[9,11], rho ~ U[27,29], beta ~ U[2.5,3]."""
+    u = np.random.default_rng(seed).random((n, 3))
+    p = np.stack([9.0 + 2.0 * u[:, 0], 27.0 + 2.0 * u[:, 1], 2.5 + 0.5 * u[:, 2]], 1)
+    y0 = np.tile(np.array(LORENZ_Y0), (n, 1))
+    return y0, p
+
+
+def lorenz_paper_timing(n, seed=0):
+    """The paper's Lorenz timing ensemble (Appendix A): sigma = 10, beta = 8/3, rho ~ U[0,21]."""
+    rho = 21.0 * np.random.default_rng(seed).random(n)
+    p = np.stack([np.full(n, 10.0), rho, np.full(n, 8.0 / 3.0)], 1)
+    return np.tile(np.array(LORENZ_Y0), (n, 1)), p
+
+
+def vdp(n, seed=0):
+    """Van der Pol ensemble: y0 = (2, 0); mu ~ U[0.5, 2]."""
+    u = np.random.default_rng(seed).random((n, 1))
+    return np.tile(np.array(VDP_Y0), (n, 1)), 0.5 + 1.5 * u
+
+
+def damped_rotation(n, seed=0):
+    """Linear test ensemble y' = A y, A = [[-a, -w], [w, -a]]: a ~ U[0.05,0.35], w ~ U[0.5,2.5], y0 ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n, 2))
+    p = np.stack([0.05 + 0.3 * u[:, 0], 0.5 + 2.0 * u[:, 1]], 1)
+    return rng.normal(size=(n, 2)), p
+
+
+# Named workloads.  "lorenz_2p20_t10" is the headline measurement: 2^20
+# Lorenz trajectories on [0, 10], Tsit5, FP64, rtol 1e-6, atol 1e-8, loss =
+# sum of squared states at 20 evenly spaced save times, gradient with respect
+# to the three per-trajectory parameters.  "lorenz_1024_t1" is the small
+# parity case: loss = sum of squared final states on [0, 1].
+WORKLOADS = {
+    "lorenz_1024_t1": dict(system="lorenz", method="tsit5", n=1024, t0=0.0, t1=1.0,
+                           rtol=1e-6, atol=1e-8, n_save=0),
+    "lorenz_2p20_t10": dict(system="lorenz", method="tsit5", n=1 << 20, t0=0.0, t1=10.0,
+                            rtol=1e-6, atol=1e-8, n_save=20),
+}
+
+
+def make(name, n=None, seed=0):
+    """(config, y0, params, save_t) of a named workload, optionally resized."""
+    cfg = dict(WORKLOADS[name])
+    if n is not None:
+        cfg["n"] = n
+    gen = {"lorenz": lorenz, "vdp": vdp}[cfg["system"]]
+    y0, p = gen(cfg["n"], seed)
+    st = save_times(cfg["t0"], cfg["t1"], cfg["n_save"]) if cfg["n_save"] else np.array([cfg["t1"]])
+    return cfg, y0, p, st
