@@ -330,6 +330,44 @@ static void erk_phi(const ERK& m, int sys, int d, const T* y, const P* p, T h,
   erk_update(m, d, y, h, k, ynew);
 }
 
+// ------------------------------------------------------- controller power --
+// x^(1/k) for the step-size controller and the starting step, k = 5..8.
+// Built only from operations that are exactly or correctly rounded (frexp,
+// ldexp, +, *, /, fma) so that any implementation that follows the same
+// sequence obtains the same bits: x = m 2^e with m in [0.5, 1), e = k q + j,
+// a linear first guess for m^(1/k) scaled by 2^(j/k) 2^q, then four Newton
+// steps r <- ((k-1) r + x / r^(k-1)) / k.
+static const double TWO_POW_5[5] = {1.0, 1.148698354997035, 1.3195079107728942,
+                                    1.515716566510398, 1.7411011265922482};
+static const double TWO_POW_6[6] = {1.0, 1.122462048309373, 1.2599210498948732,
+                                    1.4142135623730951, 1.5874010519681996,
+                                    1.7817974362806785};
+static const double TWO_POW_7[7] = {1.0, 1.1040895136738123, 1.2190136542044754,
+                                    1.3459001926323562, 1.4859942891369484,
+                                    1.640670712015276, 1.8114473285278134};
+static const double TWO_POW_8[8] = {1.0, 1.0905077326652577, 1.189207115002721,
+                                    1.2968395546510096, 1.4142135623730951,
+                                    1.5422108254079407, 1.681792830507429,
+                                    1.8340080864093424};
+
+static double root_k(double x, int k) {
+  if (!(x > 0.0) || std::isinf(x)) return x;  // 0, inf and NaN map to themselves
+  const double* c = k == 5 ? TWO_POW_5 : k == 6 ? TWO_POW_6 : k == 7 ? TWO_POW_7 : TWO_POW_8;
+  int e;
+  const double m = std::frexp(x, &e);
+  const int q = e >= 0 ? e / k : -((-e + k - 1) / k);
+  const int j = e - q * k;
+  const double lo = 0.5 * c[k - 1];  // 2^(-1/k)
+  const double g = fma(2.0 * (1.0 - lo), m - 0.5, lo);
+  double r = std::ldexp(c[j] * g, q);
+  for (int it = 0; it < 4; ++it) {
+    double pw = r;
+    for (int i = 2; i < k; ++i) pw = pw * r;
+    r = fma((double)(k - 1), r, x / pw) / (double)k;
+  }
+  return r;
+}
+
 // ----------------------------------------------------------------- record --
 enum { ST_OK = 0, ST_MAX_STEPS = 1, ST_DT_UNDERFLOW = 2, ST_NONFINITE = 3,
        ST_NOSPACE = 4 };
@@ -381,7 +419,7 @@ static double initial_step(const ERK& m, int sys, int d, const double* y0,
   double d2 = rms_norm(d, tmp, sc) / h0;
   double dm = std::fmax(d1, d2);
   double h1 = (dm <= 1e-15) ? std::fmax(1e-6, h0 * 1e-3)
-                            : std::pow(0.01 / dm, 1.0 / (double)(m.order + 1));
+                            : root_k(0.01 / dm, m.order + 1);
   return std::fmin(std::fmin(100.0 * h0, h1), t1 - t0);
 }
 
@@ -409,7 +447,7 @@ static void record_lane(const RecordArgs& A, int lane) {
   double h = A.h0 > 0.0 ? std::fmin(A.h0, A.t1 - A.t0)
                         : initial_step(m, sys, d, y, p, k1, A.t0, A.t1, A.rtol,
                                        A.atol);
-  const double expo = -1.0 / (double)(m.q_emb + 1);
+  const int kroot = m.q_emb + 1;  // controller factor 0.9 err^(-1/(q_emb+1))
   int64_t S = 0, trials = 0;
   int next_save = 0;
   bool prev_rejected = false;
@@ -476,12 +514,12 @@ static void record_lane(const RecordArgs& A, int lane) {
       }
       double fac;
       if (err == 0.0) fac = 10.0;
-      else fac = 0.9 * std::pow(err, expo);
+      else fac = 0.9 / root_k(err, kroot);
       fac = std::fmax(0.2, std::fmin(prev_rejected ? 1.0 : 10.0, fac));
       h = h * fac;
       prev_rejected = false;
     } else {
-      double fac = std::fmax(0.2, 0.9 * std::pow(err, expo));
+      double fac = std::fmax(0.2, 0.9 / root_k(err, kroot));
       h = h * fac;
       prev_rejected = true;
     }
@@ -673,6 +711,8 @@ int oracle_erk_tableau(int method, double* c, double* a, double* b, double* ew,
   *q_emb = m->q_emb;
   return m->s;
 }
+
+double oracle_root_k(double x, int k) { return root_k(x, k); }
 
 int oracle_rhs(int sys, const double* y, const double* p, double* f) {
   if (sys_dim(sys) < 0) return -1;

@@ -113,3 +113,17 @@ def test_failure_statuses():
     # unreached save times stay NaN on a failed lane
     r = O.record(O.LORENZ, O.TSIT5, y0, prm, 0.0, 1.0, 1e-6, 1e-8, save_t=[0.5, 1.0], max_steps=5)
     assert np.all(np.isnan(r["y_save"][:, 1]))
+
+
+def test_controller_root_is_accurate():
+    """The controller's k-th root (frexp/ldexp + Newton) against 40 digits."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([np.exp(rng.uniform(-700, 700, 400)), [1.0, 0.5, 2.0, 1e-310, 5e-324, 1.7e308]])
+    for k in (5, 6, 7, 8):
+        for x in xs:
+            r = O.root_k(x, k)
+            ref = float(mp.root(mp.mpf(float(x)), k))
+            assert abs(r - ref) <= 2 * np.spacing(ref), (x, k, r, ref)
+    assert O.root_k(0.0, 5) == 0.0 and np.isinf(O.root_k(np.inf, 5)) and np.isnan(O.root_k(np.nan, 5))
