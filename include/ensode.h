@@ -1,0 +1,230 @@
+/*
+ * ensode.h -- C ABI of the ODE-ensemble record-and-replay gradient library.
+ *
+ * An ensemble is n independent trajectories of one autonomous system
+ * y' = f(y, theta), y in R^d, integrated from t0 to t1, with theta per
+ * trajectory or shared by all (paper, Section 2).  The library exposes the
+ * paper's two user-facing operations (Section 3.4): a forward solve, and a
+ * gradient of a scalar loss formed from sampled states.  The gradient is the
+ * record-and-replay construction of Section 3.1:
+ *
+ *   ensemble_record   runs the adaptive solve (embedded-pair error estimate,
+ *                     RMS acceptance test and step-size controller of
+ *                     Section 2.1) and keeps each trajectory's accepted step
+ *                     sizes h_1..h_S -- its mesh -- together with the state
+ *                     before each accepted step (the "tape").
+ *   ensemble_adjoint  sweeps backward over the recorded mesh: the exact
+ *                     reverse-mode derivative of the fixed chain
+ *                     y_i = Phi(y_{i-1}; h_i, theta) (eq. replay) with the
+ *                     mesh held constant (the stop-gradient sg[h] of
+ *                     Section 3.1).  It recomputes the stages of each step
+ *                     from the taped state and takes vector-Jacobian
+ *                     products through every stage.
+ *
+ * States at requested save times are integrated, not interpolated: each is
+ * one extra step of the method from the last mesh point at or before it
+ * (Section 3.4).  The loss is a function of those save states.
+ *
+ * Device layouts are structure-of-arrays with the trajectory index fastest:
+ *   y0 [dim][n], params [P][n] (or [P] when shared), y_save [n_save][dim][n],
+ *   grad_params [P][n] (or [P] when shared), grad_y0 [dim][n].
+ * Element type is double (ENS_F64) or float (ENS_F32) for states, params
+ * and their gradients; times, step sizes, the error norm and the controller
+ * are always double.
+ *
+ * Ownership.  Every device buffer is allocated by the caller.  The library
+ * allocates no device memory in ensemble_solve / ensemble_record /
+ * ensemble_adjoint: a record lives inside a caller-owned pool whose size
+ * ensemble_record_bytes plans.  A record stays valid, and can serve any
+ * number of adjoints, while its pool is alive and unmodified.
+ *
+ * Streams.  Each call enqueues its work on `stream` (a hipStream_t; NULL is
+ * the default stream) and returns without waiting.  The return code covers
+ * argument validation and launch only.  Per-trajectory outcomes land in
+ * lane_status [n] (ENS_LANE_*), valid once the stream has completed; a
+ * failing trajectory never aborts the others.
+ *
+ * Errors.  Functions return 0 on success or a negative ENS_E* code; the
+ * calling thread's last error text is available from ensemble_last_error().
+ */
+#ifndef ENSODE_H
+#define ENSODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define ENS_OK 0
+#define ENS_EINVAL (-1)       /* null pointer, n <= 0, t1 <= t0, bad tolerance, size mismatch */
+#define ENS_EUNSUPPORTED (-2) /* system x method x dtype combination not built */
+#define ENS_ENOSPACE (-3)     /* pool smaller than the fixed part of a record */
+#define ENS_EHIP (-4)         /* HIP runtime or launch error (text has details) */
+
+/* ---- per-trajectory status (lane_status) ------------------------------- */
+#define ENS_LANE_OK 0
+#define ENS_LANE_MAX_STEPS 1   /* trial budget max_steps exhausted before t1 */
+#define ENS_LANE_DT_UNDERFLOW 2 /* proposed h below 16 eps max(|t|, 1) */
+#define ENS_LANE_NONFINITE 3   /* non-finite initial state or slope */
+#define ENS_LANE_NOSPACE 4     /* the pool ran out of tape pages */
+
+/* ---- problem description ----------------------------------------------- */
+/* Built-in systems (paper, Appendix A; the linear system is the damped
+ * rotation y' = [[-a, -w], [w, -a]] y used for closed-form checks). */
+#define ENS_SYS_LORENZ 1 /* d = 3, P = 3: (sigma, rho, beta) */
+#define ENS_SYS_VDP 2    /* d = 2, P = 1: (mu) */
+#define ENS_SYS_LINEAR 6 /* d = 2, P = 2: (a, w) */
+
+/* Methods (paper, Section 3.2). */
+#define ENS_TSIT5 1 /* Tsitouras 5(4), 7 stages, first-same-as-last */
+#define ENS_VERN7 2 /* Verner 7(6), 10 stages */
+
+#define ENS_F64 1
+#define ENS_F32 2
+
+#define ENS_MAX_SAVE 64
+
+typedef struct {
+  int32_t system;        /* ENS_SYS_* */
+  int32_t method;        /* ENS_TSIT5 / ENS_VERN7 */
+  int32_t dtype;         /* ENS_F64 / ENS_F32 */
+  int32_t dim;           /* must equal the system's state dimension */
+  int32_t nparams;       /* must equal the system's parameter count */
+  int32_t params_shared; /* 0: params [P][n]; 1: params [P] for all trajectories */
+} ens_problem;
+
+typedef struct {
+  int64_t n;                /* trajectories, >= 1 */
+  const void* y0;           /* device [dim][n] */
+  const void* params;       /* device [P][n] or [P] */
+  double t0, t1;            /* t1 > t0 */
+  double rtol, atol;        /* rtol >= 0, atol > 0 (or rtol > 0) */
+  double h0;                /* first trial step; 0 = automatic (Hairer-Norsett-Wanner) */
+  int64_t max_steps;        /* trial budget per trajectory; 0 = 100000 */
+  int32_t n_save;           /* 0: the only save time is t1 */
+  const double* save_times; /* host [n_save], nondecreasing, each in [t0, t1] */
+} ens_ivp;
+
+/* ---- records ------------------------------------------------------------ */
+/* Pool configuration.  ckpt_every must be 0 (a full tape: the state before
+ * every accepted step is kept). */
+typedef struct {
+  void* pool;        /* device, 256-byte aligned */
+  size_t pool_bytes;
+  int32_t ckpt_every;
+} ens_tape_cfg;
+
+/* A record: plain data describing what ensemble_record wrote into a pool.
+ * Filled by ensemble_record / ensemble_replay_mesh; read by the others. */
+typedef struct {
+  int64_t n;
+  int32_t system, method, dtype, dim, nparams, params_shared;
+  int32_t n_save;
+  int32_t page_steps;   /* accepted steps per tape page */
+  int32_t rec_bytes;    /* bytes per taped step: h (double) + state */
+  int64_t n_pages;      /* pages the pool holds */
+  int64_t page_bytes;
+  double t0, t1;
+  void* pool;
+  size_t pool_bytes;
+  /* device pointers into the pool */
+  int32_t* steps;       /* [n] accepted steps S */
+  int32_t* n_trial;     /* [n] trials (accepted + rejected) */
+  int32_t* first_page;  /* [n] */
+  int32_t* last_page;   /* [n] */
+  int32_t* status;      /* [n] copy of lane_status */
+  int32_t* save_idx;    /* [n_save][n] mesh index of each save's base state */
+  double* save_dt;      /* [n_save][n] side-step size t_s - t_base */
+  double* save_times;   /* [max(n_save,1)] */
+  void* y_final;        /* [dim][n] y_S */
+  int32_t* links;       /* [n_pages][2] previous / next page of the trajectory */
+  unsigned long long* counters; /* [8] page counter and step totals */
+  void* pages;          /* [n_pages][page_bytes] */
+} ens_record;
+
+typedef struct {
+  unsigned long long pages_used;
+  unsigned long long steps_accepted; /* summed over trajectories */
+  unsigned long long trials;         /* accepted + rejected, summed */
+  unsigned long long side_steps;     /* save-time steps with nonzero size */
+} ens_stats;
+
+/* Loss on the save states (paper, eq. loss, with the states at the save
+ * times in place of the final state):
+ *   ENS_LOSS_SUMSQ       L = scale * sum ||y(t_s)||^2
+ *   ENS_LOSS_MSE_TARGET  L = scale * sum ||y(t_s) - target_s||^2, data = targets
+ *   ENS_LOSS_COTANGENT   dL/dy(t_s) = data (L itself is not formed)
+ * data is device [n_save][dim][n] (n_save = 0 counts as 1). */
+#define ENS_LOSS_SUMSQ 0
+#define ENS_LOSS_MSE_TARGET 1
+#define ENS_LOSS_COTANGENT 2
+typedef struct {
+  int32_t kind;
+  const void* data;
+  double scale;
+} ens_loss;
+
+/* ---- entry points -------------------------------------------------------- */
+
+/* Forward solve only (paper, Sections 3.3-3.4, the forward-only kernel):
+ * adaptive integration of every trajectory with no record.
+ * y_out: device [max(n_save,1)][dim][n], the states at the save times (t1
+ * when n_save = 0).  lane_status: device [n]. */
+int ensemble_solve(const ens_problem* prob, const ens_ivp* ivp, void* y_out,
+                   int32_t* lane_status, void* stream);
+
+/* Pool bytes for a record of `ivp` if no trajectory accepts more than
+ * steps_hint steps (an upper plan: pages are handed out on demand, so a
+ * trajectory may exceed the hint while others stay below it). */
+int ensemble_record_bytes(const ens_problem* prob, const ens_ivp* ivp,
+                          int64_t steps_hint, int32_t ckpt_every,
+                          size_t* bytes);
+
+/* Record (paper, Section 3.1): adaptive solve keeping the accepted mesh and
+ * the state before each accepted step.  y_save as y_out above. */
+int ensemble_record(const ens_problem* prob, const ens_ivp* ivp,
+                    const ens_tape_cfg* tape, ens_record* out, void* y_save,
+                    int32_t* lane_status, void* stream);
+
+/* Replay a given mesh (paper, eq. replay; the zero-padded rectangle of
+ * Section 3.1): h device [cap][n] with S device [n] steps per trajectory
+ * (entries past S are ignored).  Produces a record as ensemble_record does,
+ * with the mesh held fixed -- the reuse of one record while theta or y0
+ * moves (Section 3.1) and the frozen-mesh finite-difference checks
+ * (Appendix B.6).  The mesh must reach t1: sum of the steps with the last
+ * point set to t1, as the record makes it. */
+int ensemble_replay_mesh(const ens_problem* prob, const ens_ivp* ivp,
+                         const ens_tape_cfg* tape, const double* h,
+                         const int32_t* steps, int64_t cap, ens_record* out,
+                         void* y_save, int32_t* lane_status, void* stream);
+
+/* Export a record's mesh as the zero-padded rectangle h [cap][n] and S [n]
+ * (device).  Trajectories with more than cap steps are truncated and their
+ * S reports the full count. */
+int ensemble_mesh_export(const ens_record* rec, double* h, int32_t* steps,
+                         int64_t cap, void* stream);
+
+/* Reverse sweep (paper, Section 3.1): gradient of the loss with respect to
+ * the parameters (grad_params) and, if grad_y0 is not NULL, the initial
+ * states.  loss_out (device [n], nullable) receives each trajectory's loss.
+ * Trajectories whose record status is not ENS_LANE_OK get NaN gradients and
+ * loss.  The ivp must describe the same ensemble as the record. */
+int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
+                     const ens_record* rec, const ens_loss* loss,
+                     void* grad_params, void* grad_y0, double* loss_out,
+                     void* stream);
+
+/* Totals of a finished record (synchronizes the stream). */
+int ensemble_record_stats(const ens_record* rec, ens_stats* out, void* stream);
+
+/* Text of the calling thread's last error. */
+const char* ensemble_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENSODE_H */

@@ -1,0 +1,217 @@
+"""Python binding of the C ABI (``include/ensode.h``), same names as there.
+
+torch supplies device memory and the stream; all computation runs in the HIP
+kernels of ``libensode.so``.  There is no CPU path: without a GPU and the
+built library these functions raise.
+
+Layouts (trajectory index fastest): y0 [d, n], params [P, n] (or [P] when
+shared), save states [n_save, d, n], grad_params [P, n], grad_y0 [d, n].
+"""
+import ctypes as C
+import math
+
+import torch
+
+from . import _abi as A
+
+_DT = {torch.float64: A.F64, torch.float32: A.F32}
+
+
+def _sysinfo(system):
+    if system not in A.SYSTEMS:
+        raise ValueError(f"unknown system {system!r}; have {sorted(A.SYSTEMS)}")
+    return A.SYSTEMS[system]
+
+
+def _require_gpu(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("ensode works on GPU tensors only")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class _Spec:
+    """Problem + ivp structs with the host arrays they point to kept alive."""
+
+    def __init__(self, system, method, y0, params, t0, t1, rtol, atol, save_times,
+                 h0, max_steps, params_shared):
+        sid, d, npar = _sysinfo(system)
+        if method not in A.METHODS:
+            raise ValueError(f"unknown method {method!r}")
+        if y0.dtype not in _DT:
+            raise ValueError("y0 must be float64 or float32")
+        if params.dtype != y0.dtype:
+            raise ValueError("params must have the dtype of y0")
+        if y0.dim() != 2 or y0.shape[0] != d:
+            raise ValueError(f"y0 must be [{d}, n]")
+        n = y0.shape[1]
+        want_p = (npar,) if params_shared else (npar, n)
+        if tuple(params.shape) != want_p:
+            raise ValueError(f"params must be {list(want_p)}")
+        _require_gpu(y0, params)
+        self.system, self.method, self.d, self.npar, self.n = system, method, d, npar, n
+        self.dtype = y0.dtype
+        self.y0, self.params = y0, params
+        self.prob = A.Problem(sid, A.METHODS[method], _DT[y0.dtype], d, npar, int(params_shared))
+        st = [] if save_times is None else [float(x) for x in save_times]
+        if len(st) > A.MAX_SAVE:
+            raise ValueError(f"at most {A.MAX_SAVE} save times")
+        self._st = (C.c_double * max(1, len(st)))(*st) if st else None
+        self.n_save = max(1, len(st))
+        self.save_times = st
+        self.ivp = A.Ivp(n, y0.data_ptr(), params.data_ptr(), float(t0), float(t1), float(rtol),
+                         float(atol), float(h0), int(max_steps), len(st),
+                         C.cast(self._st, C.POINTER(C.c_double)) if st else None)
+
+
+class RecordHandle:
+    """A record inside its pool (keeps the pool and the inputs alive)."""
+
+    def __init__(self, spec, pool, rec, y_save, status):
+        self.spec, self.pool, self.rec = spec, pool, rec
+        self.y_save, self.status = y_save, status
+
+    @property
+    def n(self):
+        return self.spec.n
+
+    def steps(self):
+        return _view_i32(self.rec.steps, self.n, self.pool)
+
+    def n_trial(self):
+        return _view_i32(self.rec.n_trial, self.n, self.pool)
+
+
+def _view_i32(ptr, n, pool):
+    off = ptr - pool.data_ptr()
+    return pool[off: off + 4 * n].view(torch.int32)
+
+
+def ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save=0,
+                          dtype=torch.float64):
+    sid, d, npar = _sysinfo(system)
+    prob = A.Problem(sid, A.METHODS[method], _DT[dtype], d, npar, 0)
+    st = (C.c_double * max(1, n_save))(*([t1] * max(1, n_save)))
+    ivp = A.Ivp(n, None, None, float(t0), float(t1), 1e-6, 1e-6, 0.0, 0, int(n_save),
+                C.cast(st, C.POINTER(C.c_double)))
+    out = C.c_size_t()
+    A.check(A.load().ensemble_record_bytes(C.byref(prob), C.byref(ivp), int(steps_hint), 0,
+                                           C.byref(out)))
+    return out.value
+
+
+def ensemble_solve(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
+                   max_steps=0, params_shared=False):
+    """Forward solve: (states at the save times [n_save, d, n], lane status [n])."""
+    spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
+                 params_shared)
+    y_out = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
+    status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
+    A.check(A.load().ensemble_solve(C.byref(spec.prob), C.byref(spec.ivp), _ptr(y_out),
+                                    _ptr(status), _stream()))
+    return y_out, status
+
+
+def _pool_for(spec, steps_hint, pool):
+    if pool is not None:
+        _require_gpu(pool)
+        return pool
+    nbytes = ensemble_record_bytes(spec.system, spec.method, spec.n, spec.ivp.t0, spec.ivp.t1,
+                                   steps_hint, spec.ivp.n_save, spec.dtype)
+    return torch.empty(nbytes, dtype=torch.uint8, device=spec.y0.device)
+
+
+def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
+                    max_steps=0, params_shared=False, steps_hint=512, pool=None):
+    """Adaptive record.  Returns a RecordHandle (.y_save, .status, .pool)."""
+    spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
+                 params_shared)
+    pool = _pool_for(spec, steps_hint, pool)
+    tc = A.TapeCfg(pool.data_ptr(), pool.numel(), 0)
+    rec = A.Record()
+    y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
+    status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
+    A.check(A.load().ensemble_record(C.byref(spec.prob), C.byref(spec.ivp), C.byref(tc),
+                                     C.byref(rec), _ptr(y_save), _ptr(status), _stream()))
+    return RecordHandle(spec, pool, rec, y_save, status)
+
+
+def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_times=None,
+                         params_shared=False, pool=None):
+    """Record on a given mesh h [cap, n] (float64), steps [n] (int32)."""
+    spec = _Spec(system, method, y0, params, t0, t1, 1e-6, 1e-6, save_times, 0.0, 0,
+                 params_shared)
+    _require_gpu(h, steps)
+    if h.dtype != torch.float64 or steps.dtype != torch.int32:
+        raise ValueError("h must be float64 and steps int32")
+    if h.dim() != 2 or h.shape[1] != spec.n or steps.shape != (spec.n,):
+        raise ValueError("h must be [cap, n] and steps [n]")
+    cap = h.shape[0]
+    pool = _pool_for(spec, cap, pool)
+    tc = A.TapeCfg(pool.data_ptr(), pool.numel(), 0)
+    rec = A.Record()
+    y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
+    status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
+    A.check(A.load().ensemble_replay_mesh(C.byref(spec.prob), C.byref(spec.ivp), C.byref(tc),
+                                          _ptr(h), _ptr(steps), cap, C.byref(rec), _ptr(y_save),
+                                          _ptr(status), _stream()))
+    return RecordHandle(spec, pool, rec, y_save, status)
+
+
+def ensemble_mesh_export(handle, cap=None):
+    """The record's mesh as the zero-padded rectangle (h [cap, n], steps [n])."""
+    n = handle.n
+    dev = handle.pool.device
+    if cap is None:
+        cap = int(handle.steps().max().item()) if n else 1
+    cap = max(1, cap)
+    h = torch.empty((cap, n), dtype=torch.float64, device=dev)
+    s = torch.empty(n, dtype=torch.int32, device=dev)
+    A.check(A.load().ensemble_mesh_export(C.byref(handle.rec), _ptr(h), _ptr(s), cap, _stream()))
+    return h, s
+
+
+_LOSS = {"sumsq": A.LOSS_SUMSQ, "mse": A.LOSS_MSE_TARGET, "cotangent": A.LOSS_COTANGENT}
+
+
+def ensemble_adjoint(handle, loss="sumsq", data=None, scale=1.0, want_y0=True,
+                     want_loss=True):
+    """Reverse sweep: (grad_params [P, n], grad_y0 [d, n] or None, loss [n] or None)."""
+    spec = handle.spec
+    if loss not in _LOSS:
+        raise ValueError(f"loss must be one of {sorted(_LOSS)}")
+    if data is not None:
+        _require_gpu(data)
+        if data.dtype != spec.dtype or tuple(data.shape) != (spec.n_save, spec.d, spec.n):
+            raise ValueError(f"loss data must be [{spec.n_save}, {spec.d}, {spec.n}] {spec.dtype}")
+    dev = spec.y0.device
+    gp = torch.empty((spec.npar, spec.n), dtype=spec.dtype, device=dev)
+    gy = torch.empty((spec.d, spec.n), dtype=spec.dtype, device=dev) if want_y0 else None
+    ll = torch.empty(spec.n, dtype=torch.float64, device=dev) if want_loss else None
+    lo = A.Loss(_LOSS[loss], data.data_ptr() if data is not None else None, float(scale))
+    A.check(A.load().ensemble_adjoint(C.byref(spec.prob), C.byref(spec.ivp), C.byref(handle.rec),
+                                      C.byref(lo), _ptr(gp), _ptr(gy), _ptr(ll), _stream()))
+    return gp, gy, ll
+
+
+def ensemble_record_stats(handle):
+    st = A.Stats()
+    A.check(A.load().ensemble_record_stats(C.byref(handle.rec), C.byref(st), _stream()))
+    return dict(pages_used=st.pages_used, steps_accepted=st.steps_accepted, trials=st.trials,
+                side_steps=st.side_steps, n_pages=handle.rec.n_pages)
+
+
+def steps_hint_for(mean_steps, margin=1.15):
+    """Pool plan per trajectory from an expected mean step count."""
+    return int(math.ceil(mean_steps * margin)) + 16

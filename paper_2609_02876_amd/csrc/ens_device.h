@@ -1,0 +1,83 @@
+// Device-side building blocks shared by the ensemble kernels: scalar fma
+// wrappers, wavefront primitives and the device view of a record.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ens {
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fmaT(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+enum : int32_t {
+  LANE_OK = 0,
+  LANE_MAX_STEPS = 1,
+  LANE_DT_UNDERFLOW = 2,
+  LANE_NONFINITE = 3,
+  LANE_NOSPACE = 4,
+};
+
+enum : int32_t { LOSS_SUMSQ = 0, LOSS_MSE_TARGET = 1, LOSS_COTANGENT = 2 };
+
+// counters[] slots in the record
+enum : int { CNT_PAGES = 0, CNT_ACCEPTED = 1, CNT_TRIALS = 2, CNT_SIDE = 3 };
+
+constexpr int PAGE_STEPS = 16;  // accepted steps per tape page
+
+// Bytes of one taped step: the step size (double) followed by the state
+// before the step, padded to 16 bytes so a step is read with vector loads.
+template <class T, int D>
+struct TapeRec {
+  static constexpr int BYTES = ((8 + D * (int)sizeof(T)) + 15) / 16 * 16;
+};
+
+// ---------------------------------------------------------- wavefronts --
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` below this lane (its rank among them).
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+// Wave-aggregated bump allocation: every active lane with `want` set gets a
+// distinct slot of a global counter; one atomic per wave.
+__device__ __forceinline__ uint64_t wave_bump(unsigned long long* counter,
+                                              bool want) {
+  const uint64_t mask = __ballot(want);
+  uint64_t base = 0;
+  if (mask) {
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    if (lane_id() == leader)
+      base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+  }
+  return base + (uint64_t)rank_below(mask);
+}
+
+// ----------------------------------------------------------- record view --
+// Device view of a record (see ens_record in ensode.h for the meaning).
+struct RecView {
+  int64_t n;
+  int32_t n_save;        // effective, >= 1
+  int64_t n_pages;
+  int64_t page_bytes;
+  int32_t* steps;
+  int32_t* n_trial;
+  int32_t* first_page;
+  int32_t* last_page;
+  int32_t* status;
+  int32_t* save_idx;     // [n_save][n]
+  double* save_dt;       // [n_save][n]
+  const double* save_times;
+  void* y_final;         // [D][n]
+  int32_t* links;        // [n_pages][2]
+  unsigned long long* counters;
+  char* pages;
+};
+
+}  // namespace ens

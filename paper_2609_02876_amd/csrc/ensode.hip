@@ -1,0 +1,512 @@
+// Host side of the C ABI declared in include/ensode.h: argument checks,
+// pool layout, kernel dispatch over (system, method, dtype).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+
+#include "ensode.h"
+#include "erk.h"
+
+using namespace ens;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(ENS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct SysInfo {
+  int d, np;
+};
+
+bool sys_info(int sys, SysInfo* s) {
+  switch (sys) {
+    case ENS_SYS_LORENZ: *s = {3, 3}; return true;
+    case ENS_SYS_VDP: *s = {2, 1}; return true;
+    case ENS_SYS_LINEAR: *s = {2, 2}; return true;
+  }
+  return false;
+}
+
+size_t elem_size(int dtype) { return dtype == ENS_F32 ? 4 : 8; }
+
+size_t rec_bytes(int dtype, int d) {
+  return ((8 + d * elem_size(dtype)) + 15) / 16 * 16;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_problem(const ens_problem* p, SysInfo* si) {
+  if (!p) return fail(ENS_EINVAL, "problem is NULL");
+  if (!sys_info(p->system, si))
+    return fail(ENS_EUNSUPPORTED, "unknown system %d", p->system);
+  if (p->dim != si->d || p->nparams != si->np)
+    return fail(ENS_EINVAL, "system %d has dim %d and %d params (got %d, %d)",
+                p->system, si->d, si->np, p->dim, p->nparams);
+  if (p->method != ENS_TSIT5 && p->method != ENS_VERN7)
+    return fail(ENS_EUNSUPPORTED, "unknown method %d", p->method);
+  if (p->dtype != ENS_F64 && p->dtype != ENS_F32)
+    return fail(ENS_EUNSUPPORTED, "unknown dtype %d", p->dtype);
+  if (p->params_shared != 0 && p->params_shared != 1)
+    return fail(ENS_EINVAL, "params_shared must be 0 or 1");
+  return ENS_OK;
+}
+
+int check_ivp(const ens_ivp* v, bool need_ptrs) {
+  if (!v) return fail(ENS_EINVAL, "ivp is NULL");
+  if (v->n <= 0 || v->n > (int64_t)INT32_MAX * 64)
+    return fail(ENS_EINVAL, "n = %lld out of range", (long long)v->n);
+  if (need_ptrs && (!v->y0 || !v->params))
+    return fail(ENS_EINVAL, "y0 and params must be device pointers");
+  if (!(std::isfinite(v->t0) && std::isfinite(v->t1) && v->t1 > v->t0))
+    return fail(ENS_EINVAL, "need finite t0 < t1 (got %g, %g)", v->t0, v->t1);
+  if (!(v->rtol >= 0.0 && v->atol >= 0.0 && (v->rtol > 0.0 || v->atol > 0.0)) ||
+      !std::isfinite(v->rtol) || !std::isfinite(v->atol))
+    return fail(ENS_EINVAL, "need rtol >= 0, atol >= 0, not both zero");
+  if (!(v->h0 >= 0.0) || !std::isfinite(v->h0))
+    return fail(ENS_EINVAL, "h0 must be finite and >= 0");
+  if (v->max_steps < 0 || v->max_steps > INT32_MAX)
+    return fail(ENS_EINVAL, "max_steps out of range");
+  if (v->n_save < 0 || v->n_save > ENS_MAX_SAVE)
+    return fail(ENS_EINVAL, "n_save must be in [0, %d]", ENS_MAX_SAVE);
+  if (v->n_save > 0) {
+    if (!v->save_times) return fail(ENS_EINVAL, "save_times is NULL");
+    for (int i = 0; i < v->n_save; ++i) {
+      const double s = v->save_times[i];
+      if (!(s >= v->t0 && s <= v->t1))
+        return fail(ENS_EINVAL, "save time %d = %g outside [t0, t1]", i, s);
+      if (i > 0 && s < v->save_times[i - 1])
+        return fail(ENS_EINVAL, "save times must be nondecreasing");
+    }
+  }
+  return ENS_OK;
+}
+
+// Pool layout of a record.
+struct Layout {
+  size_t counters, save_times, steps, n_trial, first_page, last_page, status,
+      save_idx, save_dt, y_final, links, pages;
+  size_t fixed;  // bytes before the links array
+  size_t page_bytes;
+};
+
+Layout layout(int64_t n, int n_save_eff, int d, int dtype) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  L.counters = take(8 * sizeof(unsigned long long));
+  L.save_times = take(ENS_MAX_SAVE * sizeof(double));
+  L.steps = take(n * 4);
+  L.n_trial = take(n * 4);
+  L.first_page = take(n * 4);
+  L.last_page = take(n * 4);
+  L.status = take(n * 4);
+  L.save_idx = take((size_t)n_save_eff * n * 4);
+  L.save_dt = take((size_t)n_save_eff * n * 8);
+  L.y_final = take((size_t)d * n * elem_size(dtype));
+  L.fixed = off;
+  L.links = off;
+  L.page_bytes = (size_t)PAGE_STEPS * rec_bytes(dtype, d);
+  return L;
+}
+
+int64_t pages_in(const Layout& L, size_t pool_bytes) {
+  if (pool_bytes < L.fixed + 512) return 0;
+  // links (8 B per page) then 256-aligned pages
+  size_t avail = pool_bytes - L.fixed - 256;
+  return (int64_t)(avail / (L.page_bytes + 8));
+}
+
+void fill_record(ens_record* r, const ens_problem* p, const ens_ivp* v,
+                 const ens_tape_cfg* tc, const Layout& L, int64_t n_pages) {
+  memset(r, 0, sizeof *r);
+  char* base = (char*)tc->pool;
+  r->n = v->n;
+  r->system = p->system;
+  r->method = p->method;
+  r->dtype = p->dtype;
+  r->dim = p->dim;
+  r->nparams = p->nparams;
+  r->params_shared = p->params_shared;
+  r->n_save = v->n_save > 0 ? v->n_save : 1;
+  r->page_steps = PAGE_STEPS;
+  r->rec_bytes = (int32_t)rec_bytes(p->dtype, p->dim);
+  r->n_pages = n_pages;
+  r->page_bytes = (int64_t)L.page_bytes;
+  r->t0 = v->t0;
+  r->t1 = v->t1;
+  r->pool = tc->pool;
+  r->pool_bytes = tc->pool_bytes;
+  r->counters = (unsigned long long*)(base + L.counters);
+  r->save_times = (double*)(base + L.save_times);
+  r->steps = (int32_t*)(base + L.steps);
+  r->n_trial = (int32_t*)(base + L.n_trial);
+  r->first_page = (int32_t*)(base + L.first_page);
+  r->last_page = (int32_t*)(base + L.last_page);
+  r->status = (int32_t*)(base + L.status);
+  r->save_idx = (int32_t*)(base + L.save_idx);
+  r->save_dt = (double*)(base + L.save_dt);
+  r->y_final = base + L.y_final;
+  r->links = (int32_t*)(base + L.links);
+  r->pages = base + align256(L.links + (size_t)n_pages * 8);
+}
+
+RecView view_of(const ens_record* r) {
+  RecView v{};
+  v.n = r->n;
+  v.n_save = r->n_save;
+  v.n_pages = r->n_pages;
+  v.page_bytes = r->page_bytes;
+  v.steps = r->steps;
+  v.n_trial = r->n_trial;
+  v.first_page = r->first_page;
+  v.last_page = r->last_page;
+  v.status = r->status;
+  v.save_idx = r->save_idx;
+  v.save_dt = r->save_dt;
+  v.save_times = r->save_times;
+  v.y_final = r->y_final;
+  v.links = r->links;
+  v.counters = r->counters;
+  v.pages = (char*)r->pages;
+  return v;
+}
+
+// Small setup kernel: clears the counters and copies the save times into the
+// pool (no memset node, so the sequence stays capturable).
+__global__ void setup_kernel(unsigned long long* counters, double* dst,
+                             const SaveTimes st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) counters[i] = 0ull;
+#pragma unroll
+    for (int i = 0; i < ENS_MAX_SAVE; ++i)
+      if (i < st.n) dst[i] = st.t[i];
+  }
+}
+
+SaveTimes save_times_of(const ens_ivp* v) {
+  SaveTimes st{};
+  if (v->n_save > 0) {
+    st.n = v->n_save;
+    for (int i = 0; i < v->n_save; ++i) st.t[i] = v->save_times[i];
+  } else {
+    st.n = 1;
+    st.t[0] = v->t1;
+  }
+  return st;
+}
+
+IvpArgs ivp_args(const ens_problem* p, const ens_ivp* v) {
+  IvpArgs a{};
+  a.n = v->n;
+  a.y0 = v->y0;
+  a.params = v->params;
+  a.params_shared = p->params_shared;
+  a.t0 = v->t0;
+  a.t1 = v->t1;
+  a.rtol = v->rtol;
+  a.atol = v->atol;
+  a.h0 = v->h0;
+  a.max_steps = v->max_steps > 0 ? v->max_steps : 100000;
+  a.n_save = v->n_save > 0 ? v->n_save : 1;
+  a.st = save_times_of(v);
+  return a;
+}
+
+// ------------------------------------------------------------- dispatch --
+template <class F>
+int with_kernels(int sys, int method, int dtype, F&& f) {
+  auto by_type = [&](auto sys_tag, auto tab_tag) -> int {
+    if (dtype == ENS_F64) return f(sys_tag, tab_tag, double{});
+    return f(sys_tag, tab_tag, float{});
+  };
+  auto by_method = [&](auto sys_tag) -> int {
+    if (method == ENS_TSIT5) return by_type(sys_tag, Tsit5{});
+    return by_type(sys_tag, Vern7{});
+  };
+  switch (sys) {
+    case ENS_SYS_LORENZ: return by_method(Lorenz{});
+    case ENS_SYS_VDP: return by_method(VanDerPol{});
+    case ENS_SYS_LINEAR: return by_method(Linear{});
+  }
+  return fail(ENS_EUNSUPPORTED, "unknown system %d", sys);
+}
+
+constexpr int BLOCK = 256;
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+int launch_forward(const ens_problem* p, int mode, const FwdArgs& fa,
+                   hipStream_t st) {
+  return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
+    using Sys = decltype(s);
+    using Tab = decltype(m);
+    using T = decltype(t);
+    if (mode == MODE_SOLVE)
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_SOLVE>),
+                         dim3(grid_of(fa.ivp.n)), dim3(BLOCK), 0, st, fa);
+    else if (mode == MODE_RECORD)
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD>),
+                         dim3(grid_of(fa.ivp.n)), dim3(BLOCK), 0, st, fa);
+    else
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_FROZEN>),
+                         dim3(grid_of(fa.ivp.n)), dim3(BLOCK), 0, st, fa);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ENS_OK : hip_fail(e, "forward launch");
+  });
+}
+
+int check_record_matches(const ens_problem* p, const ens_ivp* v,
+                         const ens_record* r) {
+  if (!r) return fail(ENS_EINVAL, "record is NULL");
+  if (r->n != v->n || r->system != p->system || r->method != p->method ||
+      r->dtype != p->dtype || r->params_shared != p->params_shared)
+    return fail(ENS_EINVAL, "record does not match the problem / ivp");
+  if (r->n_save != (v->n_save > 0 ? v->n_save : 1))
+    return fail(ENS_EINVAL, "record has %d save times, ivp %d", r->n_save,
+                v->n_save);
+  if (!r->pool || !r->pages) return fail(ENS_EINVAL, "record has no pool");
+  return ENS_OK;
+}
+
+int record_common(const ens_problem* p, const ens_ivp* v,
+                  const ens_tape_cfg* tc, int mode, const double* mesh_h,
+                  const int32_t* mesh_S, int64_t cap, ens_record* out,
+                  void* y_save, int32_t* lane_status, void* stream) {
+  SysInfo si;
+  int rc;
+  if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
+  if ((rc = check_ivp(v, true)) != ENS_OK) return rc;
+  if (!tc || !tc->pool) return fail(ENS_EINVAL, "tape pool is NULL");
+  if (((uintptr_t)tc->pool & 255) != 0)
+    return fail(ENS_EINVAL, "tape pool must be 256-byte aligned");
+  if (tc->ckpt_every != 0)
+    return fail(ENS_EUNSUPPORTED, "ckpt_every must be 0 (full tape)");
+  if (!out || !y_save) return fail(ENS_EINVAL, "out and y_save are required");
+  const int nse = v->n_save > 0 ? v->n_save : 1;
+  Layout L = layout(v->n, nse, si.d, p->dtype);
+  const int64_t n_pages = pages_in(L, tc->pool_bytes);
+  if (n_pages <= 0)
+    return fail(ENS_ENOSPACE, "pool of %zu bytes is below the fixed part (%zu)",
+                tc->pool_bytes, L.fixed + 512);
+  if (n_pages > INT32_MAX) return fail(ENS_EINVAL, "pool too large");
+  fill_record(out, p, v, tc, L, n_pages);
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(64), 0, st, out->counters,
+                     out->save_times, save_times_of(v));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "setup launch");
+  FwdArgs fa{};
+  fa.ivp = ivp_args(p, v);
+  fa.rec = view_of(out);
+  fa.y_save = y_save;
+  fa.lane_status = lane_status;
+  fa.mesh_h = mesh_h;
+  fa.mesh_S = mesh_S;
+  fa.cap = cap;
+  return launch_forward(p, mode, fa, st);
+}
+
+// Mesh export: walk each trajectory's pages forward.
+__global__ void mesh_export_kernel(const RecView R, int64_t rec_b, double* h,
+                                   int32_t* steps, int64_t cap) {
+  const int64_t n = R.n;
+  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tr >= n) return;
+  const int32_t S = R.steps[tr];
+  steps[tr] = S;
+  int32_t page = R.first_page[tr];
+  for (int32_t i = 0; i < S && i < cap; ++i) {
+    const int slot = i % PAGE_STEPS;
+    if (i > 0 && slot == 0) page = R.links[2 * (int64_t)page + 1];
+    h[(int64_t)i * n + tr] = *(const double*)(R.pages + (int64_t)page * R.page_bytes +
+                                              slot * rec_b);
+  }
+  for (int64_t i = S; i < cap; ++i) h[i * n + tr] = 0.0;
+}
+
+// Totals of a record: pages used, accepted steps, trials, nonzero side steps.
+__global__ void stats_kernel(const RecView R, unsigned long long* out) {
+  __shared__ unsigned long long red[3][BLOCK];
+  const int64_t n = R.n;
+  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long a = 0, b = 0, c = 0;
+  if (tr < n) {
+    a = (unsigned)R.steps[tr];
+    b = (unsigned)R.n_trial[tr];
+    for (int s = 0; s < R.n_save; ++s) {
+      const double dt = R.save_dt[(int64_t)s * n + tr];
+      c += (dt != 0.0 && R.save_idx[(int64_t)s * n + tr] >= 0) ? 1ull : 0ull;
+    }
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int off = BLOCK / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+      red[2][threadIdx.x] += red[2][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[0], red[0][0]);
+    atomicAdd(&out[1], red[1][0]);
+    atomicAdd(&out[2], red[2][0]);
+  }
+}
+
+__global__ void zero3_kernel(unsigned long long* p) {
+  if (threadIdx.x < 3) p[threadIdx.x] = 0ull;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ==
+extern "C" {
+
+const char* ensemble_last_error(void) { return g_err.c_str(); }
+
+int ensemble_solve(const ens_problem* p, const ens_ivp* v, void* y_out,
+                   int32_t* lane_status, void* stream) {
+  SysInfo si;
+  int rc;
+  if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
+  if ((rc = check_ivp(v, true)) != ENS_OK) return rc;
+  if (!y_out) return fail(ENS_EINVAL, "y_out is NULL");
+  FwdArgs fa{};
+  fa.ivp = ivp_args(p, v);
+  fa.y_save = y_out;
+  fa.lane_status = lane_status;
+  return launch_forward(p, MODE_SOLVE, fa, (hipStream_t)stream);
+}
+
+int ensemble_record_bytes(const ens_problem* p, const ens_ivp* v,
+                          int64_t steps_hint, int32_t ckpt_every,
+                          size_t* bytes) {
+  SysInfo si;
+  int rc;
+  if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
+  if ((rc = check_ivp(v, false)) != ENS_OK) return rc;
+  if (!bytes) return fail(ENS_EINVAL, "bytes is NULL");
+  if (ckpt_every != 0) return fail(ENS_EUNSUPPORTED, "ckpt_every must be 0");
+  if (steps_hint < 1) return fail(ENS_EINVAL, "steps_hint must be >= 1");
+  const int nse = v->n_save > 0 ? v->n_save : 1;
+  Layout L = layout(v->n, nse, si.d, p->dtype);
+  const int64_t pages_per = (steps_hint + PAGE_STEPS - 1) / PAGE_STEPS;
+  const int64_t n_pages = pages_per * v->n;
+  *bytes = L.fixed + 512 + (size_t)n_pages * (L.page_bytes + 8);
+  return ENS_OK;
+}
+
+int ensemble_record(const ens_problem* p, const ens_ivp* v,
+                    const ens_tape_cfg* tc, ens_record* out, void* y_save,
+                    int32_t* lane_status, void* stream) {
+  return record_common(p, v, tc, MODE_RECORD, nullptr, nullptr, 0, out, y_save,
+                       lane_status, stream);
+}
+
+int ensemble_replay_mesh(const ens_problem* p, const ens_ivp* v,
+                         const ens_tape_cfg* tc, const double* h,
+                         const int32_t* steps, int64_t cap, ens_record* out,
+                         void* y_save, int32_t* lane_status, void* stream) {
+  if (!h || !steps || cap < 1) return fail(ENS_EINVAL, "mesh h / steps / cap");
+  return record_common(p, v, tc, MODE_FROZEN, h, steps, cap, out, y_save,
+                       lane_status, stream);
+}
+
+int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,
+                         int64_t cap, void* stream) {
+  if (!r || !h || !steps || cap < 1) return fail(ENS_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(mesh_export_kernel, dim3(grid_of(r->n)), dim3(BLOCK), 0, st,
+                     view_of(r), (int64_t)r->rec_bytes, h, steps, cap);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ENS_OK : hip_fail(e, "export launch");
+}
+
+int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
+                     const ens_record* r, const ens_loss* loss,
+                     void* grad_params, void* grad_y0, double* loss_out,
+                     void* stream) {
+  SysInfo si;
+  int rc;
+  if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
+  if ((rc = check_ivp(v, true)) != ENS_OK) return rc;
+  if ((rc = check_record_matches(p, v, r)) != ENS_OK) return rc;
+  if (!loss) return fail(ENS_EINVAL, "loss is NULL");
+  if (loss->kind != ENS_LOSS_SUMSQ && loss->kind != ENS_LOSS_MSE_TARGET &&
+      loss->kind != ENS_LOSS_COTANGENT)
+    return fail(ENS_EINVAL, "unknown loss kind %d", loss->kind);
+  if (loss->kind != ENS_LOSS_SUMSQ && !loss->data)
+    return fail(ENS_EINVAL, "loss data is NULL");
+  if (!grad_params) return fail(ENS_EINVAL, "grad_params is NULL");
+  if (p->params_shared)
+    return fail(ENS_EUNSUPPORTED, "shared parameters: adjoint not built yet");
+  AdjArgs aa{};
+  aa.ivp = ivp_args(p, v);
+  aa.rec = view_of(r);
+  aa.loss_kind = loss->kind;
+  aa.loss_data = loss->data;
+  aa.scale = loss->scale;
+  aa.grad_p = grad_params;
+  aa.grad_y0 = grad_y0;
+  aa.loss_out = loss_out;
+  hipStream_t st = (hipStream_t)stream;
+  return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
+    using Sys = decltype(s);
+    using Tab = decltype(m);
+    using T = decltype(t);
+    hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T>), dim3(grid_of(v->n)),
+                       dim3(BLOCK), 0, st, aa);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
+  });
+}
+
+int ensemble_record_stats(const ens_record* r, ens_stats* out, void* stream) {
+  if (!r || !out) return fail(ENS_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  // counters[4..6] of the record receive the step totals
+  unsigned long long* tot = r->counters + 4;
+  hipLaunchKernelGGL(zero3_kernel, dim3(1), dim3(64), 0, st, tot);
+  hipLaunchKernelGGL(stats_kernel, dim3(grid_of(r->n)), dim3(BLOCK), 0, st,
+                     view_of(r), tot);
+  unsigned long long host[7] = {0};
+  hipError_t e = hipMemcpyAsync(host, r->counters, sizeof host,
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "stats");
+  out->pages_used = host[0] < (unsigned long long)r->n_pages ? host[0]
+                                                             : (unsigned long long)r->n_pages;
+  out->steps_accepted = host[4];
+  out->trials = host[5];
+  out->side_steps = host[6];
+  return ENS_OK;
+}
+
+}  // extern "C"

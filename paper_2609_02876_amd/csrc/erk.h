@@ -1,0 +1,640 @@
+// Explicit Runge-Kutta ensemble kernels: forward solve, record (adaptive or
+// on a given mesh) and the reverse sweep.  One trajectory per lane; the
+// state, the parameters and the stage vectors live in registers.
+//
+// Paper references: trial step eq. (stages)/(update) and the embedded error
+// estimate, RMS test and controller of Section 2.1; record and replay of
+// Section 3.1 (eq. replay); save states by one extra step (Section 3.4).
+//
+// Control flow is kept uniform across a wavefront: every loop iteration of a
+// lane is one step evaluation Phi(y_base; h) whose base and size are chosen
+// by selects -- a trial from the current state, or a side step from the base
+// of the last accepted step to a save time.  The reverse sweep is the same:
+// one VJP of Phi per iteration, for a mesh step or a save-time side step.
+#pragma once
+#include <math.h>
+
+#include "ens_device.h"
+#include "systems.h"
+#include "tableaux.h"
+
+namespace ens {
+
+constexpr double EPS64 = 2.220446049250313e-16;
+
+enum : int { MODE_SOLVE = 0, MODE_RECORD = 1, MODE_FROZEN = 2 };
+
+// Save times travel by value in the kernel arguments (constant memory).
+struct SaveTimes {
+  double t[64];
+  int n;
+};
+
+// t[i] for a lane-varying i without indexing the argument block dynamically.
+__device__ __forceinline__ double save_time_at(const SaveTimes& st, int i) {
+  return st.t[i];
+}
+
+struct IvpArgs {
+  int64_t n;
+  const void* y0;      // [D][n]
+  const void* params;  // [NP][n] or [NP]
+  int32_t params_shared;
+  double t0, t1, rtol, atol, h0;
+  int64_t max_steps;
+  int32_t n_save;  // >= 1 (t1 alone when the caller asks for none)
+  SaveTimes st;
+};
+
+struct FwdArgs {
+  IvpArgs ivp;
+  RecView rec;
+  void* y_save;           // [n_save][D][n]
+  int32_t* lane_status;   // [n]
+  const double* mesh_h;   // MODE_FROZEN: [cap][n]
+  const int32_t* mesh_S;  // MODE_FROZEN: [n]
+  int64_t cap;
+};
+
+struct AdjArgs {
+  IvpArgs ivp;
+  RecView rec;
+  int32_t loss_kind;
+  const void* loss_data;  // [n_save][D][n]
+  double scale;
+  void* grad_p;           // [NP][n]
+  void* grad_y0;          // [D][n] or null
+  double* loss_out;       // [n] or null
+};
+
+// ------------------------------------------------------------ one step --
+// Stage inputs Y_i = y + h * sum_j a_ij k_j (index order, fma) and stage
+// values k_i = f(Y_i) for i = 1..NST-1; k[0] = f(y) is given.
+template <class Sys, class Tab, class T, int NST>
+__device__ __forceinline__ void stages(const T* y, const T* p, T h,
+                                       T (&k)[NST][Sys::D],
+                                       T (&Y)[NST][Sys::D]) {
+  constexpr int D = Sys::D;
+#pragma unroll
+  for (int c = 0; c < D; ++c) Y[0][c] = y[c];
+#pragma unroll
+  for (int i = 1; i < NST; ++i) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T acc = T(0);
+      bool first = true;
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        if (Tab::A[i][j] != 0.0) {
+          if (first) {
+            acc = T(Tab::A[i][j]) * k[j][c];
+            first = false;
+          } else {
+            acc = fmaT(T(Tab::A[i][j]), k[j][c], acc);
+          }
+        }
+      }
+      Y[i][c] = fmaT(h, acc, y[c]);
+    }
+    Sys::rhs(Y[i], p, k[i]);
+  }
+}
+
+// y_new = y + h * sum_j b_j k_j over the stages with b_j != 0.
+template <class Tab, class T, int D, int NST>
+__device__ __forceinline__ void update(const T* y, T h, const T (&k)[NST][D],
+                                       T* ynew) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+      if (Tab::B[j] != 0.0) {
+        if (first) {
+          acc = T(Tab::B[j]) * k[j][c];
+          first = false;
+        } else {
+          acc = fmaT(T(Tab::B[j]), k[j][c], acc);
+        }
+      }
+    }
+    ynew[c] = fmaT(h, acc, y[c]);
+  }
+}
+
+// Scaled RMS norm sqrt(mean (v_c / sc_c)^2) with squares summed by fma.
+template <int D>
+__device__ __forceinline__ double rms(const double* v, const double* sc) {
+  double r = v[0] / sc[0];
+  double ss = r * r;
+#pragma unroll
+  for (int c = 1; c < D; ++c) {
+    r = v[c] / sc[c];
+    ss = fmaT(r, r, ss);
+  }
+  return sqrt(ss / (double)D);
+}
+
+// Error estimate e = h sum_j ew_j k_j (in double) and its norm against
+// atol + rtol max(|y|, |y_new|).
+template <class Tab, class T, int D, int NST>
+__device__ __forceinline__ double err_norm(const T* y, const T* ynew, double h,
+                                           const T (&k)[NST][D], double rtol,
+                                           double atol) {
+  double e[D], sc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double acc = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+      if (Tab::EW[j] != 0.0) {
+        if (first) {
+          acc = Tab::EW[j] * (double)k[j][c];
+          first = false;
+        } else {
+          acc = fmaT(Tab::EW[j], (double)k[j][c], acc);
+        }
+      }
+    }
+    e[c] = h * acc;
+    sc[c] = fmaT(rtol, fmax(fabs((double)y[c]), fabs((double)ynew[c])), atol);
+  }
+  return rms<D>(e, sc);
+}
+
+// x^(1/K) for the controller and the starting step (K = 5..8), from
+// operations that are exactly or correctly rounded on the device and on any
+// IEEE host: x = m 2^e (m in [0.5, 1)), e = K q + j, linear first guess for
+// m^(1/K) times 2^(j/K) 2^q, then four Newton steps
+// r <- ((K-1) r + x / r^(K-1)) / K.  Deterministic to the bit.
+template <int K>
+struct TwoPow;
+template <>
+struct TwoPow<5> {
+  static constexpr double c[5] = {1.0, 1.148698354997035, 1.3195079107728942,
+                                  1.515716566510398, 1.7411011265922482};
+};
+template <>
+struct TwoPow<6> {
+  static constexpr double c[6] = {1.0, 1.122462048309373, 1.2599210498948732,
+                                  1.4142135623730951, 1.5874010519681996,
+                                  1.7817974362806785};
+};
+template <>
+struct TwoPow<7> {
+  static constexpr double c[7] = {1.0, 1.1040895136738123, 1.2190136542044754,
+                                  1.3459001926323562, 1.4859942891369484,
+                                  1.640670712015276, 1.8114473285278134};
+};
+template <>
+struct TwoPow<8> {
+  static constexpr double c[8] = {1.0, 1.0905077326652577, 1.189207115002721,
+                                  1.2968395546510096, 1.4142135623730951,
+                                  1.5422108254079407, 1.681792830507429,
+                                  1.8340080864093424};
+};
+
+template <int K>
+__device__ __forceinline__ double root_k(double x) {
+  if (!(x > 0.0) || isinf(x)) return x;
+  int e;
+  const double m = frexp(x, &e);
+  const int q = e >= 0 ? e / K : -((-e + K - 1) / K);
+  const int j = e - q * K;
+  double cj = 1.0;
+#pragma unroll
+  for (int i = 0; i < K; ++i) cj = (i == j) ? TwoPow<K>::c[i] : cj;
+  const double lo = 0.5 * TwoPow<K>::c[K - 1];
+  const double g = fmaT(2.0 * (1.0 - lo), m - 0.5, lo);
+  double r = ldexp(cj * g, q);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    double pw = r;
+#pragma unroll
+    for (int i = 2; i < K; ++i) pw = pw * r;
+    r = fmaT((double)(K - 1), r, x / pw) / (double)K;
+  }
+  return r;
+}
+
+// Starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4).
+template <class Sys, class Tab, class T>
+__device__ double initial_step(const T* y0, const T* p, const T* f0, double t0,
+                               double t1, double rtol, double atol) {
+  constexpr int D = Sys::D;
+  double sc[D], v[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) sc[c] = fmaT(rtol, fabs((double)y0[c]), atol);
+#pragma unroll
+  for (int c = 0; c < D; ++c) v[c] = (double)y0[c];
+  const double d0 = rms<D>(v, sc);
+#pragma unroll
+  for (int c = 0; c < D; ++c) v[c] = (double)f0[c];
+  const double d1 = rms<D>(v, sc);
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
+  h0 = fmin(h0, t1 - t0);
+  T y1[D], f1[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y1[c] = fmaT(T(h0), f0[c], y0[c]);
+  Sys::rhs(y1, p, f1);
+#pragma unroll
+  for (int c = 0; c < D; ++c) v[c] = (double)(f1[c] - f0[c]);
+  const double d2 = rms<D>(v, sc) / h0;
+  const double dm = fmax(d1, d2);
+  const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3)
+                                  : root_k<Tab::ORDER + 1>(0.01 / dm);
+  return fmin(fmin(100.0 * h0, h1), t1 - t0);
+}
+
+template <class T, int NP>
+__device__ __forceinline__ void load_params(const IvpArgs& a, int64_t tr, T* p) {
+  const T* P = (const T*)a.params;
+#pragma unroll
+  for (int c = 0; c < NP; ++c) p[c] = a.params_shared ? P[c] : P[c * a.n + tr];
+}
+
+// ------------------------------------------------------- forward / record --
+// MODE_SOLVE: adaptive solve, no tape.  MODE_RECORD: adaptive solve writing
+// the tape.  MODE_FROZEN: steps taken from a given mesh, writing the tape.
+template <class Sys, class Tab, class T, int MODE>
+__global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
+  constexpr int D = Sys::D, NP = Sys::NP, K = PAGE_STEPS;
+  constexpr int RB = TapeRec<T, D>::BYTES;
+  const int64_t n = a.ivp.n;
+  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tr >= n) return;
+  const double t0 = a.ivp.t0, t1 = a.ivp.t1;
+  const double rtol = a.ivp.rtol, atol = a.ivp.atol;
+  const int ns = a.ivp.n_save;
+  T* ysv = (T*)a.y_save;
+  const RecView& R = a.rec;
+
+  T y[D], p[NP], k1[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = ((const T*)a.ivp.y0)[c * n + tr];
+  load_params<T, NP>(a.ivp, tr, p);
+  Sys::rhs(y, p, k1);
+  int32_t status = LANE_OK;
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    if (!isfinite(y[c]) || !isfinite(k1[c])) status = LANE_NONFINITE;
+
+  double t = t0, h = 0.0;
+  int32_t S_mesh = 0;
+  if constexpr (MODE == MODE_FROZEN) {
+    S_mesh = a.mesh_S[tr];
+    // a step count the rectangle cannot hold is refused for this lane
+    if (S_mesh < 0 || (int64_t)S_mesh > a.cap) {
+      S_mesh = 0;
+      status = LANE_MAX_STEPS;
+    }
+  } else if (status == LANE_OK) {
+    h = a.ivp.h0 > 0.0 ? fmin(a.ivp.h0, t1 - t0)
+                       : initial_step<Sys, Tab, T>(y, p, k1, t0, t1, rtol, atol);
+  }
+
+  T yp[D], k1p[D];  // base state (and its slope) of the last accepted step
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    yp[c] = y[c];
+    k1p[c] = k1[c];
+  }
+  double tp = t0;
+  int next_save = 0;
+  double ts = a.ivp.st.t[0];
+  bool side = false;
+  int32_t S = 0, trials = 0;
+  bool prev_rej = false;
+  int32_t page = -1;
+  char* pg = nullptr;
+
+  while (status == LANE_OK &&
+         (side || (MODE == MODE_FROZEN ? (S < S_mesh) : (t < t1)))) {
+    double hh;
+    bool last = false;
+    if (!side) {
+      if constexpr (MODE == MODE_FROZEN) {
+        hh = a.mesh_h[(int64_t)S * n + tr];
+        last = (S == S_mesh - 1);
+        ++trials;
+      } else {
+        if (trials >= a.ivp.max_steps) {
+          status = LANE_MAX_STEPS;
+          break;
+        }
+        if (h < 16.0 * EPS64 * fmax(fabs(t), 1.0)) {
+          status = LANE_DT_UNDERFLOW;
+          break;
+        }
+        ++trials;
+        if (t + h >= t1) {
+          h = t1 - t;
+          last = true;
+        }
+        hh = h;
+      }
+    } else {
+      hh = ts - tp;
+    }
+
+    // one evaluation of the step map from the selected base
+    T yb[D];
+    T k[Tab::S][D], Y[Tab::S][D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) yb[c] = side ? yp[c] : y[c];
+    if constexpr (Tab::FSAL) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) k[0][c] = side ? k1p[c] : k1[c];
+    } else {
+      Sys::rhs(yb, p, k[0]);
+    }
+    stages<Sys, Tab, T, Tab::S>(yb, p, T(hh), k, Y);
+    T ynew[D];
+    if constexpr (Tab::FSAL) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) ynew[c] = Y[Tab::S - 1][c];
+    } else {
+      update<Tab, T, D, Tab::S>(yb, T(hh), k, ynew);
+    }
+    double err = 0.0;
+    if constexpr (MODE != MODE_FROZEN)
+      err = err_norm<Tab, T, D, Tab::S>(yb, ynew, hh, k, rtol, atol);
+
+    if (side) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) ysv[((int64_t)next_save * D + c) * n + tr] = ynew[c];
+      if constexpr (MODE != MODE_SOLVE) {
+        R.save_idx[(int64_t)next_save * n + tr] = S - 1;
+        R.save_dt[(int64_t)next_save * n + tr] = hh;
+      }
+      ++next_save;
+      ts = next_save < ns ? save_time_at(a.ivp.st, next_save) : INFINITY;
+      side = ts < t;
+      continue;
+    }
+
+    if (MODE == MODE_FROZEN || err <= 1.0) {
+      if constexpr (MODE != MODE_SOLVE) {
+        const int slot = S % K;
+        const bool need = (slot == 0);
+        const uint64_t got = wave_bump(&R.counters[CNT_PAGES], need);
+        if (need) {
+          if (got >= (uint64_t)R.n_pages) {
+            status = LANE_NOSPACE;
+            break;
+          }
+          const int32_t np_ = (int32_t)got;
+          R.links[2 * (int64_t)np_] = page;
+          R.links[2 * (int64_t)np_ + 1] = -1;
+          if (page >= 0)
+            R.links[2 * (int64_t)page + 1] = np_;
+          else
+            R.first_page[tr] = np_;
+          page = np_;
+          pg = R.pages + (int64_t)page * R.page_bytes;
+        }
+        char* rp = pg + slot * RB;
+        *(double*)rp = hh;
+#pragma unroll
+        for (int c = 0; c < D; ++c) ((T*)(rp + 8))[c] = yb[c];
+      }
+      ++S;
+      tp = t;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        yp[c] = y[c];
+        k1p[c] = k1[c];
+        y[c] = ynew[c];
+      }
+      if constexpr (Tab::FSAL) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) k1[c] = k[Tab::S - 1][c];
+      }
+      t = last ? t1 : t + hh;
+      if constexpr (MODE != MODE_FROZEN) {
+        double fac = (err == 0.0) ? 10.0 : 0.9 / root_k<Tab::QEMB + 1>(err);
+        fac = fmax(0.2, fmin(prev_rej ? 1.0 : 10.0, fac));
+        h = hh * fac;
+        prev_rej = false;
+      }
+      side = ts < t;
+    } else {
+      const double fac = fmax(0.2, 0.9 / root_k<Tab::QEMB + 1>(err));
+      h = hh * fac;
+      prev_rej = true;
+    }
+  }
+
+  // saves at the last mesh point (t_s = t1): a side step of size zero
+  if (status == LANE_OK) {
+    for (; next_save < ns; ++next_save) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) ysv[((int64_t)next_save * D + c) * n + tr] = y[c];
+      if constexpr (MODE != MODE_SOLVE) {
+        R.save_idx[(int64_t)next_save * n + tr] = S;
+        R.save_dt[(int64_t)next_save * n + tr] = save_time_at(a.ivp.st, next_save) - t;
+      }
+    }
+  } else {
+    for (; next_save < ns; ++next_save) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) ysv[((int64_t)next_save * D + c) * n + tr] = T(NAN);
+      if constexpr (MODE != MODE_SOLVE) {
+        R.save_idx[(int64_t)next_save * n + tr] = -1;
+        R.save_dt[(int64_t)next_save * n + tr] = NAN;
+      }
+    }
+  }
+  if constexpr (MODE != MODE_SOLVE) {
+    R.steps[tr] = S;
+    R.n_trial[tr] = trials;
+    R.last_page[tr] = page;
+    if (page < 0) R.first_page[tr] = -1;
+    R.status[tr] = status;
+#pragma unroll
+    for (int c = 0; c < D; ++c) ((T*)R.y_final)[c * n + tr] = y[c];
+  }
+  if (a.lane_status) a.lane_status[tr] = status;
+}
+
+// ------------------------------------------------------------ reverse sweep --
+// Loss cotangent at one save state v, accumulating the lane's loss.
+template <class T, int D>
+__device__ __forceinline__ void save_cotangent(const AdjArgs& a, int s,
+                                               int64_t tr, const T* v, T two_scale,
+                                               T* w, double& loss) {
+  const int64_t n = a.ivp.n;
+  const T* data = (const T*)a.loss_data;
+  if (a.loss_kind == LOSS_SUMSQ) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      w[c] = two_scale * v[c];
+      loss = fmaT((double)v[c], (double)v[c], loss);
+    }
+  } else if (a.loss_kind == LOSS_MSE_TARGET) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const T r = v[c] - data[((int64_t)s * D + c) * n + tr];
+      w[c] = two_scale * r;
+      loss = fmaT((double)r, (double)r, loss);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < D; ++c) w[c] = data[((int64_t)s * D + c) * n + tr];
+  }
+}
+
+template <class Sys, class Tab, class T>
+__global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
+  constexpr int D = Sys::D, NP = Sys::NP, K = PAGE_STEPS, SU = Tab::SU;
+  constexpr int RB = TapeRec<T, D>::BYTES;
+  const int64_t n = a.ivp.n;
+  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tr >= n) return;
+  const RecView& R = a.rec;
+  T* gpo = (T*)a.grad_p;
+  T* gyo = (T*)a.grad_y0;
+
+  if (R.status[tr] != LANE_OK) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) gpo[c * n + tr] = T(NAN);
+    if (gyo) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) gyo[c * n + tr] = T(NAN);
+    }
+    if (a.loss_out) a.loss_out[tr] = NAN;
+    return;
+  }
+
+  T p[NP];
+  load_params<T, NP>(a.ivp, tr, p);
+  const int32_t S = R.steps[tr];
+  int32_t page = R.last_page[tr];
+  T ycur[D], lam[D], gp[NP];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    ycur[c] = ((const T*)R.y_final)[c * n + tr];
+    lam[c] = T(0);
+  }
+#pragma unroll
+  for (int c = 0; c < NP; ++c) gp[c] = T(0);
+  double loss = 0.0;
+  const T two_scale = T(2.0 * a.scale);
+
+  int s = R.n_save - 1;
+  int32_t sidx = R.save_idx[(int64_t)s * n + tr];
+  double sdt = R.save_dt[(int64_t)s * n + tr];
+  int32_t i = S;
+  int slot = S > 0 ? (S - 1) % K : 0;
+
+  while (true) {
+    // save states that coincide with the current mesh point
+    while (s >= 0 && sidx == i && sdt == 0.0) {
+      T w[D];
+      save_cotangent<T, D>(a, s, tr, ycur, two_scale, w, loss);
+#pragma unroll
+      for (int c = 0; c < D; ++c) lam[c] = lam[c] + w[c];
+      --s;
+      if (s >= 0) {
+        sidx = R.save_idx[(int64_t)s * n + tr];
+        sdt = R.save_dt[(int64_t)s * n + tr];
+      }
+    }
+    const bool side = (s >= 0 && sidx == i);
+    if (!side && i == 0) break;
+
+    T yb[D];
+    double hh;
+    if (side) {
+      hh = sdt;
+#pragma unroll
+      for (int c = 0; c < D; ++c) yb[c] = ycur[c];
+    } else {
+      const char* rp = R.pages + (int64_t)page * R.page_bytes + slot * RB;
+      hh = *(const double*)rp;
+#pragma unroll
+      for (int c = 0; c < D; ++c) yb[c] = ((const T*)(rp + 8))[c];
+    }
+
+    // recompute the stages of this step
+    T k[SU][D], Y[SU][D];
+    Sys::rhs(yb, p, k[0]);
+    stages<Sys, Tab, T, SU>(yb, p, T(hh), k, Y);
+    T w[D];
+    if (side) {
+      T ys[D];
+      update<Tab, T, D, SU>(yb, T(hh), k, ys);
+      save_cotangent<T, D>(a, s, tr, ys, two_scale, w, loss);
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) w[c] = lam[c];
+    }
+
+    // reverse through the stages: kbar_j = h (b_j w + sum_{l>j} a_lj Ybar_l)
+    T Yb[SU][D], lin[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) lin[c] = w[c];
+#pragma unroll
+    for (int j = SU - 1; j >= 0; --j) {
+      T kb[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        T acc = T(0);
+        bool first = true;
+        if (Tab::B[j] != 0.0) {
+          acc = T(Tab::B[j]) * w[c];
+          first = false;
+        }
+#pragma unroll
+        for (int l = j + 1; l < SU; ++l) {
+          if (Tab::A[l][j] != 0.0) {
+            if (first) {
+              acc = T(Tab::A[l][j]) * Yb[l][c];
+              first = false;
+            } else {
+              acc = fmaT(T(Tab::A[l][j]), Yb[l][c], acc);
+            }
+          }
+        }
+        kb[c] = T(hh) * acc;
+      }
+      Sys::vjp(Y[j], p, kb, Yb[j], gp);
+#pragma unroll
+      for (int c = 0; c < D; ++c) lin[c] = lin[c] + Yb[j][c];
+    }
+
+    if (side) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) lam[c] = lam[c] + lin[c];
+      --s;
+      if (s >= 0) {
+        sidx = R.save_idx[(int64_t)s * n + tr];
+        sdt = R.save_dt[(int64_t)s * n + tr];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        lam[c] = lin[c];
+        ycur[c] = yb[c];
+      }
+      --i;
+      if (--slot < 0 && i > 0) {
+        page = R.links[2 * (int64_t)page];
+        slot = K - 1;
+      }
+    }
+  }
+
+  if (a.loss_kind != LOSS_COTANGENT) loss = a.scale * loss;
+#pragma unroll
+  for (int c = 0; c < NP; ++c) gpo[c * n + tr] = gp[c];
+  if (gyo) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) gyo[c * n + tr] = lam[c];
+  }
+  if (a.loss_out) a.loss_out[tr] = (a.loss_kind == LOSS_COTANGENT) ? 0.0 : loss;
+}
+
+}  // namespace ens

@@ -1,0 +1,104 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2609_02876_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ensode.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(ensemble_\w+)\(", src, re.M)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(A.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    if not os.path.exists(A.LIB_PATH):
+        pytest.skip("libensode.so not built")
+    lib = C.CDLL(A.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _lib():
+    if not os.path.exists(A.LIB_PATH):
+        pytest.skip("libensode.so not built")
+    return A.load(build_if_missing=False)
+
+
+def _prob(**kw):
+    d = dict(system=A.SYS_LORENZ, method=A.TSIT5, dtype=A.F64, dim=3, nparams=3, params_shared=0)
+    d.update(kw)
+    return A.Problem(**d)
+
+
+def _ivp(**kw):
+    st = (C.c_double * 2)(0.5, 1.0)
+    d = dict(n=1024, y0=None, params=None, t0=0.0, t1=1.0, rtol=1e-6, atol=1e-8, h0=0.0,
+             max_steps=0, n_save=2, save_times=C.cast(st, C.POINTER(C.c_double)))
+    d.update(kw)
+    v = A.Ivp(**d)
+    v._keep = st
+    return v
+
+
+def test_record_bytes_plan():
+    lib = _lib()
+    out = C.c_size_t()
+    assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(_ivp()), 64, 0, C.byref(out)) == 0
+    # 1024 trajectories x 4 pages of 16 steps x 32 bytes, plus links and the fixed part
+    assert out.value > 1024 * 4 * 512
+    small = out.value
+    assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(_ivp()), 640, 0, C.byref(out)) == 0
+    assert out.value > 9 * small
+
+
+@pytest.mark.parametrize("prob,ivp,code", [
+    (dict(system=99), {}, A.ENS_EUNSUPPORTED),
+    (dict(dim=2), {}, A.ENS_EINVAL),
+    (dict(method=7), {}, A.ENS_EUNSUPPORTED),
+    (dict(dtype=5), {}, A.ENS_EUNSUPPORTED),
+    ({}, dict(n=0), A.ENS_EINVAL),
+    ({}, dict(t1=0.0), A.ENS_EINVAL),
+    ({}, dict(rtol=-1.0), A.ENS_EINVAL),
+    ({}, dict(rtol=0.0, atol=0.0), A.ENS_EINVAL),
+    ({}, dict(n_save=65), A.ENS_EINVAL),
+])
+def test_validation_errors(prob, ivp, code):
+    lib = _lib()
+    out = C.c_size_t()
+    rc = lib.ensemble_record_bytes(C.byref(_prob(**prob)), C.byref(_ivp(**ivp)), 64, 0, C.byref(out))
+    assert rc == code
+    assert len(lib.ensemble_last_error()) > 0
+
+
+def test_bad_save_times_rejected():
+    lib = _lib()
+    st = (C.c_double * 2)(0.7, 0.2)
+    v = _ivp(save_times=C.cast(st, C.POINTER(C.c_double)))
+    out = C.c_size_t()
+    assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(v), 64, 0, C.byref(out)) == A.ENS_EINVAL
+    assert b"nondecreasing" in lib.ensemble_last_error()
+    st2 = (C.c_double * 2)(0.5, 1.5)
+    v = _ivp(save_times=C.cast(st2, C.POINTER(C.c_double)))
+    assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(v), 64, 0, C.byref(out)) == A.ENS_EINVAL
+
+
+def test_null_pointers_rejected_before_launch():
+    lib = _lib()
+    rec = A.Record()
+    assert lib.ensemble_solve(None, None, None, None, None) == A.ENS_EINVAL
+    # y0 / params NULL: refused by validation, no device call is made
+    tc = A.TapeCfg(None, 0, 0)
+    assert lib.ensemble_record(C.byref(_prob()), C.byref(_ivp()), C.byref(tc), C.byref(rec),
+                               None, None, None) == A.ENS_EINVAL
+    assert lib.ensemble_adjoint(C.byref(_prob()), C.byref(_ivp()), None, None, None, None, None,
+                                None) == A.ENS_EINVAL
