@@ -1,0 +1,187 @@
+"""Benchmark: trajectory-gradients per second (record + reverse sweep).
+
+Default workload: 2^20 Lorenz trajectories (sigma ~ U[9,11], rho ~ U[27,29],
+beta ~ U[2.5,3], y0 = (1,0,0)) on t in [0, 10], Tsit5, FP64, rtol 1e-6,
+atol 1e-8, loss = sum of squared states at 20 evenly spaced save times,
+gradient with respect to the three parameters of every trajectory.
+
+One step = ensemble_record + ensemble_adjoint over the whole ensemble, inputs
+already resident in device memory.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lorenz_2p20_t10")
+    ap.add_argument("--n", type=int, default=None, help="override the trajectory count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON with measured HBM bytes per launch of the dominant kernel")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, y0, p, st, target_s, cap):
+    """The FP64 CPU oracle (record + adjoint) on a bounded sample of the workload."""
+    import numpy as np
+    import oracle as O
+    so = {"lorenz": O.LORENZ, "vdp": O.VDP}[cfg["system"]]
+    mo = {"tsit5": O.TSIT5, "vern7": O.VERN7}[cfg["method"]]
+    save = list(st)
+
+    def run(m):
+        t = time.perf_counter()
+        rec = O.record(so, mo, y0[:m], p[:m], cfg["t0"], cfg["t1"], cfg["rtol"], cfg["atol"],
+                       save_t=save, cap=cap)
+        O.adjoint(so, mo, y0[:m], p[:m], rec)
+        return time.perf_counter() - t
+
+    m = 2048
+    dt = run(m)
+    m2 = int(min(len(y0), max(m, m * target_s / max(dt, 1e-3))))
+    m2 = max(m, (m2 // 64) * 64)
+    dt2 = run(m2)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": m2 / dt2, "unit": "trajectory-gradients/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {m2} trajectories of the workload, record + adjoint, {dt2:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ensemble "
+              "shards by trajectory with no exchange, so more GPUs are not exercised here.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2609_02876_amd import binding as B
+    from paper_2609_02876_amd import flops
+    from paper_2609_02876_amd import workloads as W
+
+    cfg, y0, p, st = W.make(args.workload, n=args.n)
+    n = cfg["n"]
+    save = list(st) if cfg["n_save"] else None
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=torch.float64, device=dev)
+    p_d = torch.tensor(np.ascontiguousarray(p.T), dtype=torch.float64, device=dev)
+    args_common = (cfg["system"], cfg["method"], y0_d, p_d, cfg["t0"], cfg["t1"], cfg["rtol"],
+                   cfg["atol"])
+
+    # pool plan from a pilot record of a sample of the ensemble
+    m = min(n, 8192)
+    pilot = B.ensemble_record(cfg["system"], cfg["method"], y0_d[:, :m].contiguous(),
+                              p_d[:, :m].contiguous(), cfg["t0"], cfg["t1"], cfg["rtol"],
+                              cfg["atol"], save_times=save, steps_hint=4096)
+    s_pilot = pilot.steps().double()
+    cap_cpu = int(s_pilot.max().item() * 1.5) + 64
+    hint = B.steps_hint_for(float(s_pilot.mean().item()), margin=1.12)
+    del pilot
+    nbytes = B.ensemble_record_bytes(cfg["system"], cfg["method"], n, cfg["t0"], cfg["t1"], hint,
+                                     cfg["n_save"])
+    pool = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        if events:
+            events[0].record(stream)
+        rec = B.ensemble_record(*args_common, save_times=save, pool=pool, steps_per_traj=hint)
+        if events:
+            events[1].record(stream)
+        gp, gy, ll = B.ensemble_adjoint(rec, want_y0=True, want_loss=True)
+        if events:
+            events[2].record(stream)
+        return rec, gp, gy, ll
+
+    for _ in range(args.warmup):
+        rec, gp, gy, ll = step()
+    torch.cuda.synchronize()
+    if args.warmup:
+        bad = int((rec.status != 0).sum().item())
+        if bad:
+            raise RuntimeError(f"{bad} trajectories did not finish (status != OK)")
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rec, gp, gy, ll = step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+
+    bad = int((rec.status != 0).sum().item())
+    if bad:
+        raise RuntimeError(f"{bad} trajectories did not finish (status != OK)")
+    stats = B.ensemble_record_stats(rec)
+    n_saves = n * (cfg["n_save"] or 1)
+    zero_sides = n_saves - stats["side_steps"]
+    f_rec = flops.record_flops(cfg["method"], cfg["system"], stats["trials"],
+                               stats["steps_accepted"], stats["side_steps"])
+    f_adj = flops.adjoint_flops(cfg["method"], cfg["system"], stats["steps_accepted"],
+                                stats["side_steps"], zero_sides)
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * args.steps / wall
+
+    dominant = "adjoint" if adj_ms >= rec_ms else "record"
+    f_dom, ms_dom = (f_adj, adj_ms) if dominant == "adjoint" else (f_rec, rec_ms)
+    achieved = f_dom / (ms_dom * 1e-3) / 1e12
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        tr = json.load(open(args.traffic))
+        traffic = tr.get(dominant)
+    out = {
+        "metric": "trajectory-gradients/s (fwd+adjoint) at 2^20 Lorenz, rtol 1e-6",
+        "value": value,
+        "unit": "trajectory-gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "system": cfg["system"], "method": cfg["method"],
+                   "n": n, "t_span": [cfg["t0"], cfg["t1"]], "rtol": cfg["rtol"],
+                   "atol": cfg["atol"], "n_save": cfg["n_save"],
+                   "loss": "sum of squared save states", "gradient": "per-trajectory params"},
+        "roofline": {"bound": "alu", "kernel": f"erk_{dominant}_kernel (Lorenz, Tsit5, f64)",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},
+        "kernels_ms": {"record": rec_ms, "adjoint": adj_ms},
+        "algorithmic_flop": {"record": f_rec, "adjoint": f_adj,
+                             "total_tflops": (f_rec + f_adj) / (ms_per_step * 1e-3) / 1e12},
+        "record_stats": {"accepted_per_traj": stats["steps_accepted"] / n,
+                         "trials_per_traj": stats["trials"] / n,
+                         "side_steps": stats["side_steps"], "overflow_pages_used": stats["overflow_pages_used"],
+                         "pool_gb": nbytes / 1e9},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, args.cpu_seconds, cap_cpu)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

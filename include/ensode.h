@@ -110,11 +110,15 @@ typedef struct {
 
 /* ---- records ------------------------------------------------------------ */
 /* Pool configuration.  ckpt_every must be 0 (a full tape: the state before
- * every accepted step is kept). */
+ * every accepted step is kept).  Each trajectory reserves steps_per_traj
+ * taped steps up front (rounded up to whole pages); steps beyond that come
+ * from a shared overflow area of the pool, handed out on demand.
+ * steps_per_traj = 0 reserves 7/8 of the pool evenly. */
 typedef struct {
   void* pool;        /* device, 256-byte aligned */
   size_t pool_bytes;
   int32_t ckpt_every;
+  int32_t steps_per_traj;
 } ens_tape_cfg;
 
 /* A record: plain data describing what ensemble_record wrote into a pool.
@@ -125,28 +129,30 @@ typedef struct {
   int32_t n_save;
   int32_t page_steps;   /* accepted steps per tape page */
   int32_t rec_bytes;    /* bytes per taped step: h (double) + state */
-  int64_t n_pages;      /* pages the pool holds */
+  int64_t n_pages;      /* pages the pool holds (reserved + overflow) */
   int64_t page_bytes;
+  int32_t static_pages; /* pages reserved per trajectory */
+  int32_t pad_;
   double t0, t1;
   void* pool;
   size_t pool_bytes;
   /* device pointers into the pool */
   int32_t* steps;       /* [n] accepted steps S */
   int32_t* n_trial;     /* [n] trials (accepted + rejected) */
-  int32_t* first_page;  /* [n] */
-  int32_t* last_page;   /* [n] */
+  int32_t* first_page;  /* [n] first overflow page, -1 if none */
+  int32_t* last_page;   /* [n] page holding the last taped step */
   int32_t* status;      /* [n] copy of lane_status */
   int32_t* save_idx;    /* [n_save][n] mesh index of each save's base state */
   double* save_dt;      /* [n_save][n] side-step size t_s - t_base */
   double* save_times;   /* [max(n_save,1)] */
   void* y_final;        /* [dim][n] y_S */
-  int32_t* links;       /* [n_pages][2] previous / next page of the trajectory */
+  int32_t* links;       /* [overflow pages][2] previous / next page */
   unsigned long long* counters; /* [8] page counter and step totals */
   void* pages;          /* [n_pages][page_bytes] */
 } ens_record;
 
 typedef struct {
-  unsigned long long pages_used;
+  unsigned long long overflow_pages_used;
   unsigned long long steps_accepted; /* summed over trajectories */
   unsigned long long trials;         /* accepted + rejected, summed */
   unsigned long long side_steps;     /* save-time steps with nonzero size */
@@ -176,9 +182,9 @@ typedef struct {
 int ensemble_solve(const ens_problem* prob, const ens_ivp* ivp, void* y_out,
                    int32_t* lane_status, void* stream);
 
-/* Pool bytes for a record of `ivp` if no trajectory accepts more than
- * steps_hint steps (an upper plan: pages are handed out on demand, so a
- * trajectory may exceed the hint while others stay below it). */
+/* Pool bytes for a record of `ivp` that reserves steps_hint taped steps per
+ * trajectory plus an overflow area of 1/8 of that for trajectories that
+ * need more; pass steps_hint as ens_tape_cfg.steps_per_traj. */
 int ensemble_record_bytes(const ens_problem* prob, const ens_ivp* ivp,
                           int64_t steps_hint, int32_t ckpt_every,
                           size_t* bytes);

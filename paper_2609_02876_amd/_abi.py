@@ -37,7 +37,8 @@ class Ivp(C.Structure):
 
 
 class TapeCfg(C.Structure):
-    _fields_ = [("pool", C.c_void_p), ("pool_bytes", C.c_size_t), ("ckpt_every", C.c_int32)]
+    _fields_ = [("pool", C.c_void_p), ("pool_bytes", C.c_size_t), ("ckpt_every", C.c_int32),
+                ("steps_per_traj", C.c_int32)]
 
 
 class Record(C.Structure):
@@ -46,6 +47,7 @@ class Record(C.Structure):
                 ("dim", C.c_int32), ("nparams", C.c_int32), ("params_shared", C.c_int32),
                 ("n_save", C.c_int32), ("page_steps", C.c_int32), ("rec_bytes", C.c_int32),
                 ("n_pages", C.c_int64), ("page_bytes", C.c_int64),
+                ("static_pages", C.c_int32), ("pad_", C.c_int32),
                 ("t0", C.c_double), ("t1", C.c_double),
                 ("pool", C.c_void_p), ("pool_bytes", C.c_size_t),
                 ("steps", C.c_void_p), ("n_trial", C.c_void_p), ("first_page", C.c_void_p),
@@ -55,7 +57,7 @@ class Record(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("pages_used", C.c_ulonglong), ("steps_accepted", C.c_ulonglong),
+    _fields_ = [("overflow_pages_used", C.c_ulonglong), ("steps_accepted", C.c_ulonglong),
                 ("trials", C.c_ulonglong), ("side_steps", C.c_ulonglong)]
 
 

@@ -123,22 +123,32 @@ def ensemble_solve(system, method, y0, params, t0, t1, rtol, atol, save_times=No
     return y_out, status
 
 
-def _pool_for(spec, steps_hint, pool):
+def _pool_for(spec, steps_hint, pool, steps_per_traj):
+    """(pool tensor, tape config): a given pool, or one planned for steps_hint."""
     if pool is not None:
         _require_gpu(pool)
-        return pool
-    nbytes = ensemble_record_bytes(spec.system, spec.method, spec.n, spec.ivp.t0, spec.ivp.t1,
-                                   steps_hint, spec.ivp.n_save, spec.dtype)
-    return torch.empty(nbytes, dtype=torch.uint8, device=spec.y0.device)
+        if pool.dtype != torch.uint8:
+            raise ValueError("pool must be a uint8 tensor")
+        spt = int(steps_per_traj or 0)
+    else:
+        nbytes = ensemble_record_bytes(spec.system, spec.method, spec.n, spec.ivp.t0,
+                                       spec.ivp.t1, steps_hint, spec.ivp.n_save, spec.dtype)
+        pool = torch.empty(nbytes, dtype=torch.uint8, device=spec.y0.device)
+        spt = int(steps_hint)
+    return pool, A.TapeCfg(pool.data_ptr(), pool.numel(), 0, spt)
 
 
 def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
-                    max_steps=0, params_shared=False, steps_hint=512, pool=None):
-    """Adaptive record.  Returns a RecordHandle (.y_save, .status, .pool)."""
+                    max_steps=0, params_shared=False, steps_hint=512, pool=None,
+                    steps_per_traj=None):
+    """Adaptive record.  Returns a RecordHandle (.y_save, .status, .pool).
+
+    Without a pool, one is planned that reserves steps_hint taped steps per
+    trajectory (plus overflow).  With a pool, steps_per_traj sets the
+    per-trajectory reservation (None: 7/8 of the pool evenly)."""
     spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
                  params_shared)
-    pool = _pool_for(spec, steps_hint, pool)
-    tc = A.TapeCfg(pool.data_ptr(), pool.numel(), 0)
+    pool, tc = _pool_for(spec, steps_hint, pool, steps_per_traj)
     rec = A.Record()
     y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
     status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
@@ -148,7 +158,7 @@ def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=N
 
 
 def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_times=None,
-                         params_shared=False, pool=None):
+                         params_shared=False, pool=None, steps_per_traj=None):
     """Record on a given mesh h [cap, n] (float64), steps [n] (int32)."""
     spec = _Spec(system, method, y0, params, t0, t1, 1e-6, 1e-6, save_times, 0.0, 0,
                  params_shared)
@@ -158,8 +168,7 @@ def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_time
     if h.dim() != 2 or h.shape[1] != spec.n or steps.shape != (spec.n,):
         raise ValueError("h must be [cap, n] and steps [n]")
     cap = h.shape[0]
-    pool = _pool_for(spec, cap, pool)
-    tc = A.TapeCfg(pool.data_ptr(), pool.numel(), 0)
+    pool, tc = _pool_for(spec, cap, pool, steps_per_traj)
     rec = A.Record()
     y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
     status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
@@ -208,7 +217,7 @@ def ensemble_adjoint(handle, loss="sumsq", data=None, scale=1.0, want_y0=True,
 def ensemble_record_stats(handle):
     st = A.Stats()
     A.check(A.load().ensemble_record_stats(C.byref(handle.rec), C.byref(st), _stream()))
-    return dict(pages_used=st.pages_used, steps_accepted=st.steps_accepted, trials=st.trials,
+    return dict(overflow_pages_used=st.overflow_pages_used, steps_accepted=st.steps_accepted, trials=st.trials,
                 side_steps=st.side_steps, n_pages=handle.rec.n_pages)
 
 

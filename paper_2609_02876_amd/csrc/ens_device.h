@@ -64,7 +64,9 @@ __device__ __forceinline__ uint64_t wave_bump(unsigned long long* counter,
 struct RecView {
   int64_t n;
   int32_t n_save;        // effective, >= 1
-  int64_t n_pages;
+  int64_t n_pages;       // reserved + overflow
+  int64_t n_static;      // n * static_pages: ids below this are reserved pages
+  int32_t static_pages;  // reserved pages per trajectory
   int64_t page_bytes;
   int32_t* steps;
   int32_t* n_trial;
@@ -75,9 +77,24 @@ struct RecView {
   double* save_dt;       // [n_save][n]
   const double* save_times;
   void* y_final;         // [D][n]
-  int32_t* links;        // [n_pages][2]
+  int32_t* links;        // [overflow pages][2]: previous, next page id
   unsigned long long* counters;
   char* pages;
 };
+
+// Page holding the taped step before the first step of `page` (only called
+// when such a step exists): reserved pages of a trajectory are consecutive,
+// overflow pages are linked.
+__device__ __forceinline__ int32_t prev_page(const RecView& R, int32_t page) {
+  return page < R.n_static ? page - 1
+                           : R.links[2 * ((int64_t)page - R.n_static)];
+}
+
+__device__ __forceinline__ int32_t next_page(const RecView& R, int64_t tr,
+                                             int32_t page) {
+  if (page >= R.n_static) return R.links[2 * ((int64_t)page - R.n_static) + 1];
+  const int32_t k = page - (int32_t)(tr * R.static_pages);
+  return k + 1 < R.static_pages ? page + 1 : R.first_page[tr];
+}
 
 }  // namespace ens

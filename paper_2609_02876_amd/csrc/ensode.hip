@@ -131,15 +131,33 @@ Layout layout(int64_t n, int n_save_eff, int d, int dtype) {
   return L;
 }
 
-int64_t pages_in(const Layout& L, size_t pool_bytes) {
-  if (pool_bytes < L.fixed + 512) return 0;
-  // links (8 B per page) then 256-aligned pages
-  size_t avail = pool_bytes - L.fixed - 256;
-  return (int64_t)(avail / (L.page_bytes + 8));
+// Split of a pool into reserved pages (static_pages per trajectory) and an
+// overflow area whose pages carry 8 bytes of links each.
+struct PageSplit {
+  int64_t static_pages, n_static, n_over;
+};
+
+bool split_pages(const Layout& L, int64_t n, size_t pool_bytes,
+                 int32_t steps_per_traj, PageSplit* ps) {
+  if (pool_bytes < L.fixed + 512) return false;
+  const size_t avail = pool_bytes - L.fixed - 256;
+  int64_t sp;
+  if (steps_per_traj > 0) {
+    sp = (steps_per_traj + PAGE_STEPS - 1) / PAGE_STEPS;
+  } else {
+    sp = (int64_t)((avail / 8 * 7) / ((size_t)n * L.page_bytes));
+  }
+  const size_t static_bytes = (size_t)n * (size_t)sp * L.page_bytes;
+  if (static_bytes > avail) return false;
+  ps->static_pages = sp;
+  ps->n_static = n * sp;
+  ps->n_over = (int64_t)((avail - static_bytes) / (L.page_bytes + 8));
+  return true;
 }
 
 void fill_record(ens_record* r, const ens_problem* p, const ens_ivp* v,
-                 const ens_tape_cfg* tc, const Layout& L, int64_t n_pages) {
+                 const ens_tape_cfg* tc, const Layout& L, const PageSplit& ps) {
+  const int64_t n_pages = ps.n_static + ps.n_over;
   memset(r, 0, sizeof *r);
   char* base = (char*)tc->pool;
   r->n = v->n;
@@ -154,6 +172,7 @@ void fill_record(ens_record* r, const ens_problem* p, const ens_ivp* v,
   r->rec_bytes = (int32_t)rec_bytes(p->dtype, p->dim);
   r->n_pages = n_pages;
   r->page_bytes = (int64_t)L.page_bytes;
+  r->static_pages = (int32_t)ps.static_pages;
   r->t0 = v->t0;
   r->t1 = v->t1;
   r->pool = tc->pool;
@@ -169,7 +188,7 @@ void fill_record(ens_record* r, const ens_problem* p, const ens_ivp* v,
   r->save_dt = (double*)(base + L.save_dt);
   r->y_final = base + L.y_final;
   r->links = (int32_t*)(base + L.links);
-  r->pages = base + align256(L.links + (size_t)n_pages * 8);
+  r->pages = base + align256(L.links + (size_t)ps.n_over * 8);
 }
 
 RecView view_of(const ens_record* r) {
@@ -177,6 +196,8 @@ RecView view_of(const ens_record* r) {
   v.n = r->n;
   v.n_save = r->n_save;
   v.n_pages = r->n_pages;
+  v.static_pages = r->static_pages;
+  v.n_static = r->n * (int64_t)r->static_pages;
   v.page_bytes = r->page_bytes;
   v.steps = r->steps;
   v.n_trial = r->n_trial;
@@ -307,12 +328,16 @@ int record_common(const ens_problem* p, const ens_ivp* v,
   if (!out || !y_save) return fail(ENS_EINVAL, "out and y_save are required");
   const int nse = v->n_save > 0 ? v->n_save : 1;
   Layout L = layout(v->n, nse, si.d, p->dtype);
-  const int64_t n_pages = pages_in(L, tc->pool_bytes);
-  if (n_pages <= 0)
-    return fail(ENS_ENOSPACE, "pool of %zu bytes is below the fixed part (%zu)",
+  if (tc->steps_per_traj < 0) return fail(ENS_EINVAL, "steps_per_traj < 0");
+  PageSplit ps;
+  if (!split_pages(L, v->n, tc->pool_bytes, tc->steps_per_traj, &ps))
+    return fail(ENS_ENOSPACE,
+                "pool of %zu bytes is below the fixed part (%zu) plus the "
+                "reserved pages",
                 tc->pool_bytes, L.fixed + 512);
-  if (n_pages > INT32_MAX) return fail(ENS_EINVAL, "pool too large");
-  fill_record(out, p, v, tc, L, n_pages);
+  if (ps.n_static + ps.n_over > INT32_MAX)
+    return fail(ENS_EINVAL, "pool holds more than 2^31 pages");
+  fill_record(out, p, v, tc, L, ps);
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(64), 0, st, out->counters,
                      out->save_times, save_times_of(v));
@@ -337,10 +362,10 @@ __global__ void mesh_export_kernel(const RecView R, int64_t rec_b, double* h,
   if (tr >= n) return;
   const int32_t S = R.steps[tr];
   steps[tr] = S;
-  int32_t page = R.first_page[tr];
+  int32_t page = R.static_pages > 0 ? (int32_t)(tr * R.static_pages) : R.first_page[tr];
   for (int32_t i = 0; i < S && i < cap; ++i) {
     const int slot = i % PAGE_STEPS;
-    if (i > 0 && slot == 0) page = R.links[2 * (int64_t)page + 1];
+    if (i > 0 && slot == 0) page = next_page(R, tr, page);
     h[(int64_t)i * n + tr] = *(const double*)(R.pages + (int64_t)page * R.page_bytes +
                                               slot * rec_b);
   }
@@ -418,8 +443,10 @@ int ensemble_record_bytes(const ens_problem* p, const ens_ivp* v,
   const int nse = v->n_save > 0 ? v->n_save : 1;
   Layout L = layout(v->n, nse, si.d, p->dtype);
   const int64_t pages_per = (steps_hint + PAGE_STEPS - 1) / PAGE_STEPS;
-  const int64_t n_pages = pages_per * v->n;
-  *bytes = L.fixed + 512 + (size_t)n_pages * (L.page_bytes + 8);
+  const int64_t n_static = pages_per * v->n;
+  const int64_t n_over = n_static / 8 + 64;
+  *bytes = L.fixed + 512 + (size_t)n_static * L.page_bytes +
+           (size_t)n_over * (L.page_bytes + 8);
   return ENS_OK;
 }
 
@@ -501,8 +528,9 @@ int ensemble_record_stats(const ens_record* r, ens_stats* out, void* stream) {
                                 hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "stats");
-  out->pages_used = host[0] < (unsigned long long)r->n_pages ? host[0]
-                                                             : (unsigned long long)r->n_pages;
+  const unsigned long long n_over =
+      (unsigned long long)(r->n_pages - r->n * (int64_t)r->static_pages);
+  out->overflow_pages_used = (host[0] < n_over ? host[0] : n_over);  // overflow pages taken
   out->steps_accepted = host[4];
   out->trials = host[5];
   out->side_steps = host[6];

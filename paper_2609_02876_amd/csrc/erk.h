@@ -301,6 +301,7 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
     yp[c] = y[c];
     k1p[c] = k1[c];
   }
+  if constexpr (MODE != MODE_SOLVE) R.first_page[tr] = -1;
   double tp = t0;
   int next_save = 0;
   double ts = a.ivp.st.t[0];
@@ -378,20 +379,28 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
     if (MODE == MODE_FROZEN || err <= 1.0) {
       if constexpr (MODE != MODE_SOLVE) {
         const int slot = S % K;
+        const int kpage = S / K;
         const bool need = (slot == 0);
-        const uint64_t got = wave_bump(&R.counters[CNT_PAGES], need);
+        const bool over = need && (kpage >= R.static_pages);
+        const uint64_t got = wave_bump(&R.counters[CNT_PAGES], over);
         if (need) {
-          if (got >= (uint64_t)R.n_pages) {
-            status = LANE_NOSPACE;
-            break;
+          int32_t np_;
+          if (!over) {
+            np_ = (int32_t)(tr * R.static_pages + kpage);
+          } else {
+            if (got >= (uint64_t)(R.n_pages - R.n_static)) {
+              status = LANE_NOSPACE;
+              break;
+            }
+            np_ = (int32_t)(R.n_static + (int64_t)got);
+            const int64_t li = (int64_t)np_ - R.n_static;
+            R.links[2 * li] = page;
+            R.links[2 * li + 1] = -1;
+            if (page >= R.n_static)
+              R.links[2 * ((int64_t)page - R.n_static) + 1] = np_;
+            else
+              R.first_page[tr] = np_;
           }
-          const int32_t np_ = (int32_t)got;
-          R.links[2 * (int64_t)np_] = page;
-          R.links[2 * (int64_t)np_ + 1] = -1;
-          if (page >= 0)
-            R.links[2 * (int64_t)page + 1] = np_;
-          else
-            R.first_page[tr] = np_;
           page = np_;
           pg = R.pages + (int64_t)page * R.page_bytes;
         }
@@ -451,7 +460,6 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
     R.steps[tr] = S;
     R.n_trial[tr] = trials;
     R.last_page[tr] = page;
-    if (page < 0) R.first_page[tr] = -1;
     R.status[tr] = status;
 #pragma unroll
     for (int c = 0; c < D; ++c) ((T*)R.y_final)[c * n + tr] = y[c];
@@ -621,7 +629,7 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
       }
       --i;
       if (--slot < 0 && i > 0) {
-        page = R.links[2 * (int64_t)page];
+        page = prev_page(R, page);
         slot = K - 1;
       }
     }

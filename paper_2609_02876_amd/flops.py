@@ -1,0 +1,83 @@
+"""Algorithmic floating-point work of the explicit-RK record and reverse sweep.
+
+Counting rules: fma = 2; add, sub, mul, div, min, max = 1; sqrt and the
+controller's root = 1; abs, negation, selects and comparisons = 0.  Work the
+method needs is counted once (a first-same-as-last stage is not recounted;
+for a pair without that property the slope at the new state is counted once
+per accepted step); work a lane performs only because its wavefront is busy
+(masked lanes, rejected trials' unused side results) is not counted.
+
+Per-unit figures:
+  trial      one trial step of the record (stages, update, error estimate,
+             RMS norm, controller) -- rejected trials count (they are needed
+             to find the mesh)
+  accept     extra work per accepted step (the new first stage for pairs
+             without first-same-as-last)
+  side_fwd   one save-time step of nonzero size in the record
+  adj_step   one mesh step of the reverse sweep (recomputed stages, stage
+             cotangents, VJPs, adjoint update)
+  adj_side   one save-time step of nonzero size in the reverse sweep (adds
+             the forward update of the save state and the loss cotangent)
+  adj_zero   one save time on a mesh point in the reverse sweep
+"""
+
+# nonzero pattern (0-based column indices) of each stage row, b and the
+# error weights; these mirror the tableaux of the kernels.
+TABLEAUX = {
+    "tsit5": dict(S=7, SU=6, fsal=True,
+                  rows=[[], [0], [0, 1], [0, 1, 2], [0, 1, 2, 3], [0, 1, 2, 3, 4],
+                        [0, 1, 2, 3, 4, 5]],
+                  b=[0, 1, 2, 3, 4, 5], ew=[0, 1, 2, 3, 4, 5, 6]),
+    "vern7": dict(S=10, SU=9, fsal=False,
+                  rows=[[], [0], [0, 1], [0, 2], [0, 2, 3], [0, 2, 3, 4], [0, 2, 3, 4, 5],
+                        [0, 2, 3, 4, 5, 6], [0, 2, 3, 4, 5, 6, 7], [0, 2, 3, 4, 5, 6]],
+                  b=[0, 3, 4, 5, 6, 7, 8], ew=[0, 3, 4, 5, 6, 7, 8, 9]),
+}
+
+# (state dim, rhs flops, vjp flops)
+SYSTEMS = {
+    "lorenz": (3, 8, 20),
+    "vdp": (2, 5, 13),
+    "linear": (2, 6, 14),
+}
+
+
+def _combo(m):
+    """sum of m weighted terms then fma(h, acc, y): 2m - 1 + 2."""
+    return 2 * m + 1
+
+
+def per_unit(method, system):
+    t = TABLEAUX[method]
+    D, F, V = SYSTEMS[system]
+    S, SU = t["S"], t["SU"]
+    rows = t["rows"]
+    stages_all = sum(_combo(len(rows[i])) for i in range(1, S)) * D
+    stages_su = sum(_combo(len(rows[i])) for i in range(1, SU)) * D
+    update = _combo(len(t["b"])) * D
+    err = 2 * len(t["ew"]) * D + 3 * D + (3 * D + 1)
+    controller = 7
+    trial = stages_all + (S - 1) * F + (0 if t["fsal"] else update) + err + controller
+    accept = 0 if t["fsal"] else F
+    side_fwd = stages_su + (SU - 1) * F + update
+    # reverse: each stage j, terms = [b_j != 0] + #{l in (j, SU): a_lj != 0}
+    rev = 0
+    for j in range(SU):
+        terms = (1 if j in t["b"] else 0) + sum(1 for l in range(j + 1, SU) if j in rows[l])
+        rev += (2 * terms if terms else 1) * D
+    adj_step = F + stages_su + (SU - 1) * F + rev + SU * V + SU * D
+    cot = 3 * D  # sum of squares: w = 2 s v (mul), loss += v v (fma)
+    adj_side = adj_step + update + cot + D
+    adj_zero = cot + D
+    return dict(trial=trial, accept=accept, side_fwd=side_fwd, adj_step=adj_step,
+                adj_side=adj_side, adj_zero=adj_zero)
+
+
+def record_flops(method, system, trials, accepted, side_steps):
+    u = per_unit(method, system)
+    return u["trial"] * trials + u["accept"] * accepted + u["side_fwd"] * side_steps
+
+
+def adjoint_flops(method, system, accepted, side_steps, zero_sides):
+    u = per_unit(method, system)
+    return u["adj_step"] * accepted + u["adj_side"] * side_steps + u["adj_zero"] * zero_sides

@@ -213,9 +213,11 @@ def test_lane_failures_are_isolated():
     y0, p = _case("lorenz", n, seed=6)
     full = _gpu_record("lorenz", "tsit5", y0, p, 1.0, 1e-6, 1e-8, None, steps_hint=128)
     g_full = B.ensemble_adjoint(full)[0]
-    nbytes = B.ensemble_record_bytes("lorenz", "tsit5", n, 0.0, 1.0, 64) - 20 * (512 + 8)
+    # 3 reserved pages (48 steps) each and an overflow area for 3/8 of the
+    # lanes; every lane needs a 4th page (about 55 steps)
+    nbytes = B.ensemble_record_bytes("lorenz", "tsit5", n, 0.0, 1.0, 48)
     pool = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    hd = _gpu_record("lorenz", "tsit5", y0, p, 1.0, 1e-6, 1e-8, None, pool=pool)
+    hd = _gpu_record("lorenz", "tsit5", y0, p, 1.0, 1e-6, 1e-8, None, pool=pool, steps_per_traj=48)
     gp, gy, ll = B.ensemble_adjoint(hd)
     torch.cuda.synchronize()
     s = hd.status.cpu().numpy()
