@@ -45,8 +45,8 @@ def _load():
         I, L, D = C.c_int, C.c_int64, C.c_double
         lib.oracle_dims.argtypes = [I, C.POINTER(I), C.POINTER(I)]
         lib.oracle_erk_tableau.argtypes = [I, _d, _d, _d, _d, C.POINTER(I), C.POINTER(I)]
-        lib.oracle_root_k.argtypes = [D, I]
-        lib.oracle_root_k.restype = D
+        lib.oracle_root_inv.argtypes = [D, I]
+        lib.oracle_root_inv.restype = D
         lib.oracle_rhs.argtypes = [I, _d, _d, _d]
         lib.oracle_vjp.argtypes = [I, _d, _d, _d, _d, _d]
         lib.oracle_record.argtypes = [I, I, I, I, _d, _d, D, D, D, D, D, L, I, _d, L,
@@ -91,9 +91,9 @@ def erk_tableau(method):
                 ew=ew[:s].copy(), order=o.value, q_emb=q.value)
 
 
-def root_k(x, k):
-    """The controller's x^(1/k) (k = 5..8)."""
-    return _load().oracle_root_k(float(x), int(k))
+def root_inv(x, k):
+    """The controller's x^(-1/k) (k = 5..8)."""
+    return _load().oracle_root_inv(float(x), int(k))
 
 
 def rhs(system, y, p):

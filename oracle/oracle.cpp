@@ -331,41 +331,46 @@ static void erk_phi(const ERK& m, int sys, int d, const T* y, const P* p, T h,
 }
 
 // ------------------------------------------------------- controller power --
-// x^(1/k) for the step-size controller and the starting step, k = 5..8.
-// Built only from operations that are exactly or correctly rounded (frexp,
-// ldexp, +, *, /, fma) so that any implementation that follows the same
-// sequence obtains the same bits: x = m 2^e with m in [0.5, 1), e = k q + j,
-// a linear first guess for m^(1/k) scaled by 2^(j/k) 2^q, then four Newton
-// steps r <- ((k-1) r + x / r^(k-1)) / k.
-static const double TWO_POW_5[5] = {1.0, 1.148698354997035, 1.3195079107728942,
-                                    1.515716566510398, 1.7411011265922482};
-static const double TWO_POW_6[6] = {1.0, 1.122462048309373, 1.2599210498948732,
-                                    1.4142135623730951, 1.5874010519681996,
-                                    1.7817974362806785};
-static const double TWO_POW_7[7] = {1.0, 1.1040895136738123, 1.2190136542044754,
-                                    1.3459001926323562, 1.4859942891369484,
-                                    1.640670712015276, 1.8114473285278134};
-static const double TWO_POW_8[8] = {1.0, 1.0905077326652577, 1.189207115002721,
-                                    1.2968395546510096, 1.4142135623730951,
-                                    1.5422108254079407, 1.681792830507429,
-                                    1.8340080864093424};
+// x^(-1/k) for the step-size controller and the starting step, k = 5..8,
+// from operations that are exactly or correctly rounded (frexp, ldexp, +, *,
+// fma) so that any implementation following the same sequence obtains the
+// same bits.  x = m 2^e with m in [0.5, 1) and e = k q + j; a linear first
+// guess for m^(-1/k) is scaled by 2^(-j/k) 2^(-q), then four Newton steps
+// y <- y + (y / k) (1 - x y^k) on f(y) = y^(-k) - x.  Arguments below
+// 1e-300 are raised to it (the controller clamps the factor long before).
+static const double TWO_NEG_5[5] = {1.0, 0.8705505632961241, 0.757858283255199,
+                                    0.6597539553864471, 0.5743491774985175};
+static const double TWO_NEG_6[6] = {1.0, 0.8908987181403393, 0.7937005259840998,
+                                    0.7071067811865476, 0.6299605249474366,
+                                    0.5612310241546865};
+static const double TWO_NEG_7[7] = {1.0, 0.9057236642639067, 0.820335356007638,
+                                    0.7429971445684742, 0.6729500963161781,
+                                    0.6095068271022377, 0.5520447568369061};
+static const double TWO_NEG_8[8] = {1.0, 0.9170040432046712, 0.8408964152537145,
+                                    0.7711054127039704, 0.7071067811865476,
+                                    0.6484197773255048, 0.5946035575013605,
+                                    0.5452538663326288};
 
-static double root_k(double x, int k) {
-  if (!(x > 0.0) || std::isinf(x)) return x;  // 0, inf and NaN map to themselves
-  const double* c = k == 5 ? TWO_POW_5 : k == 6 ? TWO_POW_6 : k == 7 ? TWO_POW_7 : TWO_POW_8;
+static double root_inv(double x, int k) {
+  if (std::isnan(x) || x < 0.0) return NAN;
+  if (std::isinf(x)) return 0.0;
+  const double* c = k == 5 ? TWO_NEG_5 : k == 6 ? TWO_NEG_6 : k == 7 ? TWO_NEG_7 : TWO_NEG_8;
+  const double u = 2.0 * c[k - 1];  // 2^(1/k), exactly twice 2^(-(k-1)/k)
+  const double inv_k = 1.0 / (double)k;
+  x = std::fmax(x, 1e-300);
   int e;
   const double m = std::frexp(x, &e);
   const int q = e >= 0 ? e / k : -((-e + k - 1) / k);
   const int j = e - q * k;
-  const double lo = 0.5 * c[k - 1];  // 2^(-1/k)
-  const double g = fma(2.0 * (1.0 - lo), m - 0.5, lo);
-  double r = std::ldexp(c[j] * g, q);
+  const double g = fma(-2.0 * (u - 1.0), m - 0.5, u);
+  double y = std::ldexp(c[j] * g, -q);
   for (int it = 0; it < 4; ++it) {
-    double pw = r;
-    for (int i = 2; i < k; ++i) pw = pw * r;
-    r = fma((double)(k - 1), r, x / pw) / (double)k;
+    double pw = y;
+    for (int i = 1; i < k; ++i) pw = pw * y;
+    const double t = fma(-x, pw, 1.0);
+    y = fma(y * inv_k, t, y);
   }
-  return r;
+  return y;
 }
 
 // ----------------------------------------------------------------- record --
@@ -399,7 +404,7 @@ static double rms_norm(int d, const double* v, const double* sc) {
     r = v[c] / sc[c];
     ss = fma(r, r, ss);
   }
-  return std::sqrt(ss / (double)d);
+  return std::sqrt(ss * (1.0 / (double)d));
 }
 
 // Starting step: Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4, with
@@ -419,7 +424,7 @@ static double initial_step(const ERK& m, int sys, int d, const double* y0,
   double d2 = rms_norm(d, tmp, sc) / h0;
   double dm = std::fmax(d1, d2);
   double h1 = (dm <= 1e-15) ? std::fmax(1e-6, h0 * 1e-3)
-                            : root_k(0.01 / dm, m.order + 1);
+                            : root_inv(dm * 100.0, m.order + 1);
   return std::fmin(std::fmin(100.0 * h0, h1), t1 - t0);
 }
 
@@ -485,6 +490,9 @@ static void record_lane(const RecordArgs& A, int lane) {
       sc[c] = fma(A.rtol, std::fmax(std::fabs(y[c]), std::fabs(ynew[c])), A.atol);
     }
     double err = rms_norm(d, e, sc);
+    // proposed factor 0.9 err^(-1/(q_emb+1)), bounded below by 0.2 and above
+    // by 10 (1 right after a rejection); err = 0 gives the upper bound
+    const double fac0 = 0.9 * root_inv(err, kroot);
 
     if (err <= 1.0) {
       if (S >= A.cap) { status = ST_NOSPACE; break; }
@@ -512,15 +520,11 @@ static void record_lane(const RecordArgs& A, int lane) {
       } else {
         rhs(sys, y, p, k1);
       }
-      double fac;
-      if (err == 0.0) fac = 10.0;
-      else fac = 0.9 / root_k(err, kroot);
-      fac = std::fmax(0.2, std::fmin(prev_rejected ? 1.0 : 10.0, fac));
+      const double fac = std::fmax(0.2, std::fmin(prev_rejected ? 1.0 : 10.0, fac0));
       h = h * fac;
       prev_rejected = false;
     } else {
-      double fac = std::fmax(0.2, 0.9 / root_k(err, kroot));
-      h = h * fac;
+      h = h * std::fmax(0.2, fac0);
       prev_rejected = true;
     }
   }
@@ -712,7 +716,7 @@ int oracle_erk_tableau(int method, double* c, double* a, double* b, double* ew,
   return m->s;
 }
 
-double oracle_root_k(double x, int k) { return root_k(x, k); }
+double oracle_root_inv(double x, int k) { return root_inv(x, k); }
 
 int oracle_rhs(int sys, const double* y, const double* p, double* f) {
   if (sys_dim(sys) < 0) return -1;

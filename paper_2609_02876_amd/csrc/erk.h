@@ -123,6 +123,104 @@ __device__ __forceinline__ void update(const T* y, T h, const T (&k)[NST][D],
   }
 }
 
+// First nonzero column of row i of A, of b and of the error weights
+// (compile-time).
+template <class Tab>
+__host__ __device__ constexpr int first_a(int i) {
+  for (int j = 0; j < i; ++j)
+    if (Tab::A[i][j] != 0.0) return j;
+  return -1;
+}
+template <class Tab>
+__host__ __device__ constexpr int first_b() {
+  for (int j = 0; j < Tab::S; ++j)
+    if (Tab::B[j] != 0.0) return j;
+  return -1;
+}
+template <class Tab>
+__host__ __device__ constexpr int first_ew() {
+  for (int j = 0; j < Tab::S; ++j)
+    if (Tab::EW[j] != 0.0) return j;
+  return -1;
+}
+
+// Stages 1..NST-1 of one explicit step from y with k_0 given, evaluated in
+// "push" order: as soon as a stage value k_l exists it is folded into every
+// later running sum (stage inputs, the update, the error estimate), so only
+// the running sums stay live.  Each sum still receives its terms in index
+// order, as acc = c_0 k_0, then fma(c_l, k_l, acc) -- the same operations as
+// forming each sum at once.  Outputs: Y[i] (if KEEP_Y), the last stage input
+// and value, the update y + h sum_j b_j k_j (if WANT_B) and the double-precision
+// sum sum_j ew_j k_j (if WANT_E).
+template <class Sys, class Tab, class T, int NST, bool KEEP_Y, bool WANT_B, bool WANT_E>
+__device__ __forceinline__ void step_push(const T* y, const T* k0, const T* p, T h,
+                                          T (&Y)[NST][Sys::D], T* ylast, T* klast,
+                                          T* yn, double* e) {
+  constexpr int D = Sys::D;
+  T Z[NST][D];
+  T Zb[D];
+  T kc[D], Yl[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    kc[c] = k0[c];
+    Yl[c] = y[c];
+    if (KEEP_Y) Y[0][c] = y[c];
+  }
+#pragma unroll
+  for (int l = 0; l < NST; ++l) {
+    if (l > 0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        Yl[c] = fmaT(h, Z[l][c], y[c]);
+        if (KEEP_Y) Y[l][c] = Yl[c];
+      }
+      Sys::rhs(Yl, p, kc);
+    }
+#pragma unroll
+    for (int j = l + 1; j < NST; ++j) {
+      if (Tab::A[j][l] != 0.0) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          if (first_a<Tab>(j) == l)
+            Z[j][c] = T(Tab::A[j][l]) * kc[c];
+          else
+            Z[j][c] = fmaT(T(Tab::A[j][l]), kc[c], Z[j][c]);
+        }
+      }
+    }
+    if (WANT_B && Tab::B[l] != 0.0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        if (first_b<Tab>() == l)
+          Zb[c] = T(Tab::B[l]) * kc[c];
+        else
+          Zb[c] = fmaT(T(Tab::B[l]), kc[c], Zb[c]);
+      }
+    }
+    if (WANT_E && Tab::EW[l] != 0.0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        if (first_ew<Tab>() == l)
+          e[c] = Tab::EW[l] * (double)kc[c];
+        else
+          e[c] = fmaT(Tab::EW[l], (double)kc[c], e[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    ylast[c] = Yl[c];
+    klast[c] = kc[c];
+    if (WANT_B) yn[c] = fmaT(h, Zb[c], y[c]);
+  }
+}
+
+// Norm of the error estimate e = h * esum against atol + rtol max(|y|, |ynew|).
+template <class T, int D>
+__device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double h,
+                                               const double* esum, double rtol,
+                                               double atol);
+
 // Scaled RMS norm sqrt(mean (v_c / sc_c)^2) with squares summed by fma.
 template <int D>
 __device__ __forceinline__ double rms(const double* v, const double* sc) {
@@ -133,7 +231,7 @@ __device__ __forceinline__ double rms(const double* v, const double* sc) {
     r = v[c] / sc[c];
     ss = fmaT(r, r, ss);
   }
-  return sqrt(ss / (double)D);
+  return sqrt(ss * (1.0 / (double)D));
 }
 
 // Error estimate e = h sum_j ew_j k_j (in double) and its norm against
@@ -164,59 +262,77 @@ __device__ __forceinline__ double err_norm(const T* y, const T* ynew, double h,
   return rms<D>(e, sc);
 }
 
-// x^(1/K) for the controller and the starting step (K = 5..8), from
+template <class T, int D>
+__device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double h,
+                                               const double* esum, double rtol,
+                                               double atol) {
+  double e[D], sc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    e[c] = h * esum[c];
+    sc[c] = fmaT(rtol, fmax(fabs((double)y[c]), fabs((double)ynew[c])), atol);
+  }
+  return rms<D>(e, sc);
+}
+
+// x^(-1/K) for the controller and the starting step (K = 5..8), from
 // operations that are exactly or correctly rounded on the device and on any
-// IEEE host: x = m 2^e (m in [0.5, 1)), e = K q + j, linear first guess for
-// m^(1/K) times 2^(j/K) 2^q, then four Newton steps
-// r <- ((K-1) r + x / r^(K-1)) / K.  Deterministic to the bit.
+// IEEE host: x = m 2^e (m in [0.5, 1)), e = K q + j, a linear first guess
+// for m^(-1/K) times 2^(-j/K) 2^(-q), then four Newton steps
+// y <- y + (y / K)(1 - x y^K) on y^(-K) = x.  No division; deterministic to
+// the bit.  Arguments below 1e-300 are raised to it.
 template <int K>
-struct TwoPow;
+struct TwoNeg;
 template <>
-struct TwoPow<5> {
-  static constexpr double c[5] = {1.0, 1.148698354997035, 1.3195079107728942,
-                                  1.515716566510398, 1.7411011265922482};
+struct TwoNeg<5> {
+  static constexpr double c[5] = {1.0, 0.8705505632961241, 0.757858283255199,
+                                  0.6597539553864471, 0.5743491774985175};
 };
 template <>
-struct TwoPow<6> {
-  static constexpr double c[6] = {1.0, 1.122462048309373, 1.2599210498948732,
-                                  1.4142135623730951, 1.5874010519681996,
-                                  1.7817974362806785};
+struct TwoNeg<6> {
+  static constexpr double c[6] = {1.0, 0.8908987181403393, 0.7937005259840998,
+                                  0.7071067811865476, 0.6299605249474366,
+                                  0.5612310241546865};
 };
 template <>
-struct TwoPow<7> {
-  static constexpr double c[7] = {1.0, 1.1040895136738123, 1.2190136542044754,
-                                  1.3459001926323562, 1.4859942891369484,
-                                  1.640670712015276, 1.8114473285278134};
+struct TwoNeg<7> {
+  static constexpr double c[7] = {1.0, 0.9057236642639067, 0.820335356007638,
+                                  0.7429971445684742, 0.6729500963161781,
+                                  0.6095068271022377, 0.5520447568369061};
 };
 template <>
-struct TwoPow<8> {
-  static constexpr double c[8] = {1.0, 1.0905077326652577, 1.189207115002721,
-                                  1.2968395546510096, 1.4142135623730951,
-                                  1.5422108254079407, 1.681792830507429,
-                                  1.8340080864093424};
+struct TwoNeg<8> {
+  static constexpr double c[8] = {1.0, 0.9170040432046712, 0.8408964152537145,
+                                  0.7711054127039704, 0.7071067811865476,
+                                  0.6484197773255048, 0.5946035575013605,
+                                  0.5452538663326288};
 };
 
 template <int K>
-__device__ __forceinline__ double root_k(double x) {
-  if (!(x > 0.0) || isinf(x)) return x;
+__device__ __forceinline__ double root_inv(double x) {
+  if (isnan(x) || x < 0.0) return NAN;
+  if (isinf(x)) return 0.0;
+  constexpr double u = 2.0 * TwoNeg<K>::c[K - 1];  // 2^(1/K)
+  constexpr double inv_k = 1.0 / (double)K;
+  x = fmax(x, 1e-300);
   int e;
   const double m = frexp(x, &e);
   const int q = e >= 0 ? e / K : -((-e + K - 1) / K);
   const int j = e - q * K;
   double cj = 1.0;
 #pragma unroll
-  for (int i = 0; i < K; ++i) cj = (i == j) ? TwoPow<K>::c[i] : cj;
-  const double lo = 0.5 * TwoPow<K>::c[K - 1];
-  const double g = fmaT(2.0 * (1.0 - lo), m - 0.5, lo);
-  double r = ldexp(cj * g, q);
+  for (int i = 0; i < K; ++i) cj = (i == j) ? TwoNeg<K>::c[i] : cj;
+  const double g = fmaT(-2.0 * (u - 1.0), m - 0.5, u);
+  double y = ldexp(cj * g, -q);
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
-    double pw = r;
+    double pw = y;
 #pragma unroll
-    for (int i = 2; i < K; ++i) pw = pw * r;
-    r = fmaT((double)(K - 1), r, x / pw) / (double)K;
+    for (int i = 1; i < K; ++i) pw = pw * y;
+    const double t = fmaT(-x, pw, 1.0);
+    y = fmaT(y * inv_k, t, y);
   }
-  return r;
+  return y;
 }
 
 // Starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4).
@@ -244,7 +360,7 @@ __device__ double initial_step(const T* y0, const T* p, const T* f0, double t0,
   const double d2 = rms<D>(v, sc) / h0;
   const double dm = fmax(d1, d2);
   const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3)
-                                  : root_k<Tab::ORDER + 1>(0.01 / dm);
+                                  : root_inv<Tab::ORDER + 1>(dm * 100.0);
   return fmin(fmin(100.0 * h0, h1), t1 - t0);
 }
 
@@ -253,6 +369,64 @@ __device__ __forceinline__ void load_params(const IvpArgs& a, int64_t tr, T* p) 
   const T* P = (const T*)a.params;
 #pragma unroll
   for (int c = 0; c < NP; ++c) p[c] = a.params_shared ? P[c] : P[c * a.n + tr];
+}
+
+// One taped step: h then the state, moved as 16-byte chunks (the record
+// size is a multiple of 16 and every record starts 16-byte aligned).
+template <class T, int D>
+struct alignas(16) RecBuf {
+  double h;
+  T y[D];
+};
+
+template <class T, int D>
+__device__ __forceinline__ void store_rec(char* rp, double h, const T* y) {
+  constexpr int RB = TapeRec<T, D>::BYTES;
+  static_assert(sizeof(RecBuf<T, D>) == RB, "record layout");
+  RecBuf<T, D> b;
+  b.h = h;
+#pragma unroll
+  for (int c = 0; c < D; ++c) b.y[c] = y[c];
+  const uint4* src = reinterpret_cast<const uint4*>(&b);
+  uint4* dst = reinterpret_cast<uint4*>(__builtin_assume_aligned(rp, 16));
+#pragma unroll
+  for (int q = 0; q < RB / 16; ++q) dst[q] = src[q];
+}
+
+constexpr int TAPE_GROUP = 4;  // step records staged per lane before a write
+
+// Put one record into this lane's staging slots starting at chunk q0.
+template <class T, int D>
+__device__ __forceinline__ void stage_rec(uint4* stage, int q0, double h, const T* y) {
+  constexpr int CH = TapeRec<T, D>::BYTES / 16;
+  RecBuf<T, D> b;
+  b.h = h;
+#pragma unroll
+  for (int c = 0; c < D; ++c) b.y[c] = y[c];
+  const uint4* src = reinterpret_cast<const uint4*>(&b);
+#pragma unroll
+  for (int q = 0; q < CH; ++q) stage[(q0 + q) * 256 + threadIdx.x] = src[q];
+}
+
+// Write this lane's first `count` staged records to rp (contiguous).
+template <class T, int D>
+__device__ __forceinline__ void flush_recs(const uint4* stage, int count, char* rp) {
+  constexpr int CH = TapeRec<T, D>::BYTES / 16;
+  uint4* dst = reinterpret_cast<uint4*>(__builtin_assume_aligned(rp, 16));
+  for (int q = 0; q < count * CH; ++q) dst[q] = stage[q * 256 + threadIdx.x];
+}
+
+template <class T, int D>
+__device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
+  constexpr int RB = TapeRec<T, D>::BYTES;
+  RecBuf<T, D> b;
+  uint4* dst = reinterpret_cast<uint4*>(&b);
+  const uint4* src = reinterpret_cast<const uint4*>(__builtin_assume_aligned(rp, 16));
+#pragma unroll
+  for (int q = 0; q < RB / 16; ++q) dst[q] = src[q];
+  h = b.h;
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = b.y[c];
 }
 
 // ------------------------------------------------------- forward / record --
@@ -264,6 +438,18 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
   constexpr int RB = TapeRec<T, D>::BYTES;
   const int64_t n = a.ivp.n;
   const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // save times in LDS (lane-varying index, short latency); slot n_save holds
+  // +inf so that "no save left" needs no branch
+  __shared__ double s_times[65];
+  // Tape staging: each lane collects GROUP consecutive step records here and
+  // writes them out together as whole cache lines.  Chunk-major layout
+  // (chunk, lane) keeps the 16-byte LDS accesses free of bank conflicts.
+  constexpr int CH = TapeRec<T, D>::BYTES / 16;
+  __shared__ uint4 s_tape[(MODE == MODE_SOLVE) ? 1 : TAPE_GROUP * CH * 256];
+  if (threadIdx.x < 65)
+    s_times[threadIdx.x] = (int)threadIdx.x < a.ivp.n_save ? save_time_at(a.ivp.st, threadIdx.x)
+                                                          : INFINITY;
+  __syncthreads();
   if (tr >= n) return;
   const double t0 = a.ivp.t0, t1 = a.ivp.t1;
   const double rtol = a.ivp.rtol, atol = a.ivp.atol;
@@ -304,7 +490,12 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
   if constexpr (MODE != MODE_SOLVE) R.first_page[tr] = -1;
   double tp = t0;
   int next_save = 0;
-  double ts = a.ivp.st.t[0];
+  // running pointers to this lane's next save-state slots
+  T* ys_out = ysv + tr;
+  int32_t* sidx_out = R.save_idx + tr;
+  double* sdt_out = R.save_dt + tr;
+  const int64_t ys_stride = (int64_t)D * n;
+  double ts = s_times[0];
   bool side = false;
   int32_t S = 0, trials = 0;
   bool prev_rej = false;
@@ -341,37 +532,43 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
     }
 
     // one evaluation of the step map from the selected base
-    T yb[D];
-    T k[Tab::S][D], Y[Tab::S][D];
+    T yb[D], kb[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) yb[c] = side ? yp[c] : y[c];
     if constexpr (Tab::FSAL) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) k[0][c] = side ? k1p[c] : k1[c];
+      for (int c = 0; c < D; ++c) kb[c] = side ? k1p[c] : k1[c];
     } else {
-      Sys::rhs(yb, p, k[0]);
+      Sys::rhs(yb, p, kb);
     }
-    stages<Sys, Tab, T, Tab::S>(yb, p, T(hh), k, Y);
-    T ynew[D];
+    T Yunused[Tab::S][D];
+    T ylast[D], klast[D], ynew[D];
+    double esum[D];
+    step_push<Sys, Tab, T, Tab::S, false, !Tab::FSAL, MODE != MODE_FROZEN>(
+        yb, kb, p, T(hh), Yunused, ylast, klast, ynew, esum);
     if constexpr (Tab::FSAL) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) ynew[c] = Y[Tab::S - 1][c];
-    } else {
-      update<Tab, T, D, Tab::S>(yb, T(hh), k, ynew);
+      for (int c = 0; c < D; ++c) ynew[c] = ylast[c];
     }
-    double err = 0.0;
-    if constexpr (MODE != MODE_FROZEN)
-      err = err_norm<Tab, T, D, Tab::S>(yb, ynew, hh, k, rtol, atol);
+    double err = 0.0, fac0 = 0.0;
+    if constexpr (MODE != MODE_FROZEN) {
+      err = err_norm_sum<T, D>(yb, ynew, hh, esum, rtol, atol);
+      // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
+      fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
+    }
 
     if (side) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) ysv[((int64_t)next_save * D + c) * n + tr] = ynew[c];
+      for (int c = 0; c < D; ++c) ys_out[c * n] = ynew[c];
+      ys_out += ys_stride;
       if constexpr (MODE != MODE_SOLVE) {
-        R.save_idx[(int64_t)next_save * n + tr] = S - 1;
-        R.save_dt[(int64_t)next_save * n + tr] = hh;
+        *sidx_out = S - 1;
+        *sdt_out = hh;
+        sidx_out += n;
+        sdt_out += n;
       }
       ++next_save;
-      ts = next_save < ns ? save_time_at(a.ivp.st, next_save) : INFINITY;
+      ts = s_times[next_save];
       side = ts < t;
       continue;
     }
@@ -404,10 +601,9 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
           page = np_;
           pg = R.pages + (int64_t)page * R.page_bytes;
         }
-        char* rp = pg + slot * RB;
-        *(double*)rp = hh;
-#pragma unroll
-        for (int c = 0; c < D; ++c) ((T*)(rp + 8))[c] = yb[c];
+        stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, yb);
+        if (slot % TAPE_GROUP == TAPE_GROUP - 1)
+          flush_recs<T, D>(s_tape, TAPE_GROUP, pg + (slot - (TAPE_GROUP - 1)) * RB);
       }
       ++S;
       tp = t;
@@ -419,41 +615,40 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
       }
       if constexpr (Tab::FSAL) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) k1[c] = k[Tab::S - 1][c];
+        for (int c = 0; c < D; ++c) k1[c] = klast[c];
       }
       t = last ? t1 : t + hh;
       if constexpr (MODE != MODE_FROZEN) {
-        double fac = (err == 0.0) ? 10.0 : 0.9 / root_k<Tab::QEMB + 1>(err);
-        fac = fmax(0.2, fmin(prev_rej ? 1.0 : 10.0, fac));
-        h = hh * fac;
+        h = hh * fmax(0.2, fmin(prev_rej ? 1.0 : 10.0, fac0));
         prev_rej = false;
       }
       side = ts < t;
     } else {
-      const double fac = fmax(0.2, 0.9 / root_k<Tab::QEMB + 1>(err));
-      h = hh * fac;
+      h = hh * fmax(0.2, fac0);
       prev_rej = true;
     }
   }
 
-  // saves at the last mesh point (t_s = t1): a side step of size zero
-  if (status == LANE_OK) {
-    for (; next_save < ns; ++next_save) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) ysv[((int64_t)next_save * D + c) * n + tr] = y[c];
-      if constexpr (MODE != MODE_SOLVE) {
-        R.save_idx[(int64_t)next_save * n + tr] = S;
-        R.save_dt[(int64_t)next_save * n + tr] = save_time_at(a.ivp.st, next_save) - t;
-      }
+  // records of an unfinished group
+  if constexpr (MODE != MODE_SOLVE) {
+    const int rem = S % TAPE_GROUP;
+    if (rem > 0 && pg != nullptr) {
+      const int slot0 = (S - rem) % K;
+      flush_recs<T, D>(s_tape, rem, pg + slot0 * RB);
     }
-  } else {
-    for (; next_save < ns; ++next_save) {
+  }
+
+  // saves at the last mesh point (t_s = t1): a side step of size zero
+  const bool ok = (status == LANE_OK);
+  for (; next_save < ns; ++next_save) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) ysv[((int64_t)next_save * D + c) * n + tr] = T(NAN);
-      if constexpr (MODE != MODE_SOLVE) {
-        R.save_idx[(int64_t)next_save * n + tr] = -1;
-        R.save_dt[(int64_t)next_save * n + tr] = NAN;
-      }
+    for (int c = 0; c < D; ++c) ys_out[c * n] = ok ? y[c] : T(NAN);
+    ys_out += ys_stride;
+    if constexpr (MODE != MODE_SOLVE) {
+      *sidx_out = ok ? S : -1;
+      *sdt_out = ok ? s_times[next_save] - t : NAN;
+      sidx_out += n;
+      sdt_out += n;
     }
   }
   if constexpr (MODE != MODE_SOLVE) {
@@ -531,9 +726,23 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
   double loss = 0.0;
   const T two_scale = T(2.0 * a.scale);
 
+  // Save bookkeeping, walked from the last save to the first.
   int s = R.n_save - 1;
-  int32_t sidx = R.save_idx[(int64_t)s * n + tr];
-  double sdt = R.save_dt[(int64_t)s * n + tr];
+  const int32_t* sidx_p = R.save_idx + (int64_t)s * n + tr;
+  const double* sdt_p = R.save_dt + (int64_t)s * n + tr;
+  int32_t sidx = *sidx_p;
+  double sdt = *sdt_p;
+  auto next_save = [&]() {
+    --s;
+    sidx_p -= n;
+    sdt_p -= n;
+    if (s >= 0) {
+      sidx = *sidx_p;
+      sdt = *sdt_p;
+    }
+  };
+
+  // Tape position of the step record of mesh step i (h_i, y_{i-1}).
   int32_t i = S;
   int slot = S > 0 ? (S - 1) % K : 0;
 
@@ -544,11 +753,7 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
       save_cotangent<T, D>(a, s, tr, ycur, two_scale, w, loss);
 #pragma unroll
       for (int c = 0; c < D; ++c) lam[c] = lam[c] + w[c];
-      --s;
-      if (s >= 0) {
-        sidx = R.save_idx[(int64_t)s * n + tr];
-        sdt = R.save_dt[(int64_t)s * n + tr];
-      }
+      next_save();
     }
     const bool side = (s >= 0 && sidx == i);
     if (!side && i == 0) break;
@@ -560,20 +765,16 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
 #pragma unroll
       for (int c = 0; c < D; ++c) yb[c] = ycur[c];
     } else {
-      const char* rp = R.pages + (int64_t)page * R.page_bytes + slot * RB;
-      hh = *(const double*)rp;
-#pragma unroll
-      for (int c = 0; c < D; ++c) yb[c] = ((const T*)(rp + 8))[c];
+      load_rec<T, D>(R.pages + (int64_t)page * R.page_bytes + slot * RB, hh, yb);
     }
 
     // recompute the stages of this step
-    T k[SU][D], Y[SU][D];
-    Sys::rhs(yb, p, k[0]);
-    stages<Sys, Tab, T, SU>(yb, p, T(hh), k, Y);
+    T k0[D], Y[SU][D], ylast[D], klast[D], ys[D];
+    Sys::rhs(yb, p, k0);
+    step_push<Sys, Tab, T, SU, true, true, false>(yb, k0, p, T(hh), Y, ylast, klast, ys,
+                                                  nullptr);
     T w[D];
     if (side) {
-      T ys[D];
-      update<Tab, T, D, SU>(yb, T(hh), k, ys);
       save_cotangent<T, D>(a, s, tr, ys, two_scale, w, loss);
     } else {
 #pragma unroll
@@ -616,11 +817,7 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
     if (side) {
 #pragma unroll
       for (int c = 0; c < D; ++c) lam[c] = lam[c] + lin[c];
-      --s;
-      if (s >= 0) {
-        sidx = R.save_idx[(int64_t)s * n + tr];
-        sdt = R.save_dt[(int64_t)s * n + tr];
-      }
+      next_save();
     } else {
 #pragma unroll
       for (int c = 0; c < D; ++c) {
