@@ -216,12 +216,22 @@ int ensemble_mesh_export(const ens_record* rec, double* h, int32_t* steps,
 /* Reverse sweep (paper, Section 3.1): gradient of the loss with respect to
  * the parameters (grad_params) and, if grad_y0 is not NULL, the initial
  * states.  loss_out (device [n], nullable) receives each trajectory's loss.
- * Trajectories whose record status is not ENS_LANE_OK get NaN gradients and
- * loss.  The ivp must describe the same ensemble as the record. */
+ * Trajectories whose record status is not ENS_LANE_OK get NaN per-trajectory
+ * gradients and loss; with shared parameters they contribute nothing to the
+ * sum.  Shared parameters (problem.params_shared) give grad_params [P],
+ * summed over trajectories in a fixed order (run-to-run identical); they need
+ * a device workspace of ensemble_adjoint_workspace_bytes bytes (otherwise
+ * workspace may be NULL).  The ivp must describe the same ensemble as the
+ * record. */
 int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
                      const ens_record* rec, const ens_loss* loss,
                      void* grad_params, void* grad_y0, double* loss_out,
-                     void* stream);
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace ensemble_adjoint needs for this problem (0 for per-trajectory
+ * parameters). */
+int ensemble_adjoint_workspace_bytes(const ens_problem* prob,
+                                     const ens_ivp* ivp, size_t* bytes);
 
 /* Totals of a finished record (synchronizes the stream). */
 int ensemble_record_stats(const ens_record* rec, ens_stats* out, void* stream);

@@ -67,7 +67,8 @@ class Loss(C.Structure):
 
 EXPORTS = ("ensemble_solve", "ensemble_record_bytes", "ensemble_record",
            "ensemble_replay_mesh", "ensemble_mesh_export", "ensemble_adjoint",
-           "ensemble_record_stats", "ensemble_last_error")
+           "ensemble_adjoint_workspace_bytes", "ensemble_record_stats",
+           "ensemble_last_error")
 
 _lib = None
 
@@ -91,7 +92,8 @@ def load(build_if_missing=True):
                                          C.POINTER(Record), Ptr, Ptr, Ptr]
     lib.ensemble_mesh_export.argtypes = [C.POINTER(Record), Ptr, Ptr, C.c_int64, Ptr]
     lib.ensemble_adjoint.argtypes = [P, V, C.POINTER(Record), C.POINTER(Loss), Ptr, Ptr, Ptr,
-                                     Ptr]
+                                     Ptr, C.c_size_t, Ptr]
+    lib.ensemble_adjoint_workspace_bytes.argtypes = [P, V, C.POINTER(C.c_size_t)]
     lib.ensemble_record_stats.argtypes = [C.POINTER(Record), C.POINTER(Stats), Ptr]
     lib.ensemble_last_error.argtypes = []
     lib.ensemble_last_error.restype = C.c_char_p

@@ -194,9 +194,20 @@ def ensemble_mesh_export(handle, cap=None):
 _LOSS = {"sumsq": A.LOSS_SUMSQ, "mse": A.LOSS_MSE_TARGET, "cotangent": A.LOSS_COTANGENT}
 
 
+def ensemble_adjoint_workspace_bytes(handle):
+    spec = handle.spec
+    out = C.c_size_t()
+    A.check(A.load().ensemble_adjoint_workspace_bytes(C.byref(spec.prob), C.byref(spec.ivp),
+                                                      C.byref(out)))
+    return out.value
+
+
 def ensemble_adjoint(handle, loss="sumsq", data=None, scale=1.0, want_y0=True,
-                     want_loss=True):
-    """Reverse sweep: (grad_params [P, n], grad_y0 [d, n] or None, loss [n] or None)."""
+                     want_loss=True, workspace=None):
+    """Reverse sweep: (grad_params, grad_y0 [d, n] or None, loss [n] or None).
+
+    grad_params is [P, n], or [P] (summed over trajectories in a fixed order)
+    when the parameters are shared."""
     spec = handle.spec
     if loss not in _LOSS:
         raise ValueError(f"loss must be one of {sorted(_LOSS)}")
@@ -205,12 +216,19 @@ def ensemble_adjoint(handle, loss="sumsq", data=None, scale=1.0, want_y0=True,
         if data.dtype != spec.dtype or tuple(data.shape) != (spec.n_save, spec.d, spec.n):
             raise ValueError(f"loss data must be [{spec.n_save}, {spec.d}, {spec.n}] {spec.dtype}")
     dev = spec.y0.device
-    gp = torch.empty((spec.npar, spec.n), dtype=spec.dtype, device=dev)
+    shared = bool(spec.prob.params_shared)
+    gp = torch.empty((spec.npar,) if shared else (spec.npar, spec.n), dtype=spec.dtype,
+                     device=dev)
     gy = torch.empty((spec.d, spec.n), dtype=spec.dtype, device=dev) if want_y0 else None
     ll = torch.empty(spec.n, dtype=torch.float64, device=dev) if want_loss else None
+    ws_bytes = ensemble_adjoint_workspace_bytes(handle)
+    if ws_bytes and workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     lo = A.Loss(_LOSS[loss], data.data_ptr() if data is not None else None, float(scale))
     A.check(A.load().ensemble_adjoint(C.byref(spec.prob), C.byref(spec.ivp), C.byref(handle.rec),
-                                      C.byref(lo), _ptr(gp), _ptr(gy), _ptr(ll), _stream()))
+                                      C.byref(lo), _ptr(gp), _ptr(gy), _ptr(ll),
+                                      _ptr(workspace), int(workspace.numel()) if workspace is not None else 0,
+                                      _stream()))
     return gp, gy, ll
 
 

@@ -476,10 +476,21 @@ int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,
   return e == hipSuccess ? ENS_OK : hip_fail(e, "export launch");
 }
 
+int ensemble_adjoint_workspace_bytes(const ens_problem* p, const ens_ivp* v,
+                                     size_t* bytes) {
+  SysInfo si;
+  int rc;
+  if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
+  if ((rc = check_ivp(v, false)) != ENS_OK) return rc;
+  if (!bytes) return fail(ENS_EINVAL, "bytes is NULL");
+  *bytes = p->params_shared ? (size_t)grid_of(v->n) * si.np * elem_size(p->dtype) : 0;
+  return ENS_OK;
+}
+
 int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
                      const ens_record* r, const ens_loss* loss,
                      void* grad_params, void* grad_y0, double* loss_out,
-                     void* stream) {
+                     void* workspace, size_t workspace_bytes, void* stream) {
   SysInfo si;
   int rc;
   if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
@@ -492,8 +503,10 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
   if (loss->kind != ENS_LOSS_SUMSQ && !loss->data)
     return fail(ENS_EINVAL, "loss data is NULL");
   if (!grad_params) return fail(ENS_EINVAL, "grad_params is NULL");
-  if (p->params_shared)
-    return fail(ENS_EUNSUPPORTED, "shared parameters: adjoint not built yet");
+  size_t need = 0;
+  ensemble_adjoint_workspace_bytes(p, v, &need);
+  if (p->params_shared && (!workspace || workspace_bytes < need))
+    return fail(ENS_EINVAL, "shared parameters need a workspace of %zu bytes", need);
   AdjArgs aa{};
   aa.ivp = ivp_args(p, v);
   aa.rec = view_of(r);
@@ -503,13 +516,23 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
   aa.grad_p = grad_params;
   aa.grad_y0 = grad_y0;
   aa.loss_out = loss_out;
+  aa.workspace = workspace;
   hipStream_t st = (hipStream_t)stream;
+  const bool shared = p->params_shared != 0;
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);
     using T = decltype(t);
-    hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T>), dim3(grid_of(v->n)),
-                       dim3(BLOCK), 0, st, aa);
+    if (shared) {
+      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true>), dim3(grid_of(v->n)),
+                         dim3(BLOCK), 0, st, aa);
+      hipLaunchKernelGGL((reduce_partials_kernel<T>), dim3(Sys::NP), dim3(BLOCK), 0, st,
+                         (const T*)workspace, (int64_t)grid_of(v->n), Sys::NP,
+                         (T*)grad_params);
+    } else {
+      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, false>), dim3(grid_of(v->n)),
+                         dim3(BLOCK), 0, st, aa);
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
   });

@@ -65,6 +65,7 @@ struct AdjArgs {
   void* grad_p;           // [NP][n]
   void* grad_y0;          // [D][n] or null
   double* loss_out;       // [n] or null
+  void* workspace;        // shared parameters: [n_blocks][NP] partials
 };
 
 // ------------------------------------------------------------ one step --
@@ -689,41 +690,32 @@ __device__ __forceinline__ void save_cotangent(const AdjArgs& a, int s,
   }
 }
 
-template <class Sys, class Tab, class T>
+template <class Sys, class Tab, class T, bool SHARED>
 __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
   constexpr int D = Sys::D, NP = Sys::NP, K = PAGE_STEPS, SU = Tab::SU;
   constexpr int RB = TapeRec<T, D>::BYTES;
   const int64_t n = a.ivp.n;
   const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tr >= n) return;
+  const bool valid = tr < n;
   const RecView& R = a.rec;
+  const bool ok = valid && R.status[tr] == LANE_OK;
   T* gpo = (T*)a.grad_p;
   T* gyo = (T*)a.grad_y0;
-
-  if (R.status[tr] != LANE_OK) {
+  T lam[D], gp[NP];
 #pragma unroll
-    for (int c = 0; c < NP; ++c) gpo[c * n + tr] = T(NAN);
-    if (gyo) {
+  for (int c = 0; c < D; ++c) lam[c] = T(0);
 #pragma unroll
-      for (int c = 0; c < D; ++c) gyo[c * n + tr] = T(NAN);
-    }
-    if (a.loss_out) a.loss_out[tr] = NAN;
-    return;
-  }
+  for (int c = 0; c < NP; ++c) gp[c] = T(0);
+  double loss = 0.0;
 
+  if (ok) {
   T p[NP];
   load_params<T, NP>(a.ivp, tr, p);
   const int32_t S = R.steps[tr];
   int32_t page = R.last_page[tr];
-  T ycur[D], lam[D], gp[NP];
+  T ycur[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) {
-    ycur[c] = ((const T*)R.y_final)[c * n + tr];
-    lam[c] = T(0);
-  }
-#pragma unroll
-  for (int c = 0; c < NP; ++c) gp[c] = T(0);
-  double loss = 0.0;
+  for (int c = 0; c < D; ++c) ycur[c] = ((const T*)R.y_final)[c * n + tr];
   const T two_scale = T(2.0 * a.scale);
 
   // Save bookkeeping, walked from the last save to the first.
@@ -833,13 +825,55 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
   }
 
   if (a.loss_kind != LOSS_COTANGENT) loss = a.scale * loss;
+  }  // ok
+
+  // per-trajectory outputs; a trajectory whose record failed gets NaN
+  if (valid) {
+    if (!SHARED) {
 #pragma unroll
-  for (int c = 0; c < NP; ++c) gpo[c * n + tr] = gp[c];
-  if (gyo) {
+      for (int c = 0; c < NP; ++c) gpo[c * n + tr] = ok ? gp[c] : T(NAN);
+    }
+    if (gyo) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) gyo[c * n + tr] = lam[c];
+      for (int c = 0; c < D; ++c) gyo[c * n + tr] = ok ? lam[c] : T(NAN);
+    }
+    if (a.loss_out)
+      a.loss_out[tr] = !ok ? NAN : (a.loss_kind == LOSS_COTANGENT ? 0.0 : loss);
   }
-  if (a.loss_out) a.loss_out[tr] = (a.loss_kind == LOSS_COTANGENT) ? 0.0 : loss;
+  if constexpr (SHARED) {
+    // shared parameters: fixed-order tree over the block's lanes (failed
+    // trajectories contribute nothing), one partial per block
+    __shared__ T red[256];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      red[threadIdx.x] = ok ? gp[c] : T(0);
+      __syncthreads();
+      for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) ((T*)a.workspace)[(int64_t)blockIdx.x * NP + c] = red[0];
+      __syncthreads();
+    }
+  }
+}
+
+// Sum of the per-block partials of shared-parameter gradients, in a fixed
+// order: thread k adds blocks k, k+256, ... then a tree over the threads.
+template <class T>
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const T* part, int64_t nb,
+                                                              int np, T* out) {
+  __shared__ T red[256];
+  const int c = blockIdx.x;
+  T acc = T(0);
+  for (int64_t b = threadIdx.x; b < nb; b += 256) acc = acc + part[b * np + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
 }
 
 }  // namespace ens

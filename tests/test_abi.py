@@ -101,4 +101,14 @@ def test_null_pointers_rejected_before_launch():
     assert lib.ensemble_record(C.byref(_prob()), C.byref(_ivp()), C.byref(tc), C.byref(rec),
                                None, None, None) == A.ENS_EINVAL
     assert lib.ensemble_adjoint(C.byref(_prob()), C.byref(_ivp()), None, None, None, None, None,
-                                None) == A.ENS_EINVAL
+                                None, 0, None) == A.ENS_EINVAL
+
+
+def test_adjoint_workspace_plan():
+    lib = _lib()
+    out = C.c_size_t()
+    assert lib.ensemble_adjoint_workspace_bytes(C.byref(_prob()), C.byref(_ivp()), C.byref(out)) == 0
+    assert out.value == 0
+    assert lib.ensemble_adjoint_workspace_bytes(C.byref(_prob(params_shared=1)), C.byref(_ivp()),
+                                                C.byref(out)) == 0
+    assert out.value == 4 * 3 * 8   # 1024 trajectories = 4 blocks x 3 params x 8 bytes
