@@ -109,11 +109,18 @@ typedef struct {
 } ens_ivp;
 
 /* ---- records ------------------------------------------------------------ */
-/* Pool configuration.  ckpt_every must be 0 (a full tape: the state before
- * every accepted step is kept).  Each trajectory reserves steps_per_traj
- * taped steps up front (rounded up to whole pages); steps beyond that come
- * from a shared overflow area of the pool, handed out on demand.
- * steps_per_traj = 0 reserves 7/8 of the pool evenly. */
+/* Pool configuration.
+ *   ckpt_every = 0: full tape -- the state before every accepted step is kept
+ *     with its step size (16 steps per page).
+ *   ckpt_every in {16, 32, 64, 128, 256}: checkpointed tape -- one page per
+ *     segment of ckpt_every accepted steps holds the state at the segment's
+ *     start and the segment's step sizes; the reverse sweep replays each
+ *     segment forward (the same arithmetic, so the same gradient bits) before
+ *     sweeping it backward.  About 8.5 instead of 32 bytes per Lorenz step.
+ * Each trajectory reserves steps_per_traj taped steps up front (rounded up
+ * to whole pages); steps beyond that come from a shared overflow area of the
+ * pool, handed out on demand.  steps_per_traj = 0 reserves 7/8 of the pool
+ * evenly. */
 typedef struct {
   void* pool;        /* device, 256-byte aligned */
   size_t pool_bytes;
@@ -132,7 +139,7 @@ typedef struct {
   int64_t n_pages;      /* pages the pool holds (reserved + overflow) */
   int64_t page_bytes;
   int32_t static_pages; /* pages reserved per trajectory */
-  int32_t pad_;
+  int32_t ckpt_every;   /* 0: full tape; else steps per checkpoint segment */
   double t0, t1;
   void* pool;
   size_t pool_bytes;
@@ -228,10 +235,10 @@ int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
                      void* grad_params, void* grad_y0, double* loss_out,
                      void* workspace, size_t workspace_bytes, void* stream);
 
-/* Workspace ensemble_adjoint needs for this problem (0 for per-trajectory
- * parameters). */
-int ensemble_adjoint_workspace_bytes(const ens_problem* prob,
-                                     const ens_ivp* ivp, size_t* bytes);
+/* Workspace ensemble_adjoint needs for this record: per-block partial sums
+ * for shared parameters, plus one segment of step records per trajectory for
+ * a checkpointed tape (0 for a full tape with per-trajectory parameters). */
+int ensemble_adjoint_workspace_bytes(const ens_record* rec, size_t* bytes);
 
 /* Totals of a finished record (synchronizes the stream). */
 int ensemble_record_stats(const ens_record* rec, ens_stats* out, void* stream);

@@ -47,7 +47,7 @@ class Record(C.Structure):
                 ("dim", C.c_int32), ("nparams", C.c_int32), ("params_shared", C.c_int32),
                 ("n_save", C.c_int32), ("page_steps", C.c_int32), ("rec_bytes", C.c_int32),
                 ("n_pages", C.c_int64), ("page_bytes", C.c_int64),
-                ("static_pages", C.c_int32), ("pad_", C.c_int32),
+                ("static_pages", C.c_int32), ("ckpt_every", C.c_int32),
                 ("t0", C.c_double), ("t1", C.c_double),
                 ("pool", C.c_void_p), ("pool_bytes", C.c_size_t),
                 ("steps", C.c_void_p), ("n_trial", C.c_void_p), ("first_page", C.c_void_p),
@@ -93,7 +93,7 @@ def load(build_if_missing=True):
     lib.ensemble_mesh_export.argtypes = [C.POINTER(Record), Ptr, Ptr, C.c_int64, Ptr]
     lib.ensemble_adjoint.argtypes = [P, V, C.POINTER(Record), C.POINTER(Loss), Ptr, Ptr, Ptr,
                                      Ptr, C.c_size_t, Ptr]
-    lib.ensemble_adjoint_workspace_bytes.argtypes = [P, V, C.POINTER(C.c_size_t)]
+    lib.ensemble_adjoint_workspace_bytes.argtypes = [C.POINTER(Record), C.POINTER(C.c_size_t)]
     lib.ensemble_record_stats.argtypes = [C.POINTER(Record), C.POINTER(Stats), Ptr]
     lib.ensemble_last_error.argtypes = []
     lib.ensemble_last_error.restype = C.c_char_p

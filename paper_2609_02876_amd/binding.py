@@ -99,15 +99,15 @@ def _view_i32(ptr, n, pool):
 
 
 def ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save=0,
-                          dtype=torch.float64):
+                          dtype=torch.float64, ckpt_every=0):
     sid, d, npar = _sysinfo(system)
     prob = A.Problem(sid, A.METHODS[method], _DT[dtype], d, npar, 0)
     st = (C.c_double * max(1, n_save))(*([t1] * max(1, n_save)))
     ivp = A.Ivp(n, None, None, float(t0), float(t1), 1e-6, 1e-6, 0.0, 0, int(n_save),
                 C.cast(st, C.POINTER(C.c_double)))
     out = C.c_size_t()
-    A.check(A.load().ensemble_record_bytes(C.byref(prob), C.byref(ivp), int(steps_hint), 0,
-                                           C.byref(out)))
+    A.check(A.load().ensemble_record_bytes(C.byref(prob), C.byref(ivp), int(steps_hint),
+                                           int(ckpt_every), C.byref(out)))
     return out.value
 
 
@@ -123,7 +123,7 @@ def ensemble_solve(system, method, y0, params, t0, t1, rtol, atol, save_times=No
     return y_out, status
 
 
-def _pool_for(spec, steps_hint, pool, steps_per_traj):
+def _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every=0):
     """(pool tensor, tape config): a given pool, or one planned for steps_hint."""
     if pool is not None:
         _require_gpu(pool)
@@ -132,15 +132,16 @@ def _pool_for(spec, steps_hint, pool, steps_per_traj):
         spt = int(steps_per_traj or 0)
     else:
         nbytes = ensemble_record_bytes(spec.system, spec.method, spec.n, spec.ivp.t0,
-                                       spec.ivp.t1, steps_hint, spec.ivp.n_save, spec.dtype)
+                                       spec.ivp.t1, steps_hint, spec.ivp.n_save, spec.dtype,
+                                       ckpt_every)
         pool = torch.empty(nbytes, dtype=torch.uint8, device=spec.y0.device)
         spt = int(steps_hint)
-    return pool, A.TapeCfg(pool.data_ptr(), pool.numel(), 0, spt)
+    return pool, A.TapeCfg(pool.data_ptr(), pool.numel(), int(ckpt_every), spt)
 
 
 def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
                     max_steps=0, params_shared=False, steps_hint=512, pool=None,
-                    steps_per_traj=None):
+                    steps_per_traj=None, ckpt_every=0):
     """Adaptive record.  Returns a RecordHandle (.y_save, .status, .pool).
 
     Without a pool, one is planned that reserves steps_hint taped steps per
@@ -148,7 +149,7 @@ def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=N
     per-trajectory reservation (None: 7/8 of the pool evenly)."""
     spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
                  params_shared)
-    pool, tc = _pool_for(spec, steps_hint, pool, steps_per_traj)
+    pool, tc = _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every)
     rec = A.Record()
     y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
     status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
@@ -158,7 +159,7 @@ def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=N
 
 
 def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_times=None,
-                         params_shared=False, pool=None, steps_per_traj=None):
+                         params_shared=False, pool=None, steps_per_traj=None, ckpt_every=0):
     """Record on a given mesh h [cap, n] (float64), steps [n] (int32)."""
     spec = _Spec(system, method, y0, params, t0, t1, 1e-6, 1e-6, save_times, 0.0, 0,
                  params_shared)
@@ -168,7 +169,7 @@ def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_time
     if h.dim() != 2 or h.shape[1] != spec.n or steps.shape != (spec.n,):
         raise ValueError("h must be [cap, n] and steps [n]")
     cap = h.shape[0]
-    pool, tc = _pool_for(spec, cap, pool, steps_per_traj)
+    pool, tc = _pool_for(spec, cap, pool, steps_per_traj, ckpt_every)
     rec = A.Record()
     y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
     status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
@@ -195,10 +196,8 @@ _LOSS = {"sumsq": A.LOSS_SUMSQ, "mse": A.LOSS_MSE_TARGET, "cotangent": A.LOSS_CO
 
 
 def ensemble_adjoint_workspace_bytes(handle):
-    spec = handle.spec
     out = C.c_size_t()
-    A.check(A.load().ensemble_adjoint_workspace_bytes(C.byref(spec.prob), C.byref(spec.ivp),
-                                                      C.byref(out)))
+    A.check(A.load().ensemble_adjoint_workspace_bytes(C.byref(handle.rec), C.byref(out)))
     return out.value
 
 

@@ -67,6 +67,7 @@ struct RecView {
   int64_t n_pages;       // reserved + overflow
   int64_t n_static;      // n * static_pages: ids below this are reserved pages
   int32_t static_pages;  // reserved pages per trajectory
+  int32_t page_steps;    // accepted steps per page
   int64_t page_bytes;
   int32_t* steps;
   int32_t* n_trial;

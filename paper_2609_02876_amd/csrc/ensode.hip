@@ -107,7 +107,17 @@ struct Layout {
   size_t page_bytes;
 };
 
-Layout layout(int64_t n, int n_save_eff, int d, int dtype) {
+size_t state_bytes(int dtype, int d) { return (d * elem_size(dtype) + 15) / 16 * 16; }
+
+// Accepted steps per page: 16 for a full tape, the checkpoint interval otherwise.
+int page_steps_of(int ckpt_every) { return ckpt_every > 0 ? ckpt_every : PAGE_STEPS; }
+
+bool ckpt_ok(int ckpt_every) {
+  return ckpt_every == 0 || ckpt_every == 16 || ckpt_every == 32 || ckpt_every == 64 ||
+         ckpt_every == 128 || ckpt_every == 256;
+}
+
+Layout layout(int64_t n, int n_save_eff, int d, int dtype, int ckpt_every) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -127,7 +137,9 @@ Layout layout(int64_t n, int n_save_eff, int d, int dtype) {
   L.y_final = take((size_t)d * n * elem_size(dtype));
   L.fixed = off;
   L.links = off;
-  L.page_bytes = (size_t)PAGE_STEPS * rec_bytes(dtype, d);
+  L.page_bytes = ckpt_every > 0
+                     ? state_bytes(dtype, d) + (size_t)ckpt_every * sizeof(double)
+                     : (size_t)PAGE_STEPS * rec_bytes(dtype, d);
   return L;
 }
 
@@ -138,12 +150,12 @@ struct PageSplit {
 };
 
 bool split_pages(const Layout& L, int64_t n, size_t pool_bytes,
-                 int32_t steps_per_traj, PageSplit* ps) {
+                 int32_t steps_per_traj, int page_steps, PageSplit* ps) {
   if (pool_bytes < L.fixed + 512) return false;
   const size_t avail = pool_bytes - L.fixed - 256;
   int64_t sp;
   if (steps_per_traj > 0) {
-    sp = (steps_per_traj + PAGE_STEPS - 1) / PAGE_STEPS;
+    sp = (steps_per_traj + page_steps - 1) / page_steps;
   } else {
     sp = (int64_t)((avail / 8 * 7) / ((size_t)n * L.page_bytes));
   }
@@ -168,7 +180,8 @@ void fill_record(ens_record* r, const ens_problem* p, const ens_ivp* v,
   r->nparams = p->nparams;
   r->params_shared = p->params_shared;
   r->n_save = v->n_save > 0 ? v->n_save : 1;
-  r->page_steps = PAGE_STEPS;
+  r->page_steps = page_steps_of(tc->ckpt_every);
+  r->ckpt_every = tc->ckpt_every;
   r->rec_bytes = (int32_t)rec_bytes(p->dtype, p->dim);
   r->n_pages = n_pages;
   r->page_bytes = (int64_t)L.page_bytes;
@@ -197,6 +210,7 @@ RecView view_of(const ens_record* r) {
   v.n_save = r->n_save;
   v.n_pages = r->n_pages;
   v.static_pages = r->static_pages;
+  v.page_steps = r->page_steps;
   v.n_static = r->n * (int64_t)r->static_pages;
   v.page_bytes = r->page_bytes;
   v.steps = r->steps;
@@ -279,21 +293,23 @@ constexpr int BLOCK = 256;
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
-int launch_forward(const ens_problem* p, int mode, const FwdArgs& fa,
+int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
                    hipStream_t st) {
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);
     using T = decltype(t);
+    const dim3 g(grid_of(fa.ivp.n)), b(BLOCK);
     if (mode == MODE_SOLVE)
-      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_SOLVE>),
-                         dim3(grid_of(fa.ivp.n)), dim3(BLOCK), 0, st, fa);
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_SOLVE, false>), g, b, 0, st, fa);
+    else if (mode == MODE_RECORD && !ckpt)
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD, false>), g, b, 0, st, fa);
     else if (mode == MODE_RECORD)
-      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD>),
-                         dim3(grid_of(fa.ivp.n)), dim3(BLOCK), 0, st, fa);
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD, true>), g, b, 0, st, fa);
+    else if (!ckpt)
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_FROZEN, false>), g, b, 0, st, fa);
     else
-      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_FROZEN>),
-                         dim3(grid_of(fa.ivp.n)), dim3(BLOCK), 0, st, fa);
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_FROZEN, true>), g, b, 0, st, fa);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ENS_OK : hip_fail(e, "forward launch");
   });
@@ -323,14 +339,15 @@ int record_common(const ens_problem* p, const ens_ivp* v,
   if (!tc || !tc->pool) return fail(ENS_EINVAL, "tape pool is NULL");
   if (((uintptr_t)tc->pool & 255) != 0)
     return fail(ENS_EINVAL, "tape pool must be 256-byte aligned");
-  if (tc->ckpt_every != 0)
-    return fail(ENS_EUNSUPPORTED, "ckpt_every must be 0 (full tape)");
+  if (!ckpt_ok(tc->ckpt_every))
+    return fail(ENS_EINVAL, "ckpt_every must be 0, 16, 32, 64, 128 or 256");
   if (!out || !y_save) return fail(ENS_EINVAL, "out and y_save are required");
   const int nse = v->n_save > 0 ? v->n_save : 1;
-  Layout L = layout(v->n, nse, si.d, p->dtype);
+  Layout L = layout(v->n, nse, si.d, p->dtype, tc->ckpt_every);
   if (tc->steps_per_traj < 0) return fail(ENS_EINVAL, "steps_per_traj < 0");
   PageSplit ps;
-  if (!split_pages(L, v->n, tc->pool_bytes, tc->steps_per_traj, &ps))
+  if (!split_pages(L, v->n, tc->pool_bytes, tc->steps_per_traj,
+                   page_steps_of(tc->ckpt_every), &ps))
     return fail(ENS_ENOSPACE,
                 "pool of %zu bytes is below the fixed part (%zu) plus the "
                 "reserved pages",
@@ -351,22 +368,23 @@ int record_common(const ens_problem* p, const ens_ivp* v,
   fa.mesh_h = mesh_h;
   fa.mesh_S = mesh_S;
   fa.cap = cap;
-  return launch_forward(p, mode, fa, st);
+  return launch_forward(p, mode, tc->ckpt_every > 0, fa, st);
 }
 
 // Mesh export: walk each trajectory's pages forward.
-__global__ void mesh_export_kernel(const RecView R, int64_t rec_b, double* h,
-                                   int32_t* steps, int64_t cap) {
+__global__ void mesh_export_kernel(const RecView R, int64_t rec_b, int64_t h_off,
+                                   double* h, int32_t* steps, int64_t cap) {
   const int64_t n = R.n;
   const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tr >= n) return;
   const int32_t S = R.steps[tr];
   steps[tr] = S;
   int32_t page = R.static_pages > 0 ? (int32_t)(tr * R.static_pages) : R.first_page[tr];
+  const int K = R.page_steps;
   for (int32_t i = 0; i < S && i < cap; ++i) {
-    const int slot = i % PAGE_STEPS;
+    const int slot = i % K;
     if (i > 0 && slot == 0) page = next_page(R, tr, page);
-    h[(int64_t)i * n + tr] = *(const double*)(R.pages + (int64_t)page * R.page_bytes +
+    h[(int64_t)i * n + tr] = *(const double*)(R.pages + (int64_t)page * R.page_bytes + h_off +
                                               slot * rec_b);
   }
   for (int64_t i = S; i < cap; ++i) h[i * n + tr] = 0.0;
@@ -427,7 +445,7 @@ int ensemble_solve(const ens_problem* p, const ens_ivp* v, void* y_out,
   fa.ivp = ivp_args(p, v);
   fa.y_save = y_out;
   fa.lane_status = lane_status;
-  return launch_forward(p, MODE_SOLVE, fa, (hipStream_t)stream);
+  return launch_forward(p, MODE_SOLVE, false, fa, (hipStream_t)stream);
 }
 
 int ensemble_record_bytes(const ens_problem* p, const ens_ivp* v,
@@ -438,11 +456,13 @@ int ensemble_record_bytes(const ens_problem* p, const ens_ivp* v,
   if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
   if ((rc = check_ivp(v, false)) != ENS_OK) return rc;
   if (!bytes) return fail(ENS_EINVAL, "bytes is NULL");
-  if (ckpt_every != 0) return fail(ENS_EUNSUPPORTED, "ckpt_every must be 0");
+  if (!ckpt_ok(ckpt_every))
+    return fail(ENS_EINVAL, "ckpt_every must be 0, 16, 32, 64, 128 or 256");
   if (steps_hint < 1) return fail(ENS_EINVAL, "steps_hint must be >= 1");
   const int nse = v->n_save > 0 ? v->n_save : 1;
-  Layout L = layout(v->n, nse, si.d, p->dtype);
-  const int64_t pages_per = (steps_hint + PAGE_STEPS - 1) / PAGE_STEPS;
+  Layout L = layout(v->n, nse, si.d, p->dtype, ckpt_every);
+  const int ps = page_steps_of(ckpt_every);
+  const int64_t pages_per = (steps_hint + ps - 1) / ps;
   const int64_t n_static = pages_per * v->n;
   const int64_t n_over = n_static / 8 + 64;
   *bytes = L.fixed + 512 + (size_t)n_static * L.page_bytes +
@@ -470,20 +490,22 @@ int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,
                          int64_t cap, void* stream) {
   if (!r || !h || !steps || cap < 1) return fail(ENS_EINVAL, "bad arguments");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(mesh_export_kernel, dim3(grid_of(r->n)), dim3(BLOCK), 0, st,
-                     view_of(r), (int64_t)r->rec_bytes, h, steps, cap);
+  const bool ck = r->ckpt_every > 0;
+  hipLaunchKernelGGL(mesh_export_kernel, dim3(grid_of(r->n)), dim3(BLOCK), 0, st, view_of(r),
+                     ck ? (int64_t)8 : (int64_t)r->rec_bytes,
+                     ck ? (int64_t)state_bytes(r->dtype, r->dim) : (int64_t)0, h, steps, cap);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ENS_OK : hip_fail(e, "export launch");
 }
 
-int ensemble_adjoint_workspace_bytes(const ens_problem* p, const ens_ivp* v,
-                                     size_t* bytes) {
+int ensemble_adjoint_workspace_bytes(const ens_record* r, size_t* bytes) {
+  if (!r || !bytes) return fail(ENS_EINVAL, "bad arguments");
   SysInfo si;
-  int rc;
-  if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
-  if ((rc = check_ivp(v, false)) != ENS_OK) return rc;
-  if (!bytes) return fail(ENS_EINVAL, "bytes is NULL");
-  *bytes = p->params_shared ? (size_t)grid_of(v->n) * si.np * elem_size(p->dtype) : 0;
+  if (!sys_info(r->system, &si)) return fail(ENS_EINVAL, "record of unknown system");
+  size_t b = 0;
+  if (r->params_shared) b = align256((size_t)grid_of(r->n) * si.np * elem_size(r->dtype));
+  if (r->ckpt_every > 0) b += (size_t)r->n * r->page_steps * rec_bytes(r->dtype, r->dim);
+  *bytes = b;
   return ENS_OK;
 }
 
@@ -504,9 +526,11 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
     return fail(ENS_EINVAL, "loss data is NULL");
   if (!grad_params) return fail(ENS_EINVAL, "grad_params is NULL");
   size_t need = 0;
-  ensemble_adjoint_workspace_bytes(p, v, &need);
-  if (p->params_shared && (!workspace || workspace_bytes < need))
-    return fail(ENS_EINVAL, "shared parameters need a workspace of %zu bytes", need);
+  ensemble_adjoint_workspace_bytes(r, &need);
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(ENS_EINVAL, "this adjoint needs a workspace of %zu bytes", need);
+  if (((uintptr_t)workspace & 255) != 0)
+    return fail(ENS_EINVAL, "workspace must be 256-byte aligned");
   AdjArgs aa{};
   aa.ivp = ivp_args(p, v);
   aa.rec = view_of(r);
@@ -517,22 +541,29 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
   aa.grad_y0 = grad_y0;
   aa.loss_out = loss_out;
   aa.workspace = workspace;
-  hipStream_t st = (hipStream_t)stream;
   const bool shared = p->params_shared != 0;
+  const bool ckpt = r->ckpt_every > 0;
+  aa.scratch = ckpt ? (char*)workspace +
+                          (shared ? align256((size_t)grid_of(v->n) * si.np * elem_size(p->dtype)) : 0)
+                    : nullptr;
+  hipStream_t st = (hipStream_t)stream;
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);
     using T = decltype(t);
-    if (shared) {
-      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true>), dim3(grid_of(v->n)),
-                         dim3(BLOCK), 0, st, aa);
-      hipLaunchKernelGGL((reduce_partials_kernel<T>), dim3(Sys::NP), dim3(BLOCK), 0, st,
+    const dim3 g(grid_of(v->n)), b(BLOCK);
+    if (shared && ckpt)
+      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true, true>), g, b, 0, st, aa);
+    else if (shared)
+      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true, false>), g, b, 0, st, aa);
+    else if (ckpt)
+      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, false, true>), g, b, 0, st, aa);
+    else
+      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, false, false>), g, b, 0, st, aa);
+    if (shared)
+      hipLaunchKernelGGL((reduce_partials_kernel<T>), dim3(Sys::NP), b, 0, st,
                          (const T*)workspace, (int64_t)grid_of(v->n), Sys::NP,
                          (T*)grad_params);
-    } else {
-      hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, false>), dim3(grid_of(v->n)),
-                         dim3(BLOCK), 0, st, aa);
-    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
   });

@@ -66,6 +66,7 @@ struct AdjArgs {
   void* grad_y0;          // [D][n] or null
   double* loss_out;       // [n] or null
   void* workspace;        // shared parameters: [n_blocks][NP] partials
+  void* scratch;          // checkpointed tape: [n][page_steps] step records
 };
 
 // ------------------------------------------------------------ one step --
@@ -394,6 +395,50 @@ __device__ __forceinline__ void store_rec(char* rp, double h, const T* y) {
   for (int q = 0; q < RB / 16; ++q) dst[q] = src[q];
 }
 
+// Bytes of a checkpoint state (padded to 16).
+template <class T, int D>
+struct StateBytes {
+  static constexpr int BYTES = (D * (int)sizeof(T) + 15) / 16 * 16;
+};
+
+template <class T, int D>
+struct alignas(16) StateBuf {
+  T y[D];
+};
+
+template <class T, int D>
+__device__ __forceinline__ void store_state(char* rp, const T* y) {
+  StateBuf<T, D> b;
+#pragma unroll
+  for (int c = 0; c < D; ++c) b.y[c] = y[c];
+  const uint4* src = reinterpret_cast<const uint4*>(&b);
+  uint4* dst = reinterpret_cast<uint4*>(__builtin_assume_aligned(rp, 16));
+#pragma unroll
+  for (int q = 0; q < (int)sizeof(b) / 16; ++q) dst[q] = src[q];
+}
+
+template <class T, int D>
+__device__ __forceinline__ void load_state(const char* rp, T* y) {
+  StateBuf<T, D> b;
+  uint4* dst = reinterpret_cast<uint4*>(&b);
+  const uint4* src = reinterpret_cast<const uint4*>(__builtin_assume_aligned(rp, 16));
+#pragma unroll
+  for (int q = 0; q < (int)sizeof(b) / 16; ++q) dst[q] = src[q];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = b.y[c];
+}
+
+constexpr int H_GROUP = 16;  // step sizes staged per lane (checkpointed tape)
+
+// Write this lane's first `count` staged step sizes to hp (contiguous).
+__device__ __forceinline__ void flush_h(const double* s_h, int count, char* hp) {
+  double2* dst = reinterpret_cast<double2*>(__builtin_assume_aligned(hp, 16));
+  int q = 0;
+  for (; q + 1 < count; q += 2)
+    dst[q / 2] = make_double2(s_h[q * 256 + threadIdx.x], s_h[(q + 1) * 256 + threadIdx.x]);
+  if (q < count) reinterpret_cast<double*>(hp)[q] = s_h[q * 256 + threadIdx.x];
+}
+
 constexpr int TAPE_GROUP = 4;  // step records staged per lane before a write
 
 // Put one record into this lane's staging slots starting at chunk q0.
@@ -433,10 +478,15 @@ __device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
 // ------------------------------------------------------- forward / record --
 // MODE_SOLVE: adaptive solve, no tape.  MODE_RECORD: adaptive solve writing
 // the tape.  MODE_FROZEN: steps taken from a given mesh, writing the tape.
-template <class Sys, class Tab, class T, int MODE>
+//
+// CKPT (checkpointed tape): a page covers R.page_steps accepted steps and
+// holds the state before its first step followed by the step sizes only.
+template <class Sys, class Tab, class T, int MODE, bool CKPT>
 __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
-  constexpr int D = Sys::D, NP = Sys::NP, K = PAGE_STEPS;
+  constexpr int D = Sys::D, NP = Sys::NP;
   constexpr int RB = TapeRec<T, D>::BYTES;
+  constexpr int YB = StateBytes<T, D>::BYTES;
+  const int K = CKPT ? a.rec.page_steps : PAGE_STEPS;
   const int64_t n = a.ivp.n;
   const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // save times in LDS (lane-varying index, short latency); slot n_save holds
@@ -446,7 +496,9 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
   // writes them out together as whole cache lines.  Chunk-major layout
   // (chunk, lane) keeps the 16-byte LDS accesses free of bank conflicts.
   constexpr int CH = TapeRec<T, D>::BYTES / 16;
-  __shared__ uint4 s_tape[(MODE == MODE_SOLVE) ? 1 : TAPE_GROUP * CH * 256];
+  __shared__ uint4 s_tape[(MODE == MODE_SOLVE || CKPT) ? 1 : TAPE_GROUP * CH * 256];
+  // checkpointed tape: step sizes staged H_GROUP at a time (one 128-byte line)
+  __shared__ double s_h[CKPT ? H_GROUP * 256 : 1];
   if (threadIdx.x < 65)
     s_times[threadIdx.x] = (int)threadIdx.x < a.ivp.n_save ? save_time_at(a.ivp.st, threadIdx.x)
                                                           : INFINITY;
@@ -602,9 +654,16 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
           page = np_;
           pg = R.pages + (int64_t)page * R.page_bytes;
         }
-        stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, yb);
-        if (slot % TAPE_GROUP == TAPE_GROUP - 1)
-          flush_recs<T, D>(s_tape, TAPE_GROUP, pg + (slot - (TAPE_GROUP - 1)) * RB);
+        if constexpr (CKPT) {
+          if (need) store_state<T, D>(pg, yb);
+          s_h[(slot % H_GROUP) * 256 + threadIdx.x] = hh;
+          if (slot % H_GROUP == H_GROUP - 1)
+            flush_h(s_h, H_GROUP, pg + YB + (slot - (H_GROUP - 1)) * 8);
+        } else {
+          stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, yb);
+          if (slot % TAPE_GROUP == TAPE_GROUP - 1)
+            flush_recs<T, D>(s_tape, TAPE_GROUP, pg + (slot - (TAPE_GROUP - 1)) * RB);
+        }
       }
       ++S;
       tp = t;
@@ -632,10 +691,15 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
 
   // records of an unfinished group
   if constexpr (MODE != MODE_SOLVE) {
-    const int rem = S % TAPE_GROUP;
-    if (rem > 0 && pg != nullptr) {
-      const int slot0 = (S - rem) % K;
-      flush_recs<T, D>(s_tape, rem, pg + slot0 * RB);
+    if constexpr (CKPT) {
+      const int rem = S % H_GROUP;
+      if (rem > 0 && pg != nullptr) flush_h(s_h, rem, pg + YB + ((S - rem) % K) * 8);
+    } else {
+      const int rem = S % TAPE_GROUP;
+      if (rem > 0 && pg != nullptr) {
+        const int slot0 = (S - rem) % K;
+        flush_recs<T, D>(s_tape, rem, pg + slot0 * RB);
+      }
     }
   }
 
@@ -690,10 +754,17 @@ __device__ __forceinline__ void save_cotangent(const AdjArgs& a, int s,
   }
 }
 
-template <class Sys, class Tab, class T, bool SHARED>
+// CKPT: the tape holds one state per page (segment) and the step sizes; the
+// sweep first replays each segment forward into this trajectory's scratch
+// page (full step records, the same arithmetic as the record, so the same
+// bits), then walks it backward.  Replay steps and reverse steps share one
+// loop iteration so that lanes at different phases do not serialize.
+template <class Sys, class Tab, class T, bool SHARED, bool CKPT>
 __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
-  constexpr int D = Sys::D, NP = Sys::NP, K = PAGE_STEPS, SU = Tab::SU;
+  constexpr int D = Sys::D, NP = Sys::NP, SU = Tab::SU;
   constexpr int RB = TapeRec<T, D>::BYTES;
+  constexpr int YB = StateBytes<T, D>::BYTES;
+  const int K = CKPT ? a.rec.page_steps : PAGE_STEPS;
   const int64_t n = a.ivp.n;
   const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = tr < n;
@@ -738,17 +809,32 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
   int32_t i = S;
   int slot = S > 0 ? (S - 1) % K : 0;
 
+  // checkpointed tape: segment replay state
+  char* scr = CKPT ? (char*)a.scratch + (int64_t)tr * K * RB : nullptr;
+  bool rebuild = false;
+  int j_rb = 0, seg_len = 0;
+  T y_rb[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y_rb[c] = T(0);
+  auto start_segment = [&](int len) {
+    load_state<T, D>(R.pages + (int64_t)page * R.page_bytes, y_rb);
+    rebuild = true;
+    j_rb = 0;
+    seg_len = len;
+  };
+  if (CKPT && S > 0) start_segment(slot + 1);
+
   while (true) {
     // save states that coincide with the current mesh point
-    while (s >= 0 && sidx == i && sdt == 0.0) {
+    while (!rebuild && s >= 0 && sidx == i && sdt == 0.0) {
       T w[D];
       save_cotangent<T, D>(a, s, tr, ycur, two_scale, w, loss);
 #pragma unroll
       for (int c = 0; c < D; ++c) lam[c] = lam[c] + w[c];
       next_save();
     }
-    const bool side = (s >= 0 && sidx == i);
-    if (!side && i == 0) break;
+    const bool side = !rebuild && (s >= 0 && sidx == i);
+    if (!rebuild && !side && i == 0) break;
 
     T yb[D];
     double hh;
@@ -757,7 +843,15 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
 #pragma unroll
       for (int c = 0; c < D; ++c) yb[c] = ycur[c];
     } else {
-      load_rec<T, D>(R.pages + (int64_t)page * R.page_bytes + slot * RB, hh, yb);
+      if (CKPT && rebuild) {
+        hh = ((const double*)(R.pages + (int64_t)page * R.page_bytes + YB))[j_rb];
+#pragma unroll
+        for (int c = 0; c < D; ++c) yb[c] = y_rb[c];
+      } else if (CKPT) {
+        load_rec<T, D>(scr + slot * RB, hh, yb);
+      } else {
+        load_rec<T, D>(R.pages + (int64_t)page * R.page_bytes + slot * RB, hh, yb);
+      }
     }
 
     // recompute the stages of this step
@@ -765,6 +859,14 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
     Sys::rhs(yb, p, k0);
     step_push<Sys, Tab, T, SU, true, true, false>(yb, k0, p, T(hh), Y, ylast, klast, ys,
                                                   nullptr);
+    if (CKPT && rebuild) {
+      // one replay step of the segment: keep its record, move on
+      store_rec<T, D>(scr + j_rb * RB, hh, yb);
+#pragma unroll
+      for (int c = 0; c < D; ++c) y_rb[c] = ys[c];
+      if (++j_rb == seg_len) rebuild = false;
+      continue;
+    }
     T w[D];
     if (side) {
       save_cotangent<T, D>(a, s, tr, ys, two_scale, w, loss);
@@ -820,6 +922,7 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
       if (--slot < 0 && i > 0) {
         page = prev_page(R, page);
         slot = K - 1;
+        if (CKPT) start_segment(K);
       }
     }
   }

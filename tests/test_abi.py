@@ -107,8 +107,22 @@ def test_null_pointers_rejected_before_launch():
 def test_adjoint_workspace_plan():
     lib = _lib()
     out = C.c_size_t()
-    assert lib.ensemble_adjoint_workspace_bytes(C.byref(_prob()), C.byref(_ivp()), C.byref(out)) == 0
+    rec = A.Record(n=1024, system=A.SYS_LORENZ, method=A.TSIT5, dtype=A.F64, dim=3, nparams=3,
+                   params_shared=0, page_steps=16, ckpt_every=0)
+    assert lib.ensemble_adjoint_workspace_bytes(C.byref(rec), C.byref(out)) == 0
     assert out.value == 0
-    assert lib.ensemble_adjoint_workspace_bytes(C.byref(_prob(params_shared=1)), C.byref(_ivp()),
-                                                C.byref(out)) == 0
-    assert out.value == 4 * 3 * 8   # 1024 trajectories = 4 blocks x 3 params x 8 bytes
+    rec.params_shared = 1   # 4 blocks x 3 params x 8 bytes, 256-aligned
+    assert lib.ensemble_adjoint_workspace_bytes(C.byref(rec), C.byref(out)) == 0
+    assert out.value == 256
+    rec.params_shared, rec.ckpt_every, rec.page_steps = 0, 64, 64   # one 64-step segment each
+    assert lib.ensemble_adjoint_workspace_bytes(C.byref(rec), C.byref(out)) == 0
+    assert out.value == 1024 * 64 * 32
+
+
+def test_checkpoint_plan_is_smaller():
+    lib = _lib()
+    full, ck = C.c_size_t(), C.c_size_t()
+    assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(_ivp()), 640, 0, C.byref(full)) == 0
+    assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(_ivp()), 640, 64, C.byref(ck)) == 0
+    assert ck.value < full.value / 3
+    assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(_ivp()), 640, 48, C.byref(ck)) == A.ENS_EINVAL
