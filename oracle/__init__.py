@@ -48,6 +48,9 @@ def _load():
         lib.oracle_root_inv.argtypes = [D, I]
         lib.oracle_root_inv.restype = D
         lib.oracle_rhs.argtypes = [I, _d, _d, _d]
+        lib.oracle_jac.argtypes = [I, _d, _d, _d]
+        lib.oracle_jac_vjp.argtypes = [I, _d, _d, _d, _d, _d, _d]
+        lib.oracle_ros_tableau.argtypes = [_d, _d, _d, _d, C.POINTER(I), C.POINTER(I)]
         lib.oracle_vjp.argtypes = [I, _d, _d, _d, _d, _d]
         lib.oracle_record.argtypes = [I, I, I, I, _d, _d, D, D, D, D, D, L, I, _d, L,
                                       _d, _i32, _i32, _i32, _d, _d, _i64]
@@ -58,7 +61,8 @@ def _load():
                                               I, _i32, _d, _d, _d]
         lib.oracle_adjoint.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d,
                                        I, _d, D, _d, _d, _d]
-        for f in ("oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp",
+        for f in ("oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp", "oracle_jac",
+                  "oracle_jac_vjp", "oracle_ros_tableau",
                   "oracle_record", "oracle_replay", "oracle_replay_dual",
                   "oracle_replay_complex", "oracle_adjoint"):
             getattr(lib, f).restype = I
@@ -101,6 +105,32 @@ def rhs(system, y, p):
     f = np.zeros_like(y)
     _load().oracle_rhs(system, _p(y), _p(p), _p(f))
     return f
+
+
+def jac(system, y, p):
+    y, p = _f64(y), _f64(p)
+    d = len(y)
+    J = np.zeros(d * d)
+    if _load().oracle_jac(system, _p(y), _p(p), _p(J)) != 0:
+        raise ValueError("no Jacobian for this system")
+    return J.reshape(d, d)
+
+
+def jac_vjp(system, y, p, u, v):
+    """(d/dy, d/dp) of u^T J(y, p) v."""
+    y, p, u, v = _f64(y), _f64(p), _f64(u), _f64(v)
+    gy = np.zeros_like(y); gp = np.zeros_like(p)
+    if _load().oracle_jac_vjp(system, _p(y), _p(p), _p(u), _p(v), _p(gy), _p(gp)) != 0:
+        raise ValueError("no Jacobian for this system")
+    return gy, gp
+
+
+def ros_tableau():
+    g = C.c_double(); a = np.zeros(36); c = np.zeros(36); m = np.zeros(6)
+    o, q = C.c_int(), C.c_int()
+    s = _load().oracle_ros_tableau(C.byref(g), _p(a), _p(c), _p(m), C.byref(o), C.byref(q))
+    return dict(s=s, gamma=g.value, a=a.reshape(6, 6)[:s, :s].copy(),
+                c=c.reshape(6, 6)[:s, :s].copy(), m=m[:s].copy(), order=o.value, q_emb=q.value)
 
 
 def vjp(system, y, p, w):

@@ -190,12 +190,14 @@ static const ERK* erk_of(int method) {
 }
 
 // ---------------------------------------------------------------- systems --
-enum { SYS_LORENZ = 1, SYS_VDP = 2, SYS_LINEAR = 6 };
+enum { SYS_LORENZ = 1, SYS_VDP = 2, SYS_ROBERTSON = 3, SYS_HIRES = 4, SYS_LINEAR = 6 };
 
 static int sys_dim(int sys) {
   switch (sys) {
     case SYS_LORENZ: return 3;
     case SYS_VDP: return 2;
+    case SYS_ROBERTSON: return 3;
+    case SYS_HIRES: return 8;
     case SYS_LINEAR: return 2;
   }
   return -1;
@@ -204,6 +206,8 @@ static int sys_np(int sys) {
   switch (sys) {
     case SYS_LORENZ: return 3;
     case SYS_VDP: return 1;
+    case SYS_ROBERTSON: return 3;
+    case SYS_HIRES: return 12;
     case SYS_LINEAR: return 2;
   }
   return -1;
@@ -216,6 +220,7 @@ static int sys_np(int sys) {
 //    f0 = y1;  f1 = mu * fma(fma(-y0, y0, 1), y1, -y0)
 //  Linear (damped rotation y' = A y, A = [[-a, -w], [w, -a]])  p = (a, w):
 //    f0 = -fma(a, y0, w*y1);  f1 = fma(w, y0, -(a*y1))
+//  Robertson and HIRES: see below (stiff; also Jacobian and its VJP).
 template <class T, class P>
 static void rhs(int sys, const T* y, const P* p, T* f) {
   switch (sys) {
@@ -231,6 +236,94 @@ static void rhs(int sys, const T* y, const P* p, T* f) {
     case SYS_LINEAR: {
       f[0] = -fma(p[0], y[0], p[1] * y[1]);
       f[1] = fma(p[1], y[0], -(p[0] * y[1]));
+    } break;
+    case SYS_ROBERTSON: {
+      // p = (k1, k2, k3): a = k1 y0, b = k3 y1 y2, c = k2 y1^2
+      T a = p[0] * y[0];
+      T b = (p[2] * y[1]) * y[2];
+      T c = (p[1] * y[1]) * y[1];
+      f[0] = b - a;
+      f[1] = (a - b) - c;
+      f[2] = c;
+    } break;
+    case SYS_HIRES: {
+      // p = the twelve rate literals of Appendix A in order of first appearance
+      // (1.71, 0.43, 8.32, 0.0007, 8.75, 10.03, 0.035, 1.12, 1.745, 280, 0.69, 1.81)
+      f[0] = fma(p[2], y[2], fma(p[1], y[1], fma(-p[0], y[0], P(p[3]))));
+      f[1] = fma(p[0], y[0], -(p[4] * y[1]));
+      f[2] = fma(p[6], y[4], fma(p[1], y[3], -(p[5] * y[2])));
+      f[3] = fma(p[2], y[1], fma(p[0], y[2], -(p[7] * y[3])));
+      f[4] = fma(p[1], y[6], fma(p[1], y[5], -(p[8] * y[4])));
+      T z = (p[9] * y[5]) * y[7];
+      f[5] = fma(p[10], y[6], fma(-p[1], y[5], fma(p[0], y[4], fma(p[10], y[3], -z))));
+      f[6] = fma(-p[11], y[6], z);
+      f[7] = -f[6];
+    } break;
+  }
+}
+
+// Jacobian J = df/dy (row-major d x d) of the stiff systems.
+template <class T, class P>
+static void jac(int sys, const T* y, const P* p, T* J) {
+  switch (sys) {
+    case SYS_LINEAR: {
+      J[0] = -p[0]; J[1] = -p[1];
+      J[2] = p[1];  J[3] = -p[0];
+    } break;
+    case SYS_ROBERTSON: {
+      T s2 = p[2] * y[2], s1 = p[2] * y[1], q = p[1] * y[1];
+      J[0] = -p[0]; J[1] = s2;            J[2] = s1;
+      J[3] = p[0];  J[4] = -s2 - (q + q); J[5] = -s1;
+      J[6] = T(0.0); J[7] = q + q;        J[8] = T(0.0);
+    } break;
+    case SYS_HIRES: {
+      for (int i = 0; i < 64; ++i) J[i] = T(0.0);
+      T a = p[9] * y[7], b = p[9] * y[5];
+      J[0 * 8 + 0] = -p[0]; J[0 * 8 + 1] = p[1]; J[0 * 8 + 2] = p[2];
+      J[1 * 8 + 0] = p[0];  J[1 * 8 + 1] = -p[4];
+      J[2 * 8 + 2] = -p[5]; J[2 * 8 + 3] = p[1]; J[2 * 8 + 4] = p[6];
+      J[3 * 8 + 1] = p[2];  J[3 * 8 + 2] = p[0]; J[3 * 8 + 3] = -p[7];
+      J[4 * 8 + 4] = -p[8]; J[4 * 8 + 5] = p[1]; J[4 * 8 + 6] = p[1];
+      J[5 * 8 + 3] = p[10]; J[5 * 8 + 4] = p[0]; J[5 * 8 + 5] = -a - p[1];
+      J[5 * 8 + 6] = p[10]; J[5 * 8 + 7] = -b;
+      J[6 * 8 + 5] = a;     J[6 * 8 + 6] = -p[11]; J[6 * 8 + 7] = b;
+      J[7 * 8 + 5] = -a;    J[7 * 8 + 6] = p[11];  J[7 * 8 + 7] = -b;
+    } break;
+  }
+}
+
+// d/d(y, p) of G = u^T J(y, p) v, accumulated into gy and gp.
+static void jac_vjp(int sys, const double* y, const double* p, const double* u,
+                    const double* v, double* gy, double* gp) {
+  switch (sys) {
+    case SYS_LINEAR: {
+      gp[0] = gp[0] - fma(u[0], v[0], u[1] * v[1]);
+      gp[1] = gp[1] + fma(u[1], v[0], -(u[0] * v[1]));
+    } break;
+    case SYS_ROBERTSON: {
+      double du = u[0] - u[1];
+      double t = (p[1] + p[1]) * (v[1] * (u[2] - u[1]));
+      gy[1] = gy[1] + fma(p[2] * v[2], du, t);
+      gy[2] = gy[2] + (p[2] * v[1]) * du;
+      gp[0] = gp[0] + v[0] * (u[1] - u[0]);
+      gp[1] = gp[1] + (y[1] + y[1]) * (v[1] * (u[2] - u[1]));
+      gp[2] = gp[2] + du * fma(y[2], v[1], y[1] * v[2]);
+    } break;
+    case SYS_HIRES: {
+      double du = (u[6] - u[5]) - u[7];
+      gy[5] = gy[5] + (p[9] * v[7]) * du;
+      gy[7] = gy[7] + (p[9] * v[5]) * du;
+      gp[0] = gp[0] + fma(u[5], v[4], fma(u[3], v[2], v[0] * (u[1] - u[0])));
+      gp[1] = gp[1] + fma(u[4], v[5] + v[6], fma(u[2], v[3], fma(u[0], v[1], -(u[5] * v[5]))));
+      gp[2] = gp[2] + fma(u[0], v[2], u[3] * v[1]);
+      gp[4] = gp[4] - u[1] * v[1];
+      gp[5] = gp[5] - u[2] * v[2];
+      gp[6] = gp[6] + u[2] * v[4];
+      gp[7] = gp[7] - u[3] * v[3];
+      gp[8] = gp[8] - u[4] * v[4];
+      gp[9] = gp[9] + du * fma(y[7], v[5], y[5] * v[7]);
+      gp[10] = gp[10] + u[5] * (v[3] + v[6]);
+      gp[11] = gp[11] + v[6] * (u[7] - u[6]);
     } break;
   }
 }
@@ -271,6 +364,38 @@ static void vjp(int sys, const double* y, const double* p, const double* w,
       gy[1] = -fma(p[1], w[0], p[0] * w[1]);
       gp[0] = gp[0] - fma(y[0], w[0], y[1] * w[1]);
       gp[1] = gp[1] + fma(y[0], w[1], -(y[1] * w[0]));
+    } break;
+    case SYS_ROBERTSON: {
+      double s2 = p[2] * y[2], s1 = p[2] * y[1], q = p[1] * y[1];
+      gy[0] = p[0] * (w[1] - w[0]);
+      gy[1] = fma(s2, w[0] - w[1], (q + q) * (w[2] - w[1]));
+      gy[2] = s1 * (w[0] - w[1]);
+      gp[0] = fma(y[0], w[1] - w[0], gp[0]);
+      gp[1] = fma(y[1] * y[1], w[2] - w[1], gp[1]);
+      gp[2] = fma(y[1] * y[2], w[0] - w[1], gp[2]);
+    } break;
+    case SYS_HIRES: {
+      double a = p[9] * y[7], b = p[9] * y[5];
+      gy[0] = p[0] * (w[1] - w[0]);
+      gy[1] = fma(p[2], w[3], fma(p[1], w[0], -(p[4] * w[1])));
+      gy[2] = fma(p[0], w[3], fma(p[2], w[0], -(p[5] * w[2])));
+      gy[3] = fma(p[10], w[5], fma(p[1], w[2], -(p[7] * w[3])));
+      gy[4] = fma(p[0], w[5], fma(p[6], w[2], -(p[8] * w[4])));
+      gy[5] = fma(a, (w[6] - w[7]) - w[5], p[1] * (w[4] - w[5]));
+      gy[6] = fma(p[11], w[7] - w[6], fma(p[10], w[5], p[1] * w[4]));
+      gy[7] = b * ((w[6] - w[5]) - w[7]);
+      gp[0] = gp[0] + fma(y[4], w[5], fma(y[2], w[3], y[0] * (w[1] - w[0])));
+      gp[1] = gp[1] + fma(y[5] + y[6], w[4], fma(y[3], w[2], fma(y[1], w[0], -(y[5] * w[5]))));
+      gp[2] = gp[2] + fma(y[2], w[0], y[1] * w[3]);
+      gp[3] = gp[3] + w[0];
+      gp[4] = gp[4] - y[1] * w[1];
+      gp[5] = gp[5] - y[2] * w[2];
+      gp[6] = gp[6] + y[4] * w[2];
+      gp[7] = gp[7] - y[3] * w[3];
+      gp[8] = gp[8] - y[4] * w[4];
+      gp[9] = gp[9] + (y[5] * y[7]) * ((w[6] - w[5]) - w[7]);
+      gp[10] = gp[10] + (y[3] + y[6]) * w[5];
+      gp[11] = gp[11] + y[6] * (w[7] - w[6]);
     } break;
   }
 }
@@ -557,10 +682,13 @@ struct MeshArgs {
 };
 
 // Replay one lane in scalar type T; writes the save-time states.
+// One replay step Phi(y; h) of the chosen method.
+template <class T, class P>
+static void phi_any(int method, int sys, int d, const T* y, const P* p, T h, T* ynew);
+
 template <class T>
 static void replay_lane(const MeshArgs& M, int lane, const T* y0, const T* p,
                         T* ysave /*[n_save][d]*/) {
-  const ERK& m = *erk_of(M.method);
   const int d = M.d;
   const double* hrow = M.h + (int64_t)lane * M.cap;
   const int32_t* sidx = M.save_idx + (int64_t)lane * M.n_save;
@@ -572,12 +700,12 @@ static void replay_lane(const MeshArgs& M, int lane, const T* y0, const T* p,
   for (int i = 0; i <= S; ++i) {
     // saves whose base is y_i
     while (s < M.n_save && sidx[s] == i) {
-      erk_phi(m, M.sys, d, y, p, T(sdt[s]), ysave + s * d);
+      phi_any(M.method, M.sys, d, y, p, T(sdt[s]), ysave + s * d);
       ++s;
     }
     if (i == S) break;
     T yn[DMAX];
-    erk_phi(m, M.sys, d, y, p, T(hrow[i]), yn);
+    phi_any(M.method, M.sys, d, y, p, T(hrow[i]), yn);
     for (int c = 0; c < d; ++c) y[c] = yn[c];
   }
 }
@@ -625,10 +753,12 @@ struct LossArgs {
 // Discrete adjoint of one lane: gradient of the lane's loss with respect to
 // its parameters (gp, accumulated) and its initial state (gy0).  Returns the
 // lane's loss.
+static void step_vjp_any(int method, int sys, int d, const double* y, const double* p,
+                         double h, const double* lam, double* lam_in, double* gp);
+
 static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
                            const double* y0, const double* p, double* gp,
                            double* gy0) {
-  const ERK& m = *erk_of(M.method);
   const int d = M.d;
   const int S = M.S[lane];
   const double* hrow = M.h + (int64_t)lane * M.cap;
@@ -640,12 +770,12 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
   std::vector<double> ys((size_t)(S + 1) * d);
   for (int c = 0; c < d; ++c) ys[c] = y0[c];
   for (int i = 0; i < S; ++i)
-    erk_phi(m, M.sys, d, &ys[(size_t)i * d], p, hrow[i], &ys[(size_t)(i + 1) * d]);
+    phi_any(M.method, M.sys, d, &ys[(size_t)i * d], p, hrow[i], &ys[(size_t)(i + 1) * d]);
 
   // save-time states (one extra step from the base mesh point)
   std::vector<double> ysave((size_t)M.n_save * d);
   for (int s = 0; s < M.n_save; ++s)
-    erk_phi(m, M.sys, d, &ys[(size_t)sidx[s] * d], p, sdt[s], &ysave[(size_t)s * d]);
+    phi_any(M.method, M.sys, d, &ys[(size_t)sidx[s] * d], p, sdt[s], &ysave[(size_t)s * d]);
 
   // loss and save-time cotangents
   double loss = 0.0;
@@ -674,17 +804,313 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
   for (int i = S; i >= 0; --i) {
     while (s >= 0 && sidx[s] == i) {
       double li[DMAX];
-      erk_step_vjp(m, M.sys, d, &ys[(size_t)i * d], p, sdt[s], &wbar[s * d], li, gp);
+      step_vjp_any(M.method, M.sys, d, &ys[(size_t)i * d], p, sdt[s], &wbar[s * d], li, gp);
       for (int c = 0; c < d; ++c) lam[c] = lam[c] + li[c];
       --s;
     }
     if (i == 0) break;
     double li[DMAX];
-    erk_step_vjp(m, M.sys, d, &ys[(size_t)(i - 1) * d], p, hrow[i - 1], lam, li, gp);
+    step_vjp_any(M.method, M.sys, d, &ys[(size_t)(i - 1) * d], p, hrow[i - 1], lam, li, gp);
     for (int c = 0; c < d; ++c) lam[c] = li[c];
   }
   for (int c = 0; c < d; ++c) gy0[c] = lam[c];
   return loss;
+}
+
+// ============================================================ Rosenbrock ==
+// Rodas4 (Hairer & Wanner, Solving ODEs II, Sec. IV.7): a stiffly accurate,
+// L-stable Rosenbrock-Wanner method of order 4 with an embedded order-3
+// solution, in the transformed form with W = I/(gamma h) - J (J = df/dy at
+// the step's start, the systems are autonomous):
+//   Y_i = y + sum_{j<i} a_ij u_j,   W u_i = f(Y_i) + (1/h) sum_{j<i} c_ij u_j,
+//   y_new = Y_6 + u_6,   error estimate e = u_6.
+struct ROS {
+  int s, order, q_emb;
+  double gamma;
+  double a[6][6];
+  double c[6][6];
+  double m[6];
+};
+
+static ROS make_rodas4() {
+  ROS r{};
+  r.s = 6; r.order = 4; r.q_emb = 3; r.gamma = 0.25;
+  r.a[1][0] = 1.544;
+  r.a[2][0] = 0.9466785280815826;  r.a[2][1] = 0.2557011698983284;
+  r.a[3][0] = 3.314825187068521;   r.a[3][1] = 2.896124015972201;
+  r.a[3][2] = 0.9986419139977817;
+  r.a[4][0] = 1.221224509226641;   r.a[4][1] = 6.019134481288629;
+  r.a[4][2] = 12.53708332932087;   r.a[4][3] = -0.6878860361058950;
+  for (int j = 0; j < 4; ++j) r.a[5][j] = r.a[4][j];
+  r.a[5][4] = 1.0;
+  r.c[1][0] = -5.6688;
+  r.c[2][0] = -2.430093356833875;  r.c[2][1] = -0.2063599157091915;
+  r.c[3][0] = -0.1073529058151375; r.c[3][1] = -9.594562251023355;
+  r.c[3][2] = -20.47028614809616;
+  r.c[4][0] = 7.496443313967647;   r.c[4][1] = -10.24680431464352;
+  r.c[4][2] = -33.99990352819905;  r.c[4][3] = 11.70890893206160;
+  r.c[5][0] = 8.083246795921522;   r.c[5][1] = -7.981132988064893;
+  r.c[5][2] = -31.52159432874371;  r.c[5][3] = 16.31930543123136;
+  r.c[5][4] = -6.058818238834054;
+  for (int j = 0; j < 5; ++j) r.m[j] = r.a[5][j];
+  r.m[5] = 1.0;
+  return r;
+}
+static const ROS RODAS4 = make_rodas4();
+static bool is_ros(int method) { return method == 3; }
+
+inline double absval(double x) { return std::fabs(x); }
+inline double absval(Dual x) { return std::fabs(x.v); }
+inline double absval(Cplx x) { return std::fabs(x.real()); }
+
+// LU factorisation with partial pivoting, in place (row-major d x d).  The
+// pivot of column k is the first row i >= k with the largest |W_ik| (ties go
+// to the lowest row); the permutation only depends on values, so it is the
+// same in every scalar type.  l_ik = W_ik / W_kk, W_ij = fma(-l_ik, W_kj, W_ij).
+template <class T>
+static void lu_factor(int d, T* W, int* perm) {
+  for (int i = 0; i < d; ++i) perm[i] = i;
+  for (int k = 0; k < d; ++k) {
+    int piv = k;
+    double best = absval(W[k * d + k]);
+    for (int i = k + 1; i < d; ++i)
+      if (absval(W[i * d + k]) > best) { best = absval(W[i * d + k]); piv = i; }
+    if (piv != k) {
+      for (int j = 0; j < d; ++j) std::swap(W[k * d + j], W[piv * d + j]);
+      std::swap(perm[k], perm[piv]);
+    }
+    for (int i = k + 1; i < d; ++i) {
+      T l = W[i * d + k] / W[k * d + k];
+      W[i * d + k] = l;
+      for (int j = k + 1; j < d; ++j) W[i * d + j] = fma(-l, W[k * d + j], W[i * d + j]);
+    }
+  }
+}
+
+// Solve W x = b with the factors (x may not alias b).
+template <class T>
+static void lu_solve(int d, const T* LU, const int* perm, const T* b, T* x) {
+  for (int i = 0; i < d; ++i) {
+    T acc = b[perm[i]];
+    for (int j = 0; j < i; ++j) acc = fma(-LU[i * d + j], x[j], acc);
+    x[i] = acc;
+  }
+  for (int i = d - 1; i >= 0; --i) {
+    T acc = x[i];
+    for (int j = i + 1; j < d; ++j) acc = fma(-LU[i * d + j], x[j], acc);
+    x[i] = acc / LU[i * d + i];
+  }
+}
+
+// Solve W^T z = b with the factors: U^T v = b, L^T w = v, z[perm[i]] = w[i].
+static void lu_solve_t(int d, const double* LU, const int* perm, const double* b, double* z) {
+  double v[DMAX];
+  for (int i = 0; i < d; ++i) {
+    double acc = b[i];
+    for (int j = 0; j < i; ++j) acc = fma(-LU[j * d + i], v[j], acc);
+    v[i] = acc / LU[i * d + i];
+  }
+  for (int i = d - 1; i >= 0; --i) {
+    double acc = v[i];
+    for (int j = i + 1; j < d; ++j) acc = fma(-LU[j * d + i], v[j], acc);
+    v[i] = acc;
+  }
+  for (int i = 0; i < d; ++i) z[perm[i]] = v[i];
+}
+
+// One Rodas4 step from y with step h; stage inputs Y, increments u and the
+// factors are returned for the reverse sweep.  y_new = Y_6 + u_6.
+template <class T, class P>
+static void ros_step(int sys, int d, const T* y, const P* p, T h, T* ynew,
+                     T Y[6][DMAX], T u[6][DMAX], T* LU, int* perm) {
+  const ROS& m = RODAS4;
+  jac(sys, y, p, LU);
+  const T dg = T(1.0) / (T(m.gamma) * h);
+  for (int i = 0; i < d * d; ++i) LU[i] = -LU[i];
+  for (int i = 0; i < d; ++i) LU[i * d + i] = LU[i * d + i] + dg;
+  lu_factor(d, LU, perm);
+  const T hinv = T(1.0) / h;
+  for (int i = 0; i < m.s; ++i) {
+    T F[DMAX], r[DMAX];
+    for (int c = 0; c < d; ++c) {
+      T acc = T(0.0);
+      bool first = true;
+      for (int j = 0; j < i; ++j) {
+        if (m.a[i][j] == 0.0) continue;
+        if (first) { acc = T(m.a[i][j]) * u[j][c]; first = false; }
+        else acc = fma(T(m.a[i][j]), u[j][c], acc);
+      }
+      Y[i][c] = first ? y[c] : y[c] + acc;
+    }
+    rhs(sys, Y[i], p, F);
+    for (int c = 0; c < d; ++c) {
+      T acc = T(0.0);
+      bool first = true;
+      for (int j = 0; j < i; ++j) {
+        if (m.c[i][j] == 0.0) continue;
+        if (first) { acc = T(m.c[i][j]) * u[j][c]; first = false; }
+        else acc = fma(T(m.c[i][j]), u[j][c], acc);
+      }
+      r[c] = first ? F[c] : fma(acc, hinv, F[c]);
+    }
+    lu_solve(d, LU, perm, r, u[i]);
+  }
+  for (int c = 0; c < d; ++c) ynew[c] = Y[m.s - 1][c] + u[m.s - 1][c];
+}
+
+template <class T, class P>
+static void ros_phi(int sys, int d, const T* y, const P* p, T h, T* ynew) {
+  if (value_of(h) == 0.0) {  // a zero-length step is the identity (skipped)
+    for (int c = 0; c < d; ++c) ynew[c] = y[c];
+    return;
+  }
+  T Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
+  int perm[DMAX];
+  ros_step(sys, d, y, p, h, ynew, Y, u, LU, perm);
+}
+
+static void ros_record_lane(const RecordArgs& A, int lane) {
+  const ROS& m = RODAS4;
+  const int d = A.d, sys = A.sys;
+  const double* p = A.params_shared ? A.p : A.p + (int64_t)lane * A.np;
+  double y[DMAX], f0[DMAX];
+  for (int c = 0; c < d; ++c) y[c] = A.y0[(int64_t)lane * d + c];
+  double* hrow = A.h_out + (int64_t)lane * A.cap;
+  int32_t* sidx = A.save_idx + (int64_t)lane * A.n_save;
+  double* sdt = A.save_dt + (int64_t)lane * A.n_save;
+  double* ysv = A.y_save + (int64_t)lane * A.n_save * d;
+  for (int s = 0; s < A.n_save; ++s) {
+    sidx[s] = -1;
+    sdt[s] = NAN;
+    for (int c = 0; c < d; ++c) ysv[s * d + c] = NAN;
+  }
+  rhs(sys, y, p, f0);
+  int status = ST_OK;
+  for (int c = 0; c < d; ++c)
+    if (!std::isfinite(y[c]) || !std::isfinite(f0[c])) status = ST_NONFINITE;
+  double t = A.t0;
+  // starting step as for the explicit pairs, with the method's order
+  ERK pseudo{};
+  pseudo.order = m.order;
+  double h = A.h0 > 0.0 ? std::fmin(A.h0, A.t1 - A.t0)
+                        : initial_step(pseudo, sys, d, y, p, f0, A.t0, A.t1, A.rtol, A.atol);
+  const int kroot = m.q_emb + 1;
+  int64_t S = 0, trials = 0;
+  int next_save = 0;
+  bool prev_rejected = false;
+  while (status == ST_OK && t < A.t1) {
+    if (trials >= A.max_steps) { status = ST_MAX_STEPS; break; }
+    if (h < 16.0 * 2.220446049250313e-16 * std::fmax(std::fabs(t), 1.0)) {
+      status = ST_DT_UNDERFLOW;
+      break;
+    }
+    ++trials;
+    bool last = false;
+    if (t + h >= A.t1) { h = A.t1 - t; last = true; }
+    double ynew[DMAX], Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
+    int perm[DMAX];
+    ros_step(sys, d, y, p, h, ynew, Y, u, LU, perm);
+    double sc[DMAX];
+    for (int c = 0; c < d; ++c)
+      sc[c] = fma(A.rtol, std::fmax(std::fabs(y[c]), std::fabs(ynew[c])), A.atol);
+    const double err = rms_norm(d, u[m.s - 1], sc);
+    const double fac0 = 0.9 * root_inv(err, kroot);
+    if (err <= 1.0) {
+      if (S >= A.cap) { status = ST_NOSPACE; break; }
+      hrow[S] = h;
+      double tnew = last ? A.t1 : t + h;
+      while (next_save < A.n_save && A.save_t[next_save] < tnew) {
+        double dt = A.save_t[next_save] - t;
+        double ys[DMAX];
+        ros_phi(sys, d, y, p, dt, ys);
+        sidx[next_save] = (int32_t)S;
+        sdt[next_save] = dt;
+        for (int c = 0; c < d; ++c) ysv[next_save * d + c] = ys[c];
+        ++next_save;
+      }
+      ++S;
+      t = tnew;
+      for (int c = 0; c < d; ++c) y[c] = ynew[c];
+      h = h * std::fmax(0.2, std::fmin(prev_rejected ? 1.0 : 10.0, fac0));
+      prev_rejected = false;
+    } else {
+      h = h * std::fmax(0.2, fac0);
+      prev_rejected = true;
+    }
+  }
+  if (status == ST_OK) {
+    while (next_save < A.n_save) {
+      sidx[next_save] = (int32_t)S;
+      sdt[next_save] = A.save_t[next_save] - t;
+      double ys[DMAX];
+      ros_phi(sys, d, y, p, sdt[next_save], ys);
+      for (int c = 0; c < d; ++c) ysv[next_save * d + c] = ys[c];
+      ++next_save;
+    }
+  }
+  A.S_out[lane] = (int32_t)S;
+  A.status_out[lane] = status;
+  A.n_trial[lane] = trials;
+}
+
+// Reverse sweep through one Rodas4 step with output cotangent lam:
+//   ubar_i = m_i lam + sum_{l>i} (a_li Ybar_l + c_li t_l),  t_l = rbar_l / h
+//   rbar_i = W^{-T} ubar_i,  Ybar_i = J(Y_i)^T rbar_i,  p_bar += f_p(Y_i)^T rbar_i
+//   lam_in = lam + sum_i Ybar_i + d/dy sum_i rbar_i^T J(y) u_i  (J is at y)
+// with p_bar also receiving d/dp of sum_i rbar_i^T J u_i.  Stages run i = 6..1.
+static void ros_step_vjp(int sys, int d, const double* y, const double* p, double h,
+                         const double* lam, double* lam_in, double* gp) {
+  const ROS& m = RODAS4;
+  if (h == 0.0) {
+    for (int c = 0; c < d; ++c) lam_in[c] = lam[c];
+    return;
+  }
+  double ynew[DMAX], Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
+  int perm[DMAX];
+  ros_step(sys, d, y, p, h, ynew, Y, u, LU, perm);
+  const double hinv = 1.0 / h;
+  double Yb[6][DMAX], rb[6][DMAX], tb[6][DMAX];
+  for (int c = 0; c < d; ++c) lam_in[c] = lam[c];
+  for (int i = m.s - 1; i >= 0; --i) {
+    double ub[DMAX];
+    for (int c = 0; c < d; ++c) {
+      double acc = 0.0;
+      bool first = true;
+      if (m.m[i] != 0.0) { acc = m.m[i] * lam[c]; first = false; }
+      for (int l = i + 1; l < m.s; ++l) {
+        if (m.a[l][i] != 0.0) {
+          if (first) { acc = m.a[l][i] * Yb[l][c]; first = false; }
+          else acc = fma(m.a[l][i], Yb[l][c], acc);
+        }
+        if (m.c[l][i] != 0.0) {
+          if (first) { acc = m.c[l][i] * tb[l][c]; first = false; }
+          else acc = fma(m.c[l][i], tb[l][c], acc);
+        }
+      }
+      ub[c] = acc;
+    }
+    lu_solve_t(d, LU, perm, ub, rb[i]);
+    for (int c = 0; c < d; ++c) tb[i][c] = hinv * rb[i][c];
+    vjp(sys, Y[i], p, rb[i], Yb[i], gp);
+    for (int c = 0; c < d; ++c) lam_in[c] = lam_in[c] + Yb[i][c];
+  }
+  double gJ[DMAX];
+  for (int c = 0; c < d; ++c) gJ[c] = 0.0;
+  for (int i = m.s - 1; i >= 0; --i) jac_vjp(sys, y, p, rb[i], u[i], gJ, gp);
+  for (int c = 0; c < d; ++c) lam_in[c] = lam_in[c] + gJ[c];
+}
+
+// ------------------------------------------------------- method dispatch --
+template <class T, class P>
+static void phi_any(int method, int sys, int d, const T* y, const P* p, T h, T* ynew) {
+  if (is_ros(method)) ros_phi(sys, d, y, p, h, ynew);
+  else erk_phi(*erk_of(method), sys, d, y, p, h, ynew);
+}
+
+static void step_vjp_any(int method, int sys, int d, const double* y, const double* p,
+                         double h, const double* lam, double* lam_in, double* gp) {
+  if (is_ros(method)) ros_step_vjp(sys, d, y, p, h, lam, lam_in, gp);
+  else erk_step_vjp(*erk_of(method), sys, d, y, p, h, lam, lam_in, gp);
 }
 
 }  // namespace orc
@@ -724,6 +1150,36 @@ int oracle_rhs(int sys, const double* y, const double* p, double* f) {
   return 0;
 }
 
+int oracle_jac(int sys, const double* y, const double* p, double* J) {
+  if (sys != SYS_ROBERTSON && sys != SYS_HIRES && sys != SYS_LINEAR) return -1;
+  jac(sys, y, p, J);
+  return 0;
+}
+
+int oracle_jac_vjp(int sys, const double* y, const double* p, const double* u,
+                   const double* v, double* gy, double* gp) {
+  if (sys != SYS_ROBERTSON && sys != SYS_HIRES && sys != SYS_LINEAR) return -1;
+  jac_vjp(sys, y, p, u, v, gy, gp);
+  return 0;
+}
+
+// Rodas4 in transformed form: gamma, a[s*s], c[s*s], m[s]; returns s.
+int oracle_ros_tableau(double* gamma, double* a, double* c, double* m, int* order,
+                       int* q_emb) {
+  const ROS& r = RODAS4;
+  *gamma = r.gamma;
+  for (int i = 0; i < r.s; ++i) {
+    m[i] = r.m[i];
+    for (int j = 0; j < r.s; ++j) {
+      a[i * r.s + j] = r.a[i][j];
+      c[i * r.s + j] = r.c[i][j];
+    }
+  }
+  *order = r.order;
+  *q_emb = r.q_emb;
+  return r.s;
+}
+
 int oracle_vjp(int sys, const double* y, const double* p, const double* w,
                double* gy, double* gp) {
   if (sys_dim(sys) < 0) return -1;
@@ -737,14 +1193,17 @@ int oracle_record(int sys, int method, int n, int params_shared,
                   int n_save, const double* save_t, int64_t cap, double* h_out,
                   int32_t* S_out, int32_t* status_out, int32_t* save_idx,
                   double* save_dt, double* y_save, int64_t* n_trial) {
-  if (sys_dim(sys) < 0 || !erk_of(method) || n < 0 || n_save < 1 ||
+  if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method)) || n < 0 || n_save < 1 ||
       n_save > 64)
     return -1;
   RecordArgs A{sys, method, n, sys_dim(sys), sys_np(sys), params_shared,
                y0, p, t0, t1, rtol, atol, h0, max_steps, n_save, save_t, cap,
                h_out, S_out, status_out, save_idx, save_dt, y_save, n_trial};
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int l = 0; l < n; ++l) record_lane(A, l);
+  for (int l = 0; l < n; ++l) {
+    if (is_ros(method)) ros_record_lane(A, l);
+    else record_lane(A, l);
+  }
   return 0;
 }
 
@@ -762,7 +1221,7 @@ int oracle_replay(int sys, int method, int n, int params_shared,
                   const double* h, const int32_t* S, int n_save,
                   const int32_t* save_idx, const double* save_dt,
                   double* y_save) {
-  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, params_shared, cap, h, S, n_save,
                          save_idx, save_dt);
   const int d = M.d, np = M.np;
@@ -782,17 +1241,18 @@ int oracle_replay_dual(int sys, int method, int n, const double* y0,
                        int64_t cap, const double* h, const int32_t* S,
                        int n_save, const int32_t* save_idx,
                        const double* save_dt, double* y_save, double* dy_save) {
-  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, 0, cap, h, S, n_save, save_idx, save_dt);
   const int d = M.d, np = M.np;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int l = 0; l < n; ++l) {
-    Dual y[DMAX], pp[DMAX], out[64 * DMAX];
+    Dual y[DMAX], out[64 * DMAX];
+    std::vector<Dual> pp(np);
     for (int c = 0; c < d; ++c)
       y[c] = Dual(y0[(int64_t)l * d + c], dy0[(int64_t)l * d + c]);
     for (int c = 0; c < np; ++c)
       pp[c] = Dual(p[(int64_t)l * np + c], dp[(int64_t)l * np + c]);
-    replay_lane<Dual>(M, l, y, pp, out);
+    replay_lane<Dual>(M, l, y, pp.data(), out);
     for (int i = 0; i < n_save * d; ++i) {
       y_save[(int64_t)l * n_save * d + i] = out[i].v;
       dy_save[(int64_t)l * n_save * d + i] = out[i].d;
@@ -808,17 +1268,18 @@ int oracle_replay_complex(int sys, int method, int n, const double* y0,
                           double eps, int64_t cap, const double* h,
                           const int32_t* S, int n_save, const int32_t* save_idx,
                           const double* save_dt, double* re, double* im) {
-  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, 0, cap, h, S, n_save, save_idx, save_dt);
   const int d = M.d, np = M.np;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int l = 0; l < n; ++l) {
-    Cplx y[DMAX], pp[DMAX], out[64 * DMAX];
+    Cplx y[DMAX], out[64 * DMAX];
+    std::vector<Cplx> pp(np);
     for (int c = 0; c < d; ++c)
       y[c] = Cplx(y0[(int64_t)l * d + c], eps * dy0[(int64_t)l * d + c]);
     for (int c = 0; c < np; ++c)
       pp[c] = Cplx(p[(int64_t)l * np + c], eps * dp[(int64_t)l * np + c]);
-    replay_lane<Cplx>(M, l, y, pp, out);
+    replay_lane<Cplx>(M, l, y, pp.data(), out);
     for (int i = 0; i < n_save * d; ++i) {
       re[(int64_t)l * n_save * d + i] = out[i].real();
       im[(int64_t)l * n_save * d + i] = out[i].imag();
@@ -837,7 +1298,7 @@ int oracle_adjoint(int sys, int method, int n, int params_shared,
                    int loss_kind, const double* loss_data,
                    double loss_scale, double* grad_p, double* grad_y0,
                    double* loss_lane) {
-  if (sys_dim(sys) < 0 || !erk_of(method)) return -1;
+  if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, params_shared, cap, h, S, n_save,
                          save_idx, save_dt);
   LossArgs L{loss_kind, loss_data, loss_scale};
