@@ -1057,7 +1057,8 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
 //   ubar_i = m_i lam + sum_{l>i} (a_li Ybar_l + c_li t_l),  t_l = rbar_l / h
 //   rbar_i = W^{-T} ubar_i,  Ybar_i = J(Y_i)^T rbar_i,  p_bar += f_p(Y_i)^T rbar_i
 //   lam_in = lam + sum_i Ybar_i + d/dy sum_i rbar_i^T J(y) u_i  (J is at y)
-// with p_bar also receiving d/dp of sum_i rbar_i^T J u_i.  Stages run i = 6..1.
+// with p_bar also receiving d/dp of rbar_i^T J u_i.  Stages run i = 6..1 and
+// each stage adds its f_p term, then its J_p term, to p_bar.
 static void ros_step_vjp(int sys, int d, const double* y, const double* p, double h,
                          const double* lam, double* lam_in, double* gp) {
   const ROS& m = RODAS4;
@@ -1069,8 +1070,11 @@ static void ros_step_vjp(int sys, int d, const double* y, const double* p, doubl
   int perm[DMAX];
   ros_step(sys, d, y, p, h, ynew, Y, u, LU, perm);
   const double hinv = 1.0 / h;
-  double Yb[6][DMAX], rb[6][DMAX], tb[6][DMAX];
-  for (int c = 0; c < d; ++c) lam_in[c] = lam[c];
+  double Yb[6][DMAX], rb[6][DMAX], tb[6][DMAX], gJ[DMAX];
+  for (int c = 0; c < d; ++c) {
+    lam_in[c] = lam[c];
+    gJ[c] = 0.0;
+  }
   for (int i = m.s - 1; i >= 0; --i) {
     double ub[DMAX];
     for (int c = 0; c < d; ++c) {
@@ -1093,10 +1097,8 @@ static void ros_step_vjp(int sys, int d, const double* y, const double* p, doubl
     for (int c = 0; c < d; ++c) tb[i][c] = hinv * rb[i][c];
     vjp(sys, Y[i], p, rb[i], Yb[i], gp);
     for (int c = 0; c < d; ++c) lam_in[c] = lam_in[c] + Yb[i][c];
+    jac_vjp(sys, y, p, rb[i], u[i], gJ, gp);
   }
-  double gJ[DMAX];
-  for (int c = 0; c < d; ++c) gJ[c] = 0.0;
-  for (int i = m.s - 1; i >= 0; --i) jac_vjp(sys, y, p, rb[i], u[i], gJ, gp);
   for (int c = 0; c < d; ++c) lam_in[c] = lam_in[c] + gJ[c];
 }
 
