@@ -456,13 +456,15 @@ static void erk_phi(const ERK& m, int sys, int d, const T* y, const P* p, T h,
 }
 
 // ------------------------------------------------------- controller power --
-// x^(-1/k) for the step-size controller and the starting step, k = 5..8,
+// x^(-1/k) for the step-size controller and the starting step, k = 4..8,
 // from operations that are exactly or correctly rounded (frexp, ldexp, +, *,
 // fma) so that any implementation following the same sequence obtains the
 // same bits.  x = m 2^e with m in [0.5, 1) and e = k q + j; a linear first
 // guess for m^(-1/k) is scaled by 2^(-j/k) 2^(-q), then four Newton steps
 // y <- y + (y / k) (1 - x y^k) on f(y) = y^(-k) - x.  Arguments below
 // 1e-300 are raised to it (the controller clamps the factor long before).
+static const double TWO_NEG_4[4] = {1.0, 0.8408964152537145, 0.7071067811865476,
+                                    0.5946035575013605};
 static const double TWO_NEG_5[5] = {1.0, 0.8705505632961241, 0.757858283255199,
                                     0.6597539553864471, 0.5743491774985175};
 static const double TWO_NEG_6[6] = {1.0, 0.8908987181403393, 0.7937005259840998,
@@ -479,7 +481,12 @@ static const double TWO_NEG_8[8] = {1.0, 0.9170040432046712, 0.8408964152537145,
 static double root_inv(double x, int k) {
   if (std::isnan(x) || x < 0.0) return NAN;
   if (std::isinf(x)) return 0.0;
-  const double* c = k == 5 ? TWO_NEG_5 : k == 6 ? TWO_NEG_6 : k == 7 ? TWO_NEG_7 : TWO_NEG_8;
+  if (k < 4 || k > 8) return NAN;
+  const double* c = k == 4   ? TWO_NEG_4
+                    : k == 5 ? TWO_NEG_5
+                    : k == 6 ? TWO_NEG_6
+                    : k == 7 ? TWO_NEG_7
+                             : TWO_NEG_8;
   const double u = 2.0 * c[k - 1];  // 2^(1/k), exactly twice 2^(-(k-1)/k)
   const double inv_k = 1.0 / (double)k;
   x = std::fmax(x, 1e-300);
