@@ -1062,6 +1062,7 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
 
 // Reverse sweep through one Rodas4 step with output cotangent lam:
 //   ubar_i = m_i lam + sum_{l>i} (a_li Ybar_l + c_li t_l),  t_l = rbar_l / h
+// (the sum over l runs from the last stage down, as the sweep forms them)
 //   rbar_i = W^{-T} ubar_i,  Ybar_i = J(Y_i)^T rbar_i,  p_bar += f_p(Y_i)^T rbar_i
 //   lam_in = lam + sum_i Ybar_i + d/dy sum_i rbar_i^T J(y) u_i  (J is at y)
 // with p_bar also receiving d/dp of rbar_i^T J u_i.  Stages run i = 6..1 and
@@ -1088,7 +1089,7 @@ static void ros_step_vjp(int sys, int d, const double* y, const double* p, doubl
       double acc = 0.0;
       bool first = true;
       if (m.m[i] != 0.0) { acc = m.m[i] * lam[c]; first = false; }
-      for (int l = i + 1; l < m.s; ++l) {
+      for (int l = m.s - 1; l > i; --l) {  // in the order the sweep forms them
         if (m.a[l][i] != 0.0) {
           if (first) { acc = m.a[l][i] * Yb[l][c]; first = false; }
           else acc = fma(m.a[l][i], Yb[l][c], acc);
