@@ -74,13 +74,20 @@ extern "C" {
 /* ---- problem description ----------------------------------------------- */
 /* Built-in systems (paper, Appendix A; the linear system is the damped
  * rotation y' = [[-a, -w], [w, -a]] y used for closed-form checks). */
-#define ENS_SYS_LORENZ 1 /* d = 3, P = 3: (sigma, rho, beta) */
-#define ENS_SYS_VDP 2    /* d = 2, P = 1: (mu) */
-#define ENS_SYS_LINEAR 6 /* d = 2, P = 2: (a, w) */
+#define ENS_SYS_LORENZ 1    /* d = 3, P = 3: (sigma, rho, beta) */
+#define ENS_SYS_VDP 2       /* d = 2, P = 1: (mu) */
+#define ENS_SYS_ROBERTSON 3 /* d = 3, P = 3: (k1, k2, k3); stiff */
+#define ENS_SYS_HIRES 4     /* d = 8, P = 12: the rate constants in order of
+                               first appearance; stiff */
+#define ENS_SYS_LINEAR 6    /* d = 2, P = 2: (a, w) */
 
-/* Methods (paper, Section 3.2). */
-#define ENS_TSIT5 1 /* Tsitouras 5(4), 7 stages, first-same-as-last */
-#define ENS_VERN7 2 /* Verner 7(6), 10 stages */
+/* Methods (paper, Section 3.2).  The explicit pairs run on LORENZ, VDP and
+ * LINEAR in F64 or F32; the Rosenbrock method on ROBERTSON, HIRES and
+ * LINEAR in F64.  Other combinations return ENS_EUNSUPPORTED. */
+#define ENS_TSIT5 1  /* Tsitouras 5(4), 7 stages, first-same-as-last */
+#define ENS_VERN7 2  /* Verner 7(6), 10 stages */
+#define ENS_RODAS4 3 /* Rosenbrock-Wanner Rodas4 (Hairer-Wanner IV.7), order
+                        4(3), 6 stages, one LU of I/(gamma h) - J per step */
 
 #define ENS_F64 1
 #define ENS_F32 2
@@ -89,7 +96,7 @@ extern "C" {
 
 typedef struct {
   int32_t system;        /* ENS_SYS_* */
-  int32_t method;        /* ENS_TSIT5 / ENS_VERN7 */
+  int32_t method;        /* ENS_TSIT5 / ENS_VERN7 / ENS_RODAS4 */
   int32_t dtype;         /* ENS_F64 / ENS_F32 */
   int32_t dim;           /* must equal the system's state dimension */
   int32_t nparams;       /* must equal the system's parameter count */

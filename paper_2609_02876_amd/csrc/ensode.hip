@@ -40,6 +40,8 @@ bool sys_info(int sys, SysInfo* s) {
   switch (sys) {
     case ENS_SYS_LORENZ: *s = {3, 3}; return true;
     case ENS_SYS_VDP: *s = {2, 1}; return true;
+    case ENS_SYS_ROBERTSON: *s = {3, 3}; return true;
+    case ENS_SYS_HIRES: *s = {8, 12}; return true;
     case ENS_SYS_LINEAR: *s = {2, 2}; return true;
   }
   return false;
@@ -60,10 +62,19 @@ int check_problem(const ens_problem* p, SysInfo* si) {
   if (p->dim != si->d || p->nparams != si->np)
     return fail(ENS_EINVAL, "system %d has dim %d and %d params (got %d, %d)",
                 p->system, si->d, si->np, p->dim, p->nparams);
-  if (p->method != ENS_TSIT5 && p->method != ENS_VERN7)
+  if (p->method != ENS_TSIT5 && p->method != ENS_VERN7 && p->method != ENS_RODAS4)
     return fail(ENS_EUNSUPPORTED, "unknown method %d", p->method);
   if (p->dtype != ENS_F64 && p->dtype != ENS_F32)
     return fail(ENS_EUNSUPPORTED, "unknown dtype %d", p->dtype);
+  const bool stiff_sys = p->system == ENS_SYS_ROBERTSON || p->system == ENS_SYS_HIRES;
+  if (p->method == ENS_RODAS4) {
+    if (!stiff_sys && p->system != ENS_SYS_LINEAR)
+      return fail(ENS_EUNSUPPORTED, "Rodas4 runs on the Robertson, HIRES and linear systems");
+    if (p->dtype != ENS_F64)
+      return fail(ENS_EUNSUPPORTED, "Rodas4 is built for F64 only");
+  } else if (stiff_sys) {
+    return fail(ENS_EUNSUPPORTED, "system %d is stiff: use ENS_RODAS4", p->system);
+  }
   if (p->params_shared != 0 && p->params_shared != 1)
     return fail(ENS_EINVAL, "params_shared must be 0 or 1");
   return ENS_OK;
@@ -281,6 +292,15 @@ int with_kernels(int sys, int method, int dtype, F&& f) {
     if (method == ENS_TSIT5) return by_type(sys_tag, Tsit5{});
     return by_type(sys_tag, Vern7{});
   };
+  if (method == ENS_RODAS4) {
+    if (dtype != ENS_F64) return fail(ENS_EUNSUPPORTED, "Rodas4 is built for F64 only");
+    switch (sys) {
+      case ENS_SYS_ROBERTSON: return f(Robertson{}, Rodas4{}, double{});
+      case ENS_SYS_HIRES: return f(Hires{}, Rodas4{}, double{});
+      case ENS_SYS_LINEAR: return f(Linear{}, Rodas4{}, double{});
+    }
+    return fail(ENS_EUNSUPPORTED, "Rodas4 is not built for system %d", sys);
+  }
   switch (sys) {
     case ENS_SYS_LORENZ: return by_method(Lorenz{});
     case ENS_SYS_VDP: return by_method(VanDerPol{});

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include "ens_device.h"
+#include "ros.h"
 #include "systems.h"
 #include "tableaux.h"
 
@@ -277,7 +278,7 @@ __device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double
   return rms<D>(e, sc);
 }
 
-// x^(-1/K) for the controller and the starting step (K = 5..8), from
+// x^(-1/K) for the controller and the starting step (K = 4..8), from
 // operations that are exactly or correctly rounded on the device and on any
 // IEEE host: x = m 2^e (m in [0.5, 1)), e = K q + j, a linear first guess
 // for m^(-1/K) times 2^(-j/K) 2^(-q), then four Newton steps
@@ -285,6 +286,11 @@ __device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double
 // the bit.  Arguments below 1e-300 are raised to it.
 template <int K>
 struct TwoNeg;
+template <>
+struct TwoNeg<4> {
+  static constexpr double c[4] = {1.0, 0.8408964152537145, 0.7071067811865476,
+                                  0.5946035575013605};
+};
 template <>
 struct TwoNeg<5> {
   static constexpr double c[5] = {1.0, 0.8705505632961241, 0.757858283255199,
@@ -585,30 +591,42 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
     }
 
     // one evaluation of the step map from the selected base
-    T yb[D], kb[D];
+    T yb[D], ynew[D], klast[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) yb[c] = side ? yp[c] : y[c];
-    if constexpr (Tab::FSAL) {
+    double err = 0.0;
+    if constexpr (Tab::ROS) {
+      // a side step onto the base point itself is the identity (1/(gamma h)
+      // would divide by zero): evaluate at a harmless h and keep yb
+      const bool zero = (hh == 0.0);
+      T W[D * D], u[Tab::S][D];
+      int piv[D];
+      ros_step<Sys, Tab, T>(yb, p, T(zero ? 1.0 : hh), W, piv, u, ynew);
 #pragma unroll
-      for (int c = 0; c < D; ++c) kb[c] = side ? k1p[c] : k1[c];
+      for (int c = 0; c < D; ++c) ynew[c] = zero ? yb[c] : ynew[c];
+      if constexpr (MODE != MODE_FROZEN) err = ros_err<D, T>(yb, ynew, u[Tab::S - 1], rtol, atol);
     } else {
-      Sys::rhs(yb, p, kb);
-    }
-    T Yunused[Tab::S][D];
-    T ylast[D], klast[D], ynew[D];
-    double esum[D];
-    step_push<Sys, Tab, T, Tab::S, false, !Tab::FSAL, MODE != MODE_FROZEN>(
-        yb, kb, p, T(hh), Yunused, ylast, klast, ynew, esum);
-    if constexpr (Tab::FSAL) {
+      T kb[D];
+      if constexpr (Tab::FSAL) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) ynew[c] = ylast[c];
+        for (int c = 0; c < D; ++c) kb[c] = side ? k1p[c] : k1[c];
+      } else {
+        Sys::rhs(yb, p, kb);
+      }
+      T Yunused[Tab::S][D];
+      T ylast[D];
+      double esum[D];
+      step_push<Sys, Tab, T, Tab::S, false, !Tab::FSAL, MODE != MODE_FROZEN>(
+          yb, kb, p, T(hh), Yunused, ylast, klast, ynew, esum);
+      if constexpr (Tab::FSAL) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) ynew[c] = ylast[c];
+      }
+      if constexpr (MODE != MODE_FROZEN) err = err_norm_sum<T, D>(yb, ynew, hh, esum, rtol, atol);
     }
-    double err = 0.0, fac0 = 0.0;
-    if constexpr (MODE != MODE_FROZEN) {
-      err = err_norm_sum<T, D>(yb, ynew, hh, esum, rtol, atol);
-      // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
-      fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
-    }
+    double fac0 = 0.0;
+    // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
+    if constexpr (MODE != MODE_FROZEN) fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
 
     if (side) {
 #pragma unroll
@@ -855,10 +873,20 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
     }
 
     // recompute the stages of this step
-    T k0[D], Y[SU][D], ylast[D], klast[D], ys[D];
-    Sys::rhs(yb, p, k0);
-    step_push<Sys, Tab, T, SU, true, true, false>(yb, k0, p, T(hh), Y, ylast, klast, ys,
-                                                  nullptr);
+    constexpr int NW = Tab::ROS ? D * D : 1;
+    constexpr int NU = Tab::ROS ? Tab::S : 1;
+    constexpr int NY = Tab::ROS ? 1 : SU;
+    T W[NW], u[NU][D];
+    int piv[D];
+    T Y[NY][D], ys[D];
+    if constexpr (Tab::ROS) {
+      ros_step<Sys, Tab, T>(yb, p, T(hh), W, piv, u, ys);
+    } else {
+      T k0[D], ylast[D], klast[D];
+      Sys::rhs(yb, p, k0);
+      step_push<Sys, Tab, T, SU, true, true, false>(yb, k0, p, T(hh), Y, ylast, klast, ys,
+                                                    nullptr);
+    }
     if (CKPT && rebuild) {
       // one replay step of the segment: keep its record, move on
       store_rec<T, D>(scr + j_rb * RB, hh, yb);
@@ -876,7 +904,10 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
     }
 
     // reverse through the stages: kbar_j = h (b_j w + sum_{l>j} a_lj Ybar_l)
-    T Yb[SU][D], lin[D];
+    T Yb[NY][D], lin[D];
+    if constexpr (Tab::ROS) {
+      ros_step_vjp<Sys, Tab, T>(yb, p, T(hh), W, piv, u, w, lin, gp);
+    } else {
 #pragma unroll
     for (int c = 0; c < D; ++c) lin[c] = w[c];
 #pragma unroll
@@ -906,6 +937,7 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
       Sys::vjp(Y[j], p, kb, Yb[j], gp);
 #pragma unroll
       for (int c = 0; c < D; ++c) lin[c] = lin[c] + Yb[j][c];
+    }
     }
 
     if (side) {

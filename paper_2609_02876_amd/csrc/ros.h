@@ -1,0 +1,258 @@
+// Rosenbrock-Wanner (Rodas4) step for one trajectory per lane, and its
+// reverse.  Paper references: the Rosenbrock replay with the mesh frozen and
+// the transposed linear solve plus the Jacobian's own derivative in the
+// reverse sweep (Section 3.2).
+//
+// Everything lives in registers with compile-time indexing: the d x d
+// matrix W = I/(gamma h) - J is factored in place with partial pivoting,
+// the row interchanges done by selects, and the pivot row of each column
+// kept so that a right-hand side is permuted by the same interchanges in
+// the same order (and in reverse order for the transposed solve).
+#pragma once
+#include <math.h>
+
+#include "ens_device.h"
+
+namespace ens {
+
+// W = I/(gamma h) - J(y) factored as P W = L U (unit L below the diagonal,
+// U on and above it).  The pivot of column k is the first row i >= k with
+// the largest |W_ik|; piv[k] records it.
+template <class Sys, class Tab, class T>
+__device__ __forceinline__ void ros_factor(const T* y, const T* p, T h, T (&W)[Sys::D * Sys::D],
+                                           int (&piv)[Sys::D]) {
+  constexpr int D = Sys::D;
+  Sys::jac(y, p, W);
+  const T dg = T(1.0) / (T(Tab::GAMMA) * h);
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) W[i] = -W[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i) W[i * D + i] = W[i * D + i] + dg;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    int pk = k;
+    T best = fabs(W[k * D + k]);
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) {
+      const T v = fabs(W[i * D + k]);
+      const bool gt = v > best;
+      best = gt ? v : best;
+      pk = gt ? i : pk;
+    }
+    piv[k] = pk;
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) {
+      const bool sw = (pk == i);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const T a = W[k * D + j], b = W[i * D + j];
+        W[k * D + j] = sw ? b : a;
+        W[i * D + j] = sw ? a : b;
+      }
+    }
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) {
+      const T l = W[i * D + k] / W[k * D + k];
+      W[i * D + k] = l;
+#pragma unroll
+      for (int j = k + 1; j < D; ++j) W[i * D + j] = fmaT(-l, W[k * D + j], W[i * D + j]);
+    }
+  }
+}
+
+// Apply the interchanges of the factorisation to v, first to last.
+template <int D, class T>
+__device__ __forceinline__ void permute_fwd(const int (&piv)[D], T* v) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) {
+      const bool sw = (piv[k] == i);
+      const T a = v[k], b = v[i];
+      v[k] = sw ? b : a;
+      v[i] = sw ? a : b;
+    }
+  }
+}
+
+// Undo them (last to first): the permutation's transpose.
+template <int D, class T>
+__device__ __forceinline__ void permute_bwd(const int (&piv)[D], T* v) {
+#pragma unroll
+  for (int k = D - 1; k >= 0; --k) {
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) {
+      const bool sw = (piv[k] == i);
+      const T a = v[k], b = v[i];
+      v[k] = sw ? b : a;
+      v[i] = sw ? a : b;
+    }
+  }
+}
+
+// x = W^{-1} b in place: L z = P b forward, then U x = z backward.
+template <int D, class T>
+__device__ __forceinline__ void lu_solve(const T (&W)[D * D], const int (&piv)[D], T* x) {
+  permute_fwd<D, T>(piv, x);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T acc = x[i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) acc = fmaT(-W[i * D + j], x[j], acc);
+    x[i] = acc;
+  }
+#pragma unroll
+  for (int i = D - 1; i >= 0; --i) {
+    T acc = x[i];
+#pragma unroll
+    for (int j = i + 1; j < D; ++j) acc = fmaT(-W[i * D + j], x[j], acc);
+    x[i] = acc / W[i * D + i];
+  }
+}
+
+// z = W^{-T} b in place: U^T v = b forward, L^T w = v backward, z = P^T w.
+template <int D, class T>
+__device__ __forceinline__ void lu_solve_t(const T (&W)[D * D], const int (&piv)[D], T* z) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T acc = z[i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) acc = fmaT(-W[j * D + i], z[j], acc);
+    z[i] = acc / W[i * D + i];
+  }
+#pragma unroll
+  for (int i = D - 1; i >= 0; --i) {
+    T acc = z[i];
+#pragma unroll
+    for (int j = i + 1; j < D; ++j) acc = fmaT(-W[j * D + i], z[j], acc);
+    z[i] = acc;
+  }
+  permute_bwd<D, T>(piv, z);
+}
+
+// The increments u_1..u_s of one step from y with step h (h != 0), the
+// factors left in W/piv for the reverse, and y_new = Y_s + u_s.
+template <class Sys, class Tab, class T>
+__device__ __forceinline__ void ros_step(const T* y, const T* p, T h, T (&W)[Sys::D * Sys::D],
+                                         int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D], T* ynew) {
+  constexpr int D = Sys::D, NS = Tab::S;
+  ros_factor<Sys, Tab, T>(y, p, h, W, piv);
+  const T hinv = T(1.0) / h;
+  T Yi[D];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T acc = T(0);
+      bool first = true;
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        if (Tab::A[i][j] != 0.0) {
+          acc = first ? T(Tab::A[i][j]) * u[j][c] : fmaT(T(Tab::A[i][j]), u[j][c], acc);
+          first = false;
+        }
+      }
+      Yi[c] = first ? y[c] : y[c] + acc;
+    }
+    T F[D];
+    Sys::rhs(Yi, p, F);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T acc = T(0);
+      bool first = true;
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        if (Tab::C[i][j] != 0.0) {
+          acc = first ? T(Tab::C[i][j]) * u[j][c] : fmaT(T(Tab::C[i][j]), u[j][c], acc);
+          first = false;
+        }
+      }
+      u[i][c] = first ? F[c] : fmaT(acc, hinv, F[c]);
+    }
+    lu_solve<D, T>(W, piv, u[i]);
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) ynew[c] = Yi[c] + u[NS - 1][c];
+}
+
+// Reverse of one step (W, piv, u from ros_step at the same y, h): with the
+// output cotangent w, lam_in = d(y_new)/dy^T w and gp += d(y_new)/dp^T w.
+//   ubar_i = M_i w + sum_{l>i} (A_li Ybar_l + C_li rbar_l / h)   (l from s down)
+//   rbar_i = W^{-T} ubar_i,  Ybar_i = f_y(Y_i)^T rbar_i,  gp += f_p(Y_i)^T rbar_i
+//   lam_in = w + sum_i Ybar_i + d/dy sum_i rbar_i^T J(y) u_i,
+// the last term (and its p part, into gp) from each stage in turn.  Stage
+// cotangents are pushed into running sums as they are formed.
+template <class Sys, class Tab, class T>
+__device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h,
+                                             const T (&W)[Sys::D * Sys::D],
+                                             const int (&piv)[Sys::D],
+                                             const T (&u)[Tab::S][Sys::D], const T* w,
+                                             T* lam_in, T* gp) {
+  constexpr int D = Sys::D, NS = Tab::S;
+  static_assert(Tab::M[0] != 0.0 && Tab::M[1] != 0.0 && Tab::M[2] != 0.0 &&
+                    Tab::M[3] != 0.0 && Tab::M[4] != 0.0 && Tab::M[5] != 0.0,
+                "every stage sum starts with its M term");
+  const T hinv = T(1.0) / h;
+  T ub[NS][D], gJ[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    lam_in[c] = w[c];
+    gJ[c] = T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int c = 0; c < D; ++c) ub[i][c] = T(Tab::M[i]) * w[c];
+#pragma unroll
+  for (int i = NS - 1; i >= 0; --i) {
+    T rb[D], tb[D], Yi[D], Yb[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) rb[c] = ub[i][c];
+    lu_solve_t<D, T>(W, piv, rb);
+#pragma unroll
+    for (int c = 0; c < D; ++c) tb[c] = hinv * rb[c];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T acc = T(0);
+      bool first = true;
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        if (Tab::A[i][j] != 0.0) {
+          acc = first ? T(Tab::A[i][j]) * u[j][c] : fmaT(T(Tab::A[i][j]), u[j][c], acc);
+          first = false;
+        }
+      }
+      Yi[c] = first ? y[c] : y[c] + acc;
+    }
+    Sys::vjp(Yi, p, rb, Yb, gp);
+#pragma unroll
+    for (int c = 0; c < D; ++c) lam_in[c] = lam_in[c] + Yb[c];
+    Sys::jac_vjp(y, p, rb, u[i], gJ, gp);
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        if (Tab::A[i][j] != 0.0) ub[j][c] = fmaT(T(Tab::A[i][j]), Yb[c], ub[j][c]);
+        if (Tab::C[i][j] != 0.0) ub[j][c] = fmaT(T(Tab::C[i][j]), tb[c], ub[j][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) lam_in[c] = lam_in[c] + gJ[c];
+}
+
+// Scaled RMS norm of the error estimate u_s against atol + rtol max(|y|, |y_new|).
+template <int D, class T>
+__device__ __forceinline__ double ros_err(const T* y, const T* ynew, const T* e, double rtol,
+                                          double atol) {
+  double r = 0.0, ss = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sc = fmaT(rtol, fmax(fabs((double)y[c]), fabs((double)ynew[c])), atol);
+    r = (double)e[c] / sc;
+    ss = c == 0 ? r * r : fmaT(r, r, ss);
+  }
+  return sqrt(ss * (1.0 / (double)D));
+}
+
+}  // namespace ens

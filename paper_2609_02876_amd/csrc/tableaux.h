@@ -13,6 +13,7 @@ struct Tsit5 {
   static constexpr int S = 7;       // stages formed by a trial step
   static constexpr int SU = 6;      // stages that enter the update (b_7 = 0)
   static constexpr bool FSAL = true;
+  static constexpr bool ROS = false;
   static constexpr int ORDER = 5;
   static constexpr int QEMB = 4;    // order of the embedded solution
   static constexpr double A[7][7] = {
@@ -41,6 +42,7 @@ struct Vern7 {
   static constexpr int S = 10;
   static constexpr int SU = 9;
   static constexpr bool FSAL = false;
+  static constexpr bool ROS = false;
   static constexpr int ORDER = 7;
   static constexpr int QEMB = 6;
   static constexpr double A[10][10] = {
@@ -70,6 +72,38 @@ struct Vern7 {
       0.0025470118799348416, 0, 0, -0.009658394872807551, 0.04206470975642573,
       -0.06668224374695614, 0.26500974646213266, -0.29430311714032503,
       0.08131747232495111, -0.020295184663355476};
+};
+
+// Rodas4 (Hairer & Wanner, Solving ODEs II, Sec. IV.7): stiffly accurate
+// Rosenbrock-Wanner method of order 4 with an embedded order-3 solution,
+// in the transformed variables u_i = h sum_j gamma_ij k_j (W = I/(gamma h) - J):
+//   Y_i = y + sum_{j<i} A_ij u_j,   W u_i = f(Y_i) + (1/h) sum_{j<i} C_ij u_j,
+//   y_new = Y_6 + u_6 = y + sum_j M_j u_j,   error estimate u_6.
+struct Rodas4 {
+  static constexpr int S = 6;
+  static constexpr int SU = 6;
+  static constexpr bool FSAL = false;
+  static constexpr bool ROS = true;
+  static constexpr int ORDER = 4;
+  static constexpr int QEMB = 3;
+  static constexpr double GAMMA = 0.25;
+  static constexpr double A[6][6] = {
+      {0, 0, 0, 0, 0, 0},
+      {1.544, 0, 0, 0, 0, 0},
+      {0.9466785280815826, 0.2557011698983284, 0, 0, 0, 0},
+      {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0, 0},
+      {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 0, 0},
+      {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0, 0}};
+  static constexpr double C[6][6] = {
+      {0, 0, 0, 0, 0, 0},
+      {-5.6688, 0, 0, 0, 0, 0},
+      {-2.430093356833875, -0.2063599157091915, 0, 0, 0, 0},
+      {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0, 0},
+      {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.70890893206160, 0, 0},
+      {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136,
+       -6.058818238834054, 0}};
+  static constexpr double M[6] = {1.221224509226641, 6.019134481288629, 12.53708332932087,
+                                  -0.6878860361058950, 1.0, 1.0};
 };
 
 }  // namespace ens

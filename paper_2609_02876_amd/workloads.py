@@ -40,6 +40,25 @@ def vdp(n, seed=0):
     return np.tile(np.array(VDP_Y0), (n, 1)), 0.5 + 1.5 * u
 
 
+ROBERTSON_K = (0.04, 3e7, 1e4)
+HIRES_THETA = (1.71, 0.43, 8.32, 0.0007, 8.75, 10.03, 0.035, 1.12, 1.745, 280.0, 0.69, 1.81)
+HIRES_Y0 = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0057)
+
+
+def robertson(n, seed=0):
+    """Robertson kinetics: y0 = (1,0,0); (k1, k2, k3) = (0.04, 3e7, 1e4), each
+    scaled by exp(U[log 0.8, log 1.25]) (log-uniform in [0.8, 1.25])."""
+    rng = np.random.default_rng(seed)
+    k = np.array(ROBERTSON_K) * np.exp(rng.uniform(np.log(0.8), np.log(1.25), (n, 3)))
+    return np.tile([1.0, 0.0, 0.0], (n, 1)), k
+
+
+def hires(n, seed=0):
+    """HIRES: y0 = (1,0,0,0,0,0,0,0.0057); the twelve rate constants each scaled by U[0.9, 1.1]."""
+    rng = np.random.default_rng(seed)
+    return np.tile(np.array(HIRES_Y0), (n, 1)), np.array(HIRES_THETA) * rng.uniform(0.9, 1.1, (n, 12))
+
+
 def damped_rotation(n, seed=0):
     """Linear test ensemble y' = A y, A = [[-a, -w], [w, -a]]: a ~ U[0.05,0.35], w ~ U[0.5,2.5], y0 ~ N(0,1)."""
     rng = np.random.default_rng(seed)
@@ -58,7 +77,15 @@ WORKLOADS = {
                            rtol=1e-6, atol=1e-8, n_save=0),
     "lorenz_2p20_t10": dict(system="lorenz", method="tsit5", n=1 << 20, t0=0.0, t1=10.0,
                             rtol=1e-6, atol=1e-8, n_save=20),
+    # stiff: Rodas4, FP64, rtol 1e-6, atol 1e-10, loss on 20 save states
+    "robertson_2p18_t1e5": dict(system="robertson", method="rodas4", n=1 << 18, t0=0.0,
+                                t1=1e5, rtol=1e-6, atol=1e-10, n_save=20),
+    "hires_2p18": dict(system="hires", method="rodas4", n=1 << 18, t0=0.0, t1=321.8122,
+                       rtol=1e-6, atol=1e-10, n_save=20),
 }
+
+GENERATORS = {"lorenz": lorenz, "vdp": vdp, "robertson": robertson, "hires": hires,
+              "linear": damped_rotation}
 
 
 def make(name, n=None, seed=0):
@@ -66,7 +93,7 @@ def make(name, n=None, seed=0):
     cfg = dict(WORKLOADS[name])
     if n is not None:
         cfg["n"] = n
-    gen = {"lorenz": lorenz, "vdp": vdp}[cfg["system"]]
+    gen = GENERATORS[cfg["system"]]
     y0, p = gen(cfg["n"], seed)
     st = save_times(cfg["t0"], cfg["t1"], cfg["n_save"]) if cfg["n_save"] else np.array([cfg["t1"]])
     return cfg, y0, p, st

@@ -50,6 +50,17 @@ def _ivp(**kw):
     return v
 
 
+@pytest.mark.parametrize("system,method,d,np_", [
+    (A.SYS_ROBERTSON, A.RODAS4, 3, 3), (A.SYS_HIRES, A.RODAS4, 8, 12),
+    (A.SYS_LINEAR, A.RODAS4, 2, 2), (A.SYS_LINEAR, A.VERN7, 2, 2)])
+def test_supported_combinations_plan(system, method, d, np_):
+    lib = _lib()
+    out = C.c_size_t()
+    prob = _prob(system=system, method=method, dim=d, nparams=np_)
+    assert lib.ensemble_record_bytes(C.byref(prob), C.byref(_ivp()), 64, 0, C.byref(out)) == 0
+    assert out.value > 0
+
+
 def test_record_bytes_plan():
     lib = _lib()
     out = C.c_size_t()
@@ -71,6 +82,11 @@ def test_record_bytes_plan():
     ({}, dict(rtol=-1.0), A.ENS_EINVAL),
     ({}, dict(rtol=0.0, atol=0.0), A.ENS_EINVAL),
     ({}, dict(n_save=65), A.ENS_EINVAL),
+    # the Rosenbrock method: stiff systems and the linear one, FP64 only
+    (dict(method=A.RODAS4), {}, A.ENS_EUNSUPPORTED),
+    (dict(system=A.SYS_ROBERTSON, method=A.RODAS4, dtype=A.F32), {}, A.ENS_EUNSUPPORTED),
+    (dict(system=A.SYS_ROBERTSON, method=A.TSIT5), {}, A.ENS_EUNSUPPORTED),
+    (dict(system=A.SYS_HIRES, method=A.RODAS4, dim=8, nparams=3), {}, A.ENS_EINVAL),
 ])
 def test_validation_errors(prob, ivp, code):
     lib = _lib()

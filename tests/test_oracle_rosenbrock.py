@@ -23,24 +23,15 @@ from scipy.integrate import solve_ivp
 from scipy.linalg import expm
 
 import oracle as O
+from paper_2609_02876_amd import workloads as W
 from oracle_helpers import make_mesh, rot_matrix
 from test_oracle_tableaux import _gamma, _trees
 
 mp.mp.dps = 40
-HIRES_THETA = np.array([1.71, 0.43, 8.32, 0.0007, 8.75, 10.03, 0.035, 1.12, 1.745, 280.0,
-                        0.69, 1.81])
-HIRES_Y0 = np.array([1.0, 0, 0, 0, 0, 0, 0, 0.0057])
-
-
-def _robertson(n, seed=0):
-    rng = np.random.default_rng(seed)
-    k = np.array([0.04, 3e7, 1e4]) * np.exp(rng.uniform(np.log(0.8), np.log(1.25), (n, 3)))
-    return np.tile([1.0, 0.0, 0.0], (n, 1)), k
-
-
-def _hires(n, seed=0):
-    rng = np.random.default_rng(seed)
-    return np.tile(HIRES_Y0, (n, 1)), HIRES_THETA * rng.uniform(0.9, 1.1, (n, 12))
+HIRES_THETA = np.array(W.HIRES_THETA)
+HIRES_Y0 = np.array(W.HIRES_Y0)
+_robertson = W.robertson
+_hires = W.hires
 
 
 # ------------------------------------------------------------- tableau ---
