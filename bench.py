@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+METRIC = "trajectory-gradients/s (fwd+adjoint) at 2^20 Lorenz, rtol 1e-6"
 
 
 def parse():
@@ -41,8 +42,9 @@ def cpu_baseline(cfg, y0, p, st, target_s, cap):
     """The FP64 CPU oracle (record + adjoint) on a bounded sample of the workload."""
     import numpy as np
     import oracle as O
-    so = {"lorenz": O.LORENZ, "vdp": O.VDP}[cfg["system"]]
-    mo = {"tsit5": O.TSIT5, "vern7": O.VERN7}[cfg["method"]]
+    so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON, "hires": O.HIRES,
+          "linear": O.LINEAR}[cfg["system"]]
+    mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS}[cfg["method"]]
     save = list(st)
 
     def run(m):
@@ -151,7 +153,7 @@ def main():
         tr = json.load(open(args.traffic))
         traffic = tr.get(dominant)
     out = {
-        "metric": "trajectory-gradients/s (fwd+adjoint) at 2^20 Lorenz, rtol 1e-6",
+        "metric": METRIC if args.workload == "lorenz_2p20_t10" else "trajectory-gradients/s (fwd+adjoint)",
         "value": value,
         "unit": "trajectory-gradients/s",
         "n_gpus": 1,
@@ -167,7 +169,8 @@ def main():
                    "n": n, "t_span": [cfg["t0"], cfg["t1"]], "rtol": cfg["rtol"],
                    "atol": cfg["atol"], "n_save": cfg["n_save"],
                    "loss": "sum of squared save states", "gradient": "per-trajectory params"},
-        "roofline": {"bound": "alu", "kernel": f"erk_{dominant}_kernel (Lorenz, Tsit5, f64)",
+        "roofline": {"bound": "alu",
+                     "kernel": f"erk_{dominant}_kernel ({cfg['system']}, {cfg['method']}, f64)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},
         "kernels_ms": {"record": rec_ms, "adjoint": adj_ms},

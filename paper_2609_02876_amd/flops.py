@@ -1,4 +1,5 @@
-"""Algorithmic floating-point work of the explicit-RK record and reverse sweep.
+"""Algorithmic floating-point work of the record and the reverse sweep
+(explicit Runge-Kutta pairs and the Rodas4 Rosenbrock method).
 
 Counting rules: fma = 2; add, sub, mul, div, min, max = 1; sqrt and the
 controller's root = 1; abs, negation, selects and comparisons = 0.  Work the
@@ -38,8 +39,54 @@ TABLEAUX = {
 SYSTEMS = {
     "lorenz": (3, 8, 20),
     "vdp": (2, 5, 13),
+    "robertson": (3, 8, 20),
+    "hires": (8, 36, 77),
     "linear": (2, 6, 14),
 }
+
+# (jacobian flops, flops of d/d(y, p) of u^T J v) for the stiff path
+JACOBIANS = {
+    "robertson": (5, 24),
+    "hires": (3, 49),
+    "linear": (0, 8),
+}
+
+# Rodas4: nonzero counts of the rows of A (stage inputs) and C (stage
+# right-hand sides), stages 2..6
+ROS_TABLEAUX = {
+    "rodas4": dict(S=6, a_nnz=[0, 1, 2, 3, 4, 5], c_nnz=[0, 1, 2, 3, 4, 5]),
+}
+
+
+def _lu(D):
+    """LU with partial pivoting of a D x D matrix: for column k, D-k-1
+    multipliers (div) and (D-k-1)^2 fma updates."""
+    return sum(m * (1 + 2 * m) for m in range(1, D))
+
+
+def _ros_per_unit(method, system):
+    t = ROS_TABLEAUX[method]
+    D, F, V = SYSTEMS[system]
+    J, JV = JACOBIANS[system]
+    S = t["S"]
+    solve = 2 * D * D - D                       # L and U sweeps, D divisions
+    factor = J + 2 + D + _lu(D)                 # jac, 1/(gamma h), diagonal, LU
+    stage_in = sum(2 * z for z in t["a_nnz"]) * D
+    stage_rhs = sum(2 * w + 1 for w in t["c_nnz"] if w) * D
+    stages = 1 + stage_in + S * F + stage_rhs + S * solve     # 1: 1/h
+    update = D                                   # y_new = Y_s + u_s
+    err = 3 * D + (3 * D + 1)
+    controller = 7
+    trial = factor + stages + update + err + controller
+    side_fwd = factor + stages + update
+    push = sum(2 * (z + w) for z, w in zip(t["a_nnz"], t["c_nnz"])) * D
+    reverse = S * D + S * solve + S * D + stage_in + S * V + S * D + S * JV + push + D
+    adj_step = factor + stages + reverse
+    cot = 3 * D
+    adj_side = adj_step + update + cot + D
+    adj_zero = cot + D
+    return dict(trial=trial, accept=0, side_fwd=side_fwd, adj_step=adj_step,
+                adj_side=adj_side, adj_zero=adj_zero)
 
 
 def _combo(m):
@@ -48,6 +95,8 @@ def _combo(m):
 
 
 def per_unit(method, system):
+    if method in ROS_TABLEAUX:
+        return _ros_per_unit(method, system)
     t = TABLEAUX[method]
     D, F, V = SYSTEMS[system]
     S, SU = t["S"], t["SU"]
