@@ -41,7 +41,8 @@ class _Cfg:
     params_shared: bool
     steps_hint: int
     max_steps: int
-    ckpt_every: int
+    ckpt_every: object
+    tape_budget_bytes: Optional[int]
 
 
 class _EnsembleODE(torch.autograd.Function):
@@ -53,7 +54,8 @@ class _EnsembleODE(torch.autograd.Function):
             rec = B.ensemble_record(cfg.system, cfg.method, y0, params, cfg.t0, cfg.t1, cfg.rtol,
                                     cfg.atol, save_times=cfg.save_times,
                                     params_shared=cfg.params_shared, steps_hint=cfg.steps_hint,
-                                    max_steps=cfg.max_steps, ckpt_every=cfg.ckpt_every)
+                                    max_steps=cfg.max_steps, ckpt_every=cfg.ckpt_every,
+                                    tape_budget_bytes=cfg.tape_budget_bytes)
         else:
             rec = B.ensemble_replay_mesh(cfg.system, cfg.method, y0, params, cfg.t0, cfg.t1,
                                          cfg.mesh.h, cfg.mesh.steps, save_times=cfg.save_times,
@@ -75,14 +77,20 @@ class _EnsembleODE(torch.autograd.Function):
 
 def odeint(system, method, y0, params, t0, t1, rtol=1e-6, atol=1e-8, save_times=None,
            mesh: Optional[Mesh] = None, params_shared=False, steps_hint=512, max_steps=0,
-           ckpt_every=0, return_status=False):
+           ckpt_every=0, tape_budget_bytes=None, return_status=False):
     """States at the save times [n_save, d, n] (t1 alone when save_times is None).
 
     ckpt_every > 0 records a checkpointed tape (one state per segment of that
-    many steps); the gradient is the same to the bit, the tape about 4x smaller."""
+    many steps); the gradient is the same to the bit, the tape about 4x smaller.
+    ckpt_every="auto" checkpoints every 64 steps only when the full tape's
+    plan exceeds tape_budget_bytes."""
+    if ckpt_every != "auto":
+        ckpt_every = int(ckpt_every)
+    if mesh is not None and ckpt_every == "auto":
+        ckpt_every = 0
     cfg = _Cfg(system, method, float(t0), float(t1), float(rtol), float(atol),
                list(save_times) if save_times is not None else None, mesh, bool(params_shared),
-               int(steps_hint), int(max_steps), int(ckpt_every))
+               int(steps_hint), int(max_steps), ckpt_every, tape_budget_bytes)
     ys, status = _EnsembleODE.apply(y0, params, cfg)
     return (ys, status) if return_status else ys
 

@@ -111,6 +111,21 @@ def ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save=0,
     return out.value
 
 
+def plan_tape(system, method, n, t0, t1, steps_hint, n_save=0, dtype=torch.float64,
+              budget_bytes=None, ckpt_every=64):
+    """Tape layout for a record: 0 (full tape) when its planned pool fits the
+    HBM budget, else ckpt_every (one state per segment, the segment replayed
+    in the reverse sweep).  Raises when neither fits."""
+    full = ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save, dtype, 0)
+    if budget_bytes is None or full <= budget_bytes:
+        return 0
+    ck = ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save, dtype, ckpt_every)
+    if ck > budget_bytes:
+        raise ValueError(f"record needs {ck} bytes even with checkpoints every {ckpt_every} "
+                         f"steps; budget is {budget_bytes}")
+    return ckpt_every
+
+
 def ensemble_solve(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
                    max_steps=0, params_shared=False):
     """Forward solve: (states at the save times [n_save, d, n], lane status [n])."""
@@ -141,14 +156,19 @@ def _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every=0):
 
 def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
                     max_steps=0, params_shared=False, steps_hint=512, pool=None,
-                    steps_per_traj=None, ckpt_every=0):
+                    steps_per_traj=None, ckpt_every=0, tape_budget_bytes=None):
     """Adaptive record.  Returns a RecordHandle (.y_save, .status, .pool).
 
     Without a pool, one is planned that reserves steps_hint taped steps per
     trajectory (plus overflow).  With a pool, steps_per_traj sets the
-    per-trajectory reservation (None: 7/8 of the pool evenly)."""
+    per-trajectory reservation (None: 7/8 of the pool evenly).
+    ckpt_every="auto" keeps the full tape unless its plan exceeds
+    tape_budget_bytes, then checkpoints every 64 steps (plan_tape)."""
     spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
                  params_shared)
+    if ckpt_every == "auto":
+        ckpt_every = plan_tape(system, method, spec.n, t0, t1, steps_hint, spec.ivp.n_save,
+                               spec.dtype, tape_budget_bytes)
     pool, tc = _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every)
     rec = A.Record()
     y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)

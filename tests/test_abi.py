@@ -142,3 +142,19 @@ def test_checkpoint_plan_is_smaller():
     assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(_ivp()), 640, 64, C.byref(ck)) == 0
     assert ck.value < full.value / 3
     assert lib.ensemble_record_bytes(C.byref(_prob()), C.byref(_ivp()), 640, 48, C.byref(ck)) == A.ENS_EINVAL
+
+
+def test_tape_plan_switches_to_checkpoints_over_budget():
+    """Full tape while its plan fits the HBM budget, checkpoint-64 above it,
+    an error when even the checkpointed plan does not fit (host logic only)."""
+    _lib()
+    from paper_2609_02876_amd import binding as B
+    args = ("lorenz", "tsit5", 1 << 20, 0.0, 10.0, 352, 20)
+    full = B.ensemble_record_bytes(*args)
+    ck = B.ensemble_record_bytes(*args, ckpt_every=64)
+    assert ck < full / 3
+    assert B.plan_tape(*args) == 0
+    assert B.plan_tape(*args, budget_bytes=full) == 0
+    assert B.plan_tape(*args, budget_bytes=full - 1) == 64
+    with pytest.raises(ValueError):
+        B.plan_tape(*args, budget_bytes=ck - 1)
