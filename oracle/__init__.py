@@ -96,7 +96,7 @@ def erk_tableau(method):
 
 
 def root_inv(x, k):
-    """The controller's x^(-1/k) (k = 5..8)."""
+    """The controller's x^(-1/k) (k = 4..8)."""
     return _load().oracle_root_inv(float(x), int(k))
 
 

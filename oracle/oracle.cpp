@@ -190,7 +190,81 @@ static const ERK* erk_of(int method) {
 }
 
 // ---------------------------------------------------------------- systems --
-enum { SYS_LORENZ = 1, SYS_VDP = 2, SYS_ROBERTSON = 3, SYS_HIRES = 4, SYS_LINEAR = 6 };
+enum { SYS_LORENZ = 1, SYS_VDP = 2, SYS_ROBERTSON = 3, SYS_HIRES = 4, SYS_LV_UDE = 5,
+       SYS_LINEAR = 6 };
+
+// Universal differential equation: Lotka-Volterra plus a multilayer
+// perceptron, y' = f_LV(y) + NN(y), with the predator-prey constants fixed,
+//   f_LV = (alpha x - beta x y, delta x y - gamma y),
+//   (alpha, beta, gamma, delta) = (1.5, 1, 3, 1),
+// and NN(y) = W3 tanh(W2 tanh(W1 y + b1) + b2) + b3 with widths 2-32-32-2.
+// The parameter vector holds W1 [32][2], b1 [32], W2 [32][32], b2 [32],
+// W3 [2][32], b3 [2] in that order, row-major (1218 values).  Plain loops,
+// left to right sums; no operation order is shared with any device code.
+constexpr int UDE_H = 32;
+constexpr int UDE_W1 = 0, UDE_B1 = 64, UDE_W2 = 96, UDE_B2 = 1120, UDE_W3 = 1152,
+              UDE_B3 = 1216, UDE_NP = 1218;
+constexpr double LV_ALPHA = 1.5, LV_BETA = 1.0, LV_GAMMA = 3.0, LV_DELTA = 1.0;
+
+template <class T, class P>
+static void ude_forward(const T* y, const P* p, T* h1, T* h2, T* f) {
+  for (int i = 0; i < UDE_H; ++i) {
+    T a = T(p[UDE_B1 + i]);
+    for (int k = 0; k < 2; ++k) a = a + T(p[UDE_W1 + 2 * i + k]) * y[k];
+    h1[i] = tanh(a);
+  }
+  for (int i = 0; i < UDE_H; ++i) {
+    T a = T(p[UDE_B2 + i]);
+    for (int j = 0; j < UDE_H; ++j) a = a + T(p[UDE_W2 + UDE_H * i + j]) * h1[j];
+    h2[i] = tanh(a);
+  }
+  for (int o = 0; o < 2; ++o) {
+    T a = T(p[UDE_B3 + o]);
+    for (int j = 0; j < UDE_H; ++j) a = a + T(p[UDE_W3 + UDE_H * o + j]) * h2[j];
+    f[o] = a;
+  }
+  const T xy = y[0] * y[1];
+  f[0] = f[0] + (T(LV_ALPHA) * y[0] - T(LV_BETA) * xy);
+  f[1] = f[1] + (T(LV_DELTA) * xy - T(LV_GAMMA) * y[1]);
+}
+
+// gy = (df/dy)^T w (overwritten), gp += (df/dp)^T w, by the chain rule
+// through the three layers (tanh' = 1 - tanh^2).
+static void ude_vjp(const double* y, const double* p, const double* w, double* gy,
+                    double* gp) {
+  double h1[UDE_H], h2[UDE_H], f[2], d2[UDE_H], d1[UDE_H];
+  ude_forward(y, p, h1, h2, f);
+  for (int o = 0; o < 2; ++o) {
+    gp[UDE_B3 + o] += w[o];
+    for (int j = 0; j < UDE_H; ++j) gp[UDE_W3 + UDE_H * o + j] += w[o] * h2[j];
+  }
+  for (int j = 0; j < UDE_H; ++j) {
+    double g = 0.0;
+    for (int o = 0; o < 2; ++o) g += p[UDE_W3 + UDE_H * o + j] * w[o];
+    d2[j] = g * (1.0 - h2[j] * h2[j]);
+  }
+  for (int i = 0; i < UDE_H; ++i) {
+    gp[UDE_B2 + i] += d2[i];
+    for (int j = 0; j < UDE_H; ++j) gp[UDE_W2 + UDE_H * i + j] += d2[i] * h1[j];
+  }
+  for (int j = 0; j < UDE_H; ++j) {
+    double g = 0.0;
+    for (int i = 0; i < UDE_H; ++i) g += p[UDE_W2 + UDE_H * i + j] * d2[i];
+    d1[j] = g * (1.0 - h1[j] * h1[j]);
+  }
+  for (int i = 0; i < UDE_H; ++i) {
+    gp[UDE_B1 + i] += d1[i];
+    for (int k = 0; k < 2; ++k) gp[UDE_W1 + 2 * i + k] += d1[i] * y[k];
+  }
+  for (int k = 0; k < 2; ++k) {
+    double g = 0.0;
+    for (int i = 0; i < UDE_H; ++i) g += p[UDE_W1 + 2 * i + k] * d1[i];
+    gy[k] = g;
+  }
+  // Lotka-Volterra part: J_LV = [[alpha - beta y, -beta x], [delta y, delta x - gamma]]
+  gy[0] += (LV_ALPHA - LV_BETA * y[1]) * w[0] + LV_DELTA * y[1] * w[1];
+  gy[1] += -LV_BETA * y[0] * w[0] + (LV_DELTA * y[0] - LV_GAMMA) * w[1];
+}
 
 static int sys_dim(int sys) {
   switch (sys) {
@@ -198,6 +272,7 @@ static int sys_dim(int sys) {
     case SYS_VDP: return 2;
     case SYS_ROBERTSON: return 3;
     case SYS_HIRES: return 8;
+    case SYS_LV_UDE: return 2;
     case SYS_LINEAR: return 2;
   }
   return -1;
@@ -208,6 +283,7 @@ static int sys_np(int sys) {
     case SYS_VDP: return 1;
     case SYS_ROBERTSON: return 3;
     case SYS_HIRES: return 12;
+    case SYS_LV_UDE: return UDE_NP;
     case SYS_LINEAR: return 2;
   }
   return -1;
@@ -245,6 +321,10 @@ static void rhs(int sys, const T* y, const P* p, T* f) {
       f[0] = b - a;
       f[1] = (a - b) - c;
       f[2] = c;
+    } break;
+    case SYS_LV_UDE: {
+      T h1[UDE_H], h2[UDE_H];
+      ude_forward(y, p, h1, h2, f);
     } break;
     case SYS_HIRES: {
       // p = the twelve rate literals of Appendix A in order of first appearance
@@ -374,6 +454,7 @@ static void vjp(int sys, const double* y, const double* p, const double* w,
       gp[1] = fma(y[1] * y[1], w[2] - w[1], gp[1]);
       gp[2] = fma(y[1] * y[2], w[0] - w[1], gp[2]);
     } break;
+    case SYS_LV_UDE: ude_vjp(y, p, w, gy, gp); break;
     case SYS_HIRES: {
       double a = p[9] * y[7], b = p[9] * y[5];
       gy[0] = p[0] * (w[1] - w[0]);

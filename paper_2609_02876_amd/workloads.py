@@ -59,6 +59,37 @@ def hires(n, seed=0):
     return np.tile(np.array(HIRES_Y0), (n, 1)), np.array(HIRES_THETA) * rng.uniform(0.9, 1.1, (n, 12))
 
 
+UDE_HIDDEN = 32
+UDE_NP = 2 * 32 + 32 + 32 * 32 + 32 + 32 * 2 + 2   # 1218
+
+
+def ude_weights(seed=0, scale=0.1):
+    """MLP 2-32-32-2 parameters in the order W1 [32][2], b1, W2 [32][32], b2,
+    W3 [2][32], b3: Glorot-uniform weights (bound sqrt(6 / (fan_in + fan_out)))
+    times `scale`, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((32, 2), (32, 32), (2, 32)):
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(scale * rng.uniform(-a, a, (fan_out, fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    th = np.concatenate(parts)
+    assert th.size == UDE_NP
+    return th
+
+
+def ude(n, seed=0):
+    """Lotka-Volterra UDE ensemble: y0 ~ U[0.5, 2]^2 per trajectory; the MLP
+    weights (shared by all trajectories) from ude_weights(seed 0)."""
+    y0 = np.random.default_rng(seed).uniform(0.5, 2.0, (n, 2))
+    return y0, ude_weights(0)
+
+
+def ude_teacher():
+    """Teacher weights of the synthetic targets (seed 1)."""
+    return ude_weights(1)
+
+
 def damped_rotation(n, seed=0):
     """Linear test ensemble y' = A y, A = [[-a, -w], [w, -a]]: a ~ U[0.05,0.35], w ~ U[0.5,2.5], y0 ~ N(0,1)."""
     rng = np.random.default_rng(seed)
