@@ -38,23 +38,29 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, y0, p, st, target_s, cap):
+def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
     """The FP64 CPU oracle (record + adjoint) on a bounded sample of the workload."""
     import numpy as np
     import oracle as O
     so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON, "hires": O.HIRES,
-          "linear": O.LINEAR}[cfg["system"]]
+          "linear": O.LINEAR, "ude": O.LV_UDE}[cfg["system"]]
     mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS}[cfg["method"]]
     save = list(st)
+    shared = cfg.get("shared", False)
 
     def run(m):
+        pm = p if shared else p[:m]
         t = time.perf_counter()
-        rec = O.record(so, mo, y0[:m], p[:m], cfg["t0"], cfg["t1"], cfg["rtol"], cfg["atol"],
-                       save_t=save, cap=cap)
-        O.adjoint(so, mo, y0[:m], p[:m], rec)
+        rec = O.record(so, mo, y0[:m], pm, cfg["t0"], cfg["t1"], cfg["rtol"], cfg["atol"],
+                       save_t=save, cap=cap, params_shared=shared)
+        if loss_data is None:
+            O.adjoint(so, mo, y0[:m], pm, rec, params_shared=shared)
+        else:
+            O.adjoint(so, mo, y0[:m], pm, rec, O.LOSS_MSE_TARGET, loss_data[:m], scale,
+                      params_shared=shared)
         return time.perf_counter() - t
 
-    m = 2048
+    m = 256 if cfg["system"] == "ude" else 2048
     dt = run(m)
     m2 = int(min(len(y0), max(m, m * target_s / max(dt, 1e-3))))
     m2 = max(m, (m2 // 64) * 64)
@@ -83,22 +89,37 @@ def main():
     save = list(st) if cfg["n_save"] else None
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=torch.float64, device=dev)
-    p_d = torch.tensor(np.ascontiguousarray(p.T), dtype=torch.float64, device=dev)
+    f32 = cfg.get("dtype", "f64") == "f32"
+    tdt = torch.float32 if f32 else torch.float64
+    shared = cfg.get("shared", False)
+    ckpt = cfg.get("ckpt_every", 0)
+    y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=tdt, device=dev)
+    p_d = torch.tensor(np.ascontiguousarray(p if shared else p.T), dtype=tdt, device=dev)
     args_common = (cfg["system"], cfg["method"], y0_d, p_d, cfg["t0"], cfg["t1"], cfg["rtol"],
                    cfg["atol"])
+
+    # loss: sum of squares, or MSE to targets from the teacher network (UDE)
+    loss_kind, loss_data, scale, tgt_host = "sumsq", None, 1.0, None
+    if cfg.get("loss") == "mse":
+        th_t = torch.tensor(W.ude_teacher(), dtype=tdt, device=dev)
+        loss_data, _ = B.ensemble_solve(cfg["system"], cfg["method"], y0_d, th_t, cfg["t0"],
+                                        cfg["t1"], cfg["rtol"], cfg["atol"], save_times=save,
+                                        params_shared=True)
+        loss_kind, scale = "mse", 1.0 / (n * cfg["n_save"] * y0.shape[1])
+        tgt_host = np.transpose(loss_data.double().cpu().numpy(), (2, 0, 1))
 
     # pool plan from a pilot record of a sample of the ensemble
     m = min(n, 8192)
     pilot = B.ensemble_record(cfg["system"], cfg["method"], y0_d[:, :m].contiguous(),
-                              p_d[:, :m].contiguous(), cfg["t0"], cfg["t1"], cfg["rtol"],
-                              cfg["atol"], save_times=save, steps_hint=4096)
+                              p_d if shared else p_d[:, :m].contiguous(), cfg["t0"], cfg["t1"],
+                              cfg["rtol"], cfg["atol"], save_times=save, steps_hint=4096,
+                              params_shared=shared)
     s_pilot = pilot.steps().double()
     cap_cpu = int(s_pilot.max().item() * 1.5) + 64
     hint = B.steps_hint_for(float(s_pilot.mean().item()), margin=1.12)
     del pilot
     nbytes = B.ensemble_record_bytes(cfg["system"], cfg["method"], n, cfg["t0"], cfg["t1"], hint,
-                                     cfg["n_save"])
+                                     cfg["n_save"], tdt, ckpt)
     pool = torch.empty(nbytes, dtype=torch.uint8, device=dev)
 
     stream = torch.cuda.current_stream()
@@ -106,10 +127,12 @@ def main():
     def step(events=None):
         if events:
             events[0].record(stream)
-        rec = B.ensemble_record(*args_common, save_times=save, pool=pool, steps_per_traj=hint)
+        rec = B.ensemble_record(*args_common, save_times=save, pool=pool, steps_per_traj=hint,
+                                params_shared=shared, ckpt_every=ckpt)
         if events:
             events[1].record(stream)
-        gp, gy, ll = B.ensemble_adjoint(rec, want_y0=True, want_loss=True)
+        gp, gy, ll = B.ensemble_adjoint(rec, loss_kind, loss_data, scale, want_y0=True,
+                                        want_loss=True)
         if events:
             events[2].record(stream)
         return rec, gp, gy, ll
@@ -152,6 +175,12 @@ def main():
     if args.traffic and os.path.exists(args.traffic):
         tr = json.load(open(args.traffic))
         traffic = tr.get(dominant)
+    if cfg["system"] == "ude":
+        bound, peak = "mfma", PEAK_FP32_TFLOPS
+        kname = f"ude_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel (f32)"
+    else:
+        bound, peak = "alu", (PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS)
+        kname = f"erk_{dominant}_kernel ({cfg['system']}, {cfg['method']}, {'f32' if f32 else 'f64'})"
     out = {
         "metric": METRIC if args.workload == "lorenz_2p20_t10" else "trajectory-gradients/s (fwd+adjoint)",
         "value": value,
@@ -163,16 +192,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if f32 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "system": cfg["system"], "method": cfg["method"],
                    "n": n, "t_span": [cfg["t0"], cfg["t1"]], "rtol": cfg["rtol"],
-                   "atol": cfg["atol"], "n_save": cfg["n_save"],
-                   "loss": "sum of squared save states", "gradient": "per-trajectory params"},
-        "roofline": {"bound": "alu",
-                     "kernel": f"erk_{dominant}_kernel ({cfg['system']}, {cfg['method']}, f64)",
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},
+                   "atol": cfg["atol"], "n_save": cfg["n_save"], "ckpt_every": ckpt,
+                   "loss": ("MSE to teacher-network trajectories" if loss_kind == "mse"
+                            else "sum of squared save states"),
+                   "gradient": "shared weights" if shared else "per-trajectory params"},
+        "roofline": {"bound": bound, "kernel": kname,
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic},
         "kernels_ms": {"record": rec_ms, "adjoint": adj_ms},
         "algorithmic_flop": {"record": f_rec, "adjoint": f_adj,
                              "total_tflops": (f_rec + f_adj) / (ms_per_step * 1e-3) / 1e12},
@@ -182,7 +212,8 @@ def main():
                          "pool_gb": nbytes / 1e9},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, args.cpu_seconds, cap_cpu)
+        out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, args.cpu_seconds, cap_cpu, tgt_host,
+                                           scale)
     print(json.dumps(out), flush=True)
 
 

@@ -79,11 +79,16 @@ extern "C" {
 #define ENS_SYS_ROBERTSON 3 /* d = 3, P = 3: (k1, k2, k3); stiff */
 #define ENS_SYS_HIRES 4     /* d = 8, P = 12: the rate constants in order of
                                first appearance; stiff */
+#define ENS_SYS_LV_UDE 5    /* d = 2, P = 1218: Lotka-Volterra (1.5, 1, 3, 1) plus a
+                               2-32-32-2 tanh MLP, weights W1 [32][2], b1, W2 [32][32],
+                               b2, W3 [2][32], b3; shared by all trajectories
+                               (params_shared = 1), Tsit5, F32 */
 #define ENS_SYS_LINEAR 6    /* d = 2, P = 2: (a, w) */
 
 /* Methods (paper, Section 3.2).  The explicit pairs run on LORENZ, VDP and
- * LINEAR in F64 or F32; the Rosenbrock method on ROBERTSON, HIRES and
- * LINEAR in F64.  Other combinations return ENS_EUNSUPPORTED. */
+ * LINEAR in F64 or F32, Tsit5 also on LV_UDE in F32; the Rosenbrock method on
+ * ROBERTSON, HIRES and LINEAR in F64.  Other combinations return
+ * ENS_EUNSUPPORTED. */
 #define ENS_TSIT5 1  /* Tsitouras 5(4), 7 stages, first-same-as-last */
 #define ENS_VERN7 2  /* Verner 7(6), 10 stages */
 #define ENS_RODAS4 3 /* Rosenbrock-Wanner Rodas4 (Hairer-Wanner IV.7), order

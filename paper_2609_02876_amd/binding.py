@@ -15,6 +15,7 @@ import torch
 from . import _abi as A
 
 _DT = {torch.float64: A.F64, torch.float32: A.F32}
+SHARED_ONLY = ("ude",)   # systems whose parameters are always shared
 
 
 def _sysinfo(system):
@@ -99,9 +100,11 @@ def _view_i32(ptr, n, pool):
 
 
 def ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save=0,
-                          dtype=torch.float64, ckpt_every=0):
+                          dtype=torch.float64, ckpt_every=0, params_shared=None):
     sid, d, npar = _sysinfo(system)
-    prob = A.Problem(sid, A.METHODS[method], _DT[dtype], d, npar, 0)
+    if params_shared is None:
+        params_shared = system in SHARED_ONLY
+    prob = A.Problem(sid, A.METHODS[method], _DT[dtype], d, npar, int(params_shared))
     st = (C.c_double * max(1, n_save))(*([t1] * max(1, n_save)))
     ivp = A.Ivp(n, None, None, float(t0), float(t1), 1e-6, 1e-6, 0.0, 0, int(n_save),
                 C.cast(st, C.POINTER(C.c_double)))
@@ -112,14 +115,15 @@ def ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save=0,
 
 
 def plan_tape(system, method, n, t0, t1, steps_hint, n_save=0, dtype=torch.float64,
-              budget_bytes=None, ckpt_every=64):
+              budget_bytes=None, ckpt_every=64, shared=None):
     """Tape layout for a record: 0 (full tape) when its planned pool fits the
     HBM budget, else ckpt_every (one state per segment, the segment replayed
     in the reverse sweep).  Raises when neither fits."""
-    full = ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save, dtype, 0)
+    full = ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save, dtype, 0, shared)
     if budget_bytes is None or full <= budget_bytes:
         return 0
-    ck = ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save, dtype, ckpt_every)
+    ck = ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save, dtype, ckpt_every,
+                               shared)
     if ck > budget_bytes:
         raise ValueError(f"record needs {ck} bytes even with checkpoints every {ckpt_every} "
                          f"steps; budget is {budget_bytes}")
@@ -148,7 +152,7 @@ def _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every=0):
     else:
         nbytes = ensemble_record_bytes(spec.system, spec.method, spec.n, spec.ivp.t0,
                                        spec.ivp.t1, steps_hint, spec.ivp.n_save, spec.dtype,
-                                       ckpt_every)
+                                       ckpt_every, bool(spec.prob.params_shared))
         pool = torch.empty(nbytes, dtype=torch.uint8, device=spec.y0.device)
         spt = int(steps_hint)
     return pool, A.TapeCfg(pool.data_ptr(), pool.numel(), int(ckpt_every), spt)
@@ -168,7 +172,7 @@ def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=N
                  params_shared)
     if ckpt_every == "auto":
         ckpt_every = plan_tape(system, method, spec.n, t0, t1, steps_hint, spec.ivp.n_save,
-                               spec.dtype, tape_budget_bytes)
+                               spec.dtype, tape_budget_bytes, shared=bool(params_shared))
     pool, tc = _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every)
     rec = A.Record()
     y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)

@@ -11,6 +11,7 @@
 
 #include "ensode.h"
 #include "erk.h"
+#include "ude.h"
 
 using namespace ens;
 
@@ -42,6 +43,7 @@ bool sys_info(int sys, SysInfo* s) {
     case ENS_SYS_VDP: *s = {2, 1}; return true;
     case ENS_SYS_ROBERTSON: *s = {3, 3}; return true;
     case ENS_SYS_HIRES: *s = {8, 12}; return true;
+    case ENS_SYS_LV_UDE: *s = {2, UDE_NP}; return true;
     case ENS_SYS_LINEAR: *s = {2, 2}; return true;
   }
   return false;
@@ -66,6 +68,13 @@ int check_problem(const ens_problem* p, SysInfo* si) {
     return fail(ENS_EUNSUPPORTED, "unknown method %d", p->method);
   if (p->dtype != ENS_F64 && p->dtype != ENS_F32)
     return fail(ENS_EUNSUPPORTED, "unknown dtype %d", p->dtype);
+  if (p->system == ENS_SYS_LV_UDE) {
+    if (p->method != ENS_TSIT5 || p->dtype != ENS_F32)
+      return fail(ENS_EUNSUPPORTED, "the UDE is built for Tsit5 in F32 only");
+    if (p->params_shared != 1)
+      return fail(ENS_EINVAL, "the UDE's network weights are shared: params_shared must be 1");
+    return ENS_OK;
+  }
   const bool stiff_sys = p->system == ENS_SYS_ROBERTSON || p->system == ENS_SYS_HIRES;
   if (p->method == ENS_RODAS4) {
     if (!stiff_sys && p->system != ENS_SYS_LINEAR)
@@ -313,8 +322,32 @@ constexpr int BLOCK = 256;
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
+// Shared-parameter partials of the reverse sweep: one per block, or one per
+// wavefront for the UDE (whose gradient is reduced per wavefront).
+size_t partials_bytes(int sys, int64_t n, int np, int dtype) {
+  const size_t parts = (size_t)grid_of(n) * (sys == ENS_SYS_LV_UDE ? UDE_ADJ_WAVES : 1);
+  return align256(parts * np * elem_size(dtype));
+}
+
+int launch_forward_ude(int mode, bool ckpt, const FwdArgs& fa, hipStream_t st) {
+  const dim3 g(grid_of(fa.ivp.n)), b(BLOCK);
+  if (mode == MODE_SOLVE)
+    hipLaunchKernelGGL((ude_forward_kernel<MODE_SOLVE, false>), g, b, 0, st, fa);
+  else if (mode == MODE_RECORD && !ckpt)
+    hipLaunchKernelGGL((ude_forward_kernel<MODE_RECORD, false>), g, b, 0, st, fa);
+  else if (mode == MODE_RECORD)
+    hipLaunchKernelGGL((ude_forward_kernel<MODE_RECORD, true>), g, b, 0, st, fa);
+  else if (!ckpt)
+    hipLaunchKernelGGL((ude_forward_kernel<MODE_FROZEN, false>), g, b, 0, st, fa);
+  else
+    hipLaunchKernelGGL((ude_forward_kernel<MODE_FROZEN, true>), g, b, 0, st, fa);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ENS_OK : hip_fail(e, "forward launch");
+}
+
 int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
                    hipStream_t st) {
+  if (p->system == ENS_SYS_LV_UDE) return launch_forward_ude(mode, ckpt, fa, st);
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);
@@ -523,7 +556,7 @@ int ensemble_adjoint_workspace_bytes(const ens_record* r, size_t* bytes) {
   SysInfo si;
   if (!sys_info(r->system, &si)) return fail(ENS_EINVAL, "record of unknown system");
   size_t b = 0;
-  if (r->params_shared) b = align256((size_t)grid_of(r->n) * si.np * elem_size(r->dtype));
+  if (r->params_shared) b = partials_bytes(r->system, r->n, si.np, r->dtype);
   if (r->ckpt_every > 0) b += (size_t)r->n * r->page_steps * rec_bytes(r->dtype, r->dim);
   *bytes = b;
   return ENS_OK;
@@ -564,9 +597,21 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
   const bool shared = p->params_shared != 0;
   const bool ckpt = r->ckpt_every > 0;
   aa.scratch = ckpt ? (char*)workspace +
-                          (shared ? align256((size_t)grid_of(v->n) * si.np * elem_size(p->dtype)) : 0)
+                          (shared ? partials_bytes(p->system, v->n, si.np, p->dtype) : 0)
                     : nullptr;
   hipStream_t st = (hipStream_t)stream;
+  if (p->system == ENS_SYS_LV_UDE) {
+    const dim3 g(grid_of(v->n)), b(64 * UDE_ADJ_WAVES);
+    if (ckpt)
+      hipLaunchKernelGGL((ude_adjoint_kernel<true>), g, b, 0, st, aa);
+    else
+      hipLaunchKernelGGL((ude_adjoint_kernel<false>), g, b, 0, st, aa);
+    hipLaunchKernelGGL((reduce_partials_kernel<float>), dim3(UDE_NP), dim3(BLOCK), 0, st,
+                       (const float*)workspace, (int64_t)grid_of(v->n) * UDE_ADJ_WAVES, UDE_NP,
+                       (float*)grad_params);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
+  }
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);

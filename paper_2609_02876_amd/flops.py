@@ -42,6 +42,11 @@ SYSTEMS = {
     "robertson": (3, 8, 20),
     "hires": (8, 36, 77),
     "linear": (2, 6, 14),
+    # Lotka-Volterra + 2-32-32-2 tanh MLP (tanh = 1): the field is layers
+    # 128 + 2048 + 128, two tanh layers 64, bias/LV 14; the VJP recomputes the
+    # hidden layers (2240) and adds dW3/db3 130, delta2 and db2 224, W2^T
+    # delta2 2048, delta1/db1/dW1 256, W1^T delta1 + LV 136 and dW2 2048
+    "ude": (2, 2382, 7082),
 }
 
 # (jacobian flops, flops of d/d(y, p) of u^T J v) for the stiff path

@@ -113,10 +113,19 @@ WORKLOADS = {
                                 t1=1e5, rtol=1e-6, atol=1e-10, n_save=20),
     "hires_2p18": dict(system="hires", method="rodas4", n=1 << 18, t0=0.0, t1=321.8122,
                        rtol=1e-6, atol=1e-10, n_save=20),
+    # UDE: Lotka-Volterra + MLP 2-32-32-2 (weights shared), Tsit5, FP32,
+    # rtol = atol = 1e-6, 20 save times t = 0.5 s, loss = MSE to the teacher
+    # network's trajectories, tape checkpointed every 64 steps (or full)
+    "ude_2p16": dict(system="ude", method="tsit5", n=1 << 16, t0=0.0, t1=10.0, rtol=1e-6,
+                     atol=1e-6, n_save=20, dtype="f32", shared=True, loss="mse",
+                     ckpt_every=64),
+    "ude_2p16_full": dict(system="ude", method="tsit5", n=1 << 16, t0=0.0, t1=10.0,
+                          rtol=1e-6, atol=1e-6, n_save=20, dtype="f32", shared=True,
+                          loss="mse", ckpt_every=0),
 }
 
 GENERATORS = {"lorenz": lorenz, "vdp": vdp, "robertson": robertson, "hires": hires,
-              "linear": damped_rotation}
+              "linear": damped_rotation, "ude": ude}
 
 
 def make(name, n=None, seed=0):

@@ -158,3 +158,31 @@ def test_tape_plan_switches_to_checkpoints_over_budget():
     assert B.plan_tape(*args, budget_bytes=full - 1) == 64
     with pytest.raises(ValueError):
         B.plan_tape(*args, budget_bytes=ck - 1)
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({}, 0),
+    (dict(params_shared=0), A.ENS_EINVAL),
+    (dict(dtype=A.F64), A.ENS_EUNSUPPORTED),
+    (dict(method=A.VERN7), A.ENS_EUNSUPPORTED),
+])
+def test_ude_problem_checks(kw, code):
+    """The UDE runs Tsit5 in F32 with its 1218 network weights shared."""
+    lib = _lib()
+    out = C.c_size_t()
+    d = dict(system=A.SYS_LV_UDE, method=A.TSIT5, dtype=A.F32, dim=2, nparams=1218,
+             params_shared=1)
+    d.update(kw)
+    rc = lib.ensemble_record_bytes(C.byref(A.Problem(**d)), C.byref(_ivp()), 64, 0, C.byref(out))
+    assert rc == code
+
+
+def test_ude_pool_plan_through_the_binding():
+    _lib()
+    import torch
+    from paper_2609_02876_amd import binding as B
+    full = B.ensemble_record_bytes("ude", "tsit5", 4096, 0.0, 10.0, 256, 20, torch.float32)
+    ck = B.ensemble_record_bytes("ude", "tsit5", 4096, 0.0, 10.0, 256, 20, torch.float32, 64)
+    assert 0 < ck < full
+    assert B.plan_tape("ude", "tsit5", 4096, 0.0, 10.0, 256, 20, torch.float32,
+                       budget_bytes=full - 1) == 64
