@@ -35,6 +35,10 @@ def parse():
                     help="target CPU time of the oracle sample")
     ap.add_argument("--traffic", default=None,
                     help="JSON with measured HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--serve-jobs", type=int, default=120,
+                    help="jobs in the serving workload (--workload serve_mix)")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
+                    help="offered loads (fractions of the one-shot capacity)")
     return ap.parse_args()
 
 
@@ -84,6 +88,8 @@ def main():
     from paper_2609_02876_amd import flops
     from paper_2609_02876_amd import workloads as W
 
+    if args.workload == "serve_mix":
+        return serve_bench(args)
     cfg, y0, p, st = W.make(args.workload, n=args.n)
     n = cfg["n"]
     save = list(st) if cfg["n_save"] else None
@@ -214,6 +220,121 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, args.cpu_seconds, cap_cpu, tgt_host,
                                            scale)
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Mixed ensemble-gradient jobs through the server (continuous batching)
+    against the same trajectories as one-shot launches, one per (system, rtol)
+    group, and as plain per-job launches.  Jobs: systems uniform over Lorenz,
+    Van der Pol (Tsit5), Robertson and HIRES (Rodas4); lanes 2^(8 + 8u);
+    rtol in {1e-4, 1e-6, 1e-8} (HIRES: 1e-4, 1e-6); atol = 1e-2 rtol
+    (explicit) or 1e-4 rtol (stiff); loss = |y(t1)|^2; parameters seeded by
+    the job id; FP64."""
+    import numpy as np
+    import torch
+
+    from paper_2609_02876_amd import binding as B
+    from paper_2609_02876_amd import serving as SV
+    from paper_2609_02876_amd import workloads as W
+
+    span = {"lorenz": 10.0, "vdp": 6.3, "robertson": 1e5, "hires": 321.8122}
+    method = {"lorenz": "tsit5", "vdp": "tsit5", "robertson": "rodas4", "hires": "rodas4"}
+    rng = np.random.default_rng(2026)
+    dev = torch.device("cuda:0")
+    jobs = []
+    for k in range(args.serve_jobs):
+        system = ["lorenz", "vdp", "robertson", "hires"][int(rng.integers(0, 4))]
+        n = int(round(2 ** (8 + 8 * rng.random())))
+        rtols = [1e-4, 1e-6] if system == "hires" else [1e-4, 1e-6, 1e-8]
+        rtol = rtols[int(rng.integers(0, len(rtols)))]
+        atol = rtol * (1e-2 if system in ("lorenz", "vdp") else 1e-4)
+        y0, p = W.GENERATORS[system](n, seed=k)
+        jobs.append(dict(system=system, method=method[system], n=n, rtol=rtol, atol=atol,
+                         y0=torch.tensor(np.ascontiguousarray(y0.T), device=dev),
+                         p=torch.tensor(np.ascontiguousarray(p.T), device=dev)))
+    groups = {}
+    for j in jobs:
+        groups.setdefault((j["system"], j["rtol"]), []).append(j)
+
+    # memory plan per group: a pilot record's longest trajectory, +20 %
+    hints = {}
+    for (system, rtol), js in groups.items():
+        j = js[0]
+        h = B.ensemble_record(system, j["method"], j["y0"], j["p"], 0.0, span[system], rtol,
+                              j["atol"], steps_hint=4096)
+        hints[(system, rtol)] = int(h.steps().max().item() * 1.2) + 32
+    for j in jobs:
+        j["hint"] = hints[(j["system"], j["rtol"])]
+    total = sum(j["n"] for j in jobs)
+
+    def run_plain(j):
+        h = B.ensemble_record(j["system"], j["method"], j["y0"], j["p"], 0.0, span[j["system"]],
+                              j["rtol"], j["atol"], steps_hint=j["hint"])
+        B.ensemble_adjoint(h, want_y0=True, want_loss=True)
+        return h
+
+    # one-shot: all trajectories of a (system, rtol) group as one ensemble
+    cat = {key: dict(js[0], y0=torch.cat([j["y0"] for j in js], 1),
+                     p=torch.cat([j["p"] for j in js], 1), n=sum(j["n"] for j in js))
+           for key, js in groups.items()}
+    for c in cat.values():
+        run_plain(c)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for c in cat.values():
+        run_plain(c)
+    torch.cuda.synchronize()
+    t_oneshot = time.perf_counter() - t
+    t = time.perf_counter()
+    for j in jobs:
+        run_plain(j)
+    torch.cuda.synchronize()
+    t_perjob = time.perf_counter() - t
+    cap = total / t_oneshot
+
+    pool = max(sum(B.ensemble_record_bytes(j["system"], j["method"], j["n"], 0.0,
+                                           span[j["system"]], j["hint"]) for j in jobs) // 3,
+               4 << 30)
+
+    def serve(load):
+        srv = SV.Server(pool, n_slots=4)
+        arrive = np.cumsum(rng.exponential(total / len(jobs) / (load * cap), len(jobs))) \
+            if load else np.zeros(len(jobs))
+        t0 = time.perf_counter()
+        for k, j in enumerate(jobs):
+            while time.perf_counter() - t0 < arrive[k]:
+                srv.progress()
+            srv.submit(j["system"], j["method"], j["y0"], j["p"], 0.0, span[j["system"]],
+                       j["rtol"], j["atol"], steps_hint=j["hint"])
+        srv.drain()
+        st = srv.stats()
+        srv.close()
+        return st
+
+    serve(0)  # warm-up
+    sat = serve(0)   # everything submitted at once: the served capacity
+    loads = {}
+    for x in [float(v) for v in args.serve_loads.split(",") if v]:
+        st = serve(x)
+        loads[str(x)] = {"p50_ms": st["p50_latency_s"] * 1e3, "p99_ms": st["p99_latency_s"] * 1e3,
+                         "throughput": st["throughput"], "retried": st["retried"],
+                         "failed": st["failed"]}
+    out = {
+        "metric": "served trajectory-gradients/s (mixed jobs, continuous batching)",
+        "value": sat["throughput"], "unit": "trajectory-gradients/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": sat["busy_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serve_mix", "jobs": len(jobs), "trajectories": total,
+                   "systems": ["lorenz", "vdp", "robertson", "hires"], "lanes": "2^(8+8u)",
+                   "rtol": [1e-4, 1e-6, 1e-8], "slots": 4, "pool_gb": pool / 1e9},
+        "oneshot_throughput": cap,
+        "served_over_oneshot": sat["throughput"] / cap,
+        "perjob_throughput": total / t_perjob,
+        "saturated": {"p50_ms": sat["p50_latency_s"] * 1e3, "p99_ms": sat["p99_latency_s"] * 1e3,
+                      "retried": sat["retried"], "failed": sat["failed"]},
+        "poisson_loads": loads,
+    }
     print(json.dumps(out), flush=True)
 
 

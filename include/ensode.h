@@ -258,6 +258,85 @@ int ensemble_record_stats(const ens_record* rec, ens_stats* out, void* stream);
 /* Text of the calling thread's last error. */
 const char* ensemble_last_error(void);
 
+/* ---- serving: continuous batching of ensemble-gradient jobs ------------
+ * A server owns a caller-provided device pool and runs submitted jobs -- each
+ * one ensemble_record + ensemble_adjoint on its own trajectories -- on the
+ * GPU as they arrive.  Admission is by memory: a job is admitted when its
+ * record (planned from steps_hint) fits in the free part of the pool; until
+ * then it waits in FIFO order.  Admitted jobs of one (system, method,
+ * dtype) family are packed into one launch of a persistent kernel: a grid
+ * sized to the GPU whose blocks pull 256-trajectory tiles of any packed job
+ * from a device-resident queue and run the record and the reverse sweep of
+ * that tile back to back.  Up to n_slots launches are in flight on separate
+ * streams, so jobs that arrive while others run are admitted as memory and
+ * slots free up and their work overlaps on the device.
+ *
+ * A job's results are those of ensemble_record + ensemble_adjoint run alone
+ * on it, to the bit: no arithmetic depends on the co-scheduled jobs.  A job
+ * whose record runs out of pages (a lane reports ENS_LANE_NOSPACE) is run
+ * again with twice the steps_hint (at most 3 times) before it fails.
+ *
+ * Per-trajectory parameters only (params_shared = 0); the UDE is not served.
+ * A server is used from one host thread at a time.  Every device pointer of a
+ * job must stay valid until the job is done or failed. */
+typedef struct ens_server ens_server; /* opaque */
+
+typedef struct {
+  ens_problem prob;      /* params_shared must be 0 */
+  ens_ivp ivp;           /* y0, params: device; save_times: host (copied at submit) */
+  ens_loss loss;         /* loss.data: device, or NULL for ENS_LOSS_SUMSQ */
+  int64_t steps_hint;    /* expected accepted steps per trajectory; 0 = 512 */
+  void* y_save;          /* out [n_save][dim][n] (n_save = 1 when ivp.n_save = 0) */
+  int32_t* lane_status;  /* out [n] or NULL */
+  void* grad_params;     /* out [P][n] */
+  void* grad_y0;         /* out [dim][n] or NULL */
+  double* loss_out;      /* out [n] or NULL */
+} ens_job;
+
+#define ENS_JOB_WAITING 0
+#define ENS_JOB_RUNNING 1
+#define ENS_JOB_DONE 2
+#define ENS_JOB_FAILED (-1)
+
+typedef struct {
+  int64_t submitted, completed, failed, retried, running, waiting;
+  int64_t lanes_completed;   /* trajectory-gradients delivered */
+  double p50_latency_s;      /* submission to completion, completed jobs */
+  double p99_latency_s;
+  double mean_latency_s;
+  double busy_s;             /* first submission to last completion */
+  double throughput;         /* lanes_completed / busy_s */
+  size_t pool_in_use, pool_peak, pool_arena;
+} ens_server_stats;
+
+/* Create a server over the device pool [pool, pool + pool_bytes) (256-byte
+ * aligned; the caller keeps it alive until destroy).  n_slots in [1, 8]
+ * launches may be in flight.  Creates its streams and pinned staging
+ * buffers; allocates no device memory.  EINVAL: bad arguments or a pool too
+ * small for the control area (n_slots x about 1 MiB). */
+int ensemble_server_create(void* pool, size_t pool_bytes, int32_t n_slots, ens_server** out);
+
+/* Queue a job (validated here: EINVAL / EUNSUPPORTED as ensemble_record and
+ * ensemble_adjoint would return) and start it if it fits.  *id names it. */
+int ensemble_server_submit(ens_server* s, const ens_job* job, int64_t* id);
+
+/* Retire finished launches and start waiting jobs; never blocks.
+ * *n_active (may be NULL) = jobs waiting or running. */
+int ensemble_server_progress(ens_server* s, int32_t* n_active);
+
+/* State of a job (ENS_JOB_*); EINVAL for an unknown id. */
+int ensemble_server_poll(ens_server* s, int64_t id, int32_t* state);
+
+/* Make progress until job `id` (or, for ensemble_server_drain, every job)
+ * is done or failed. */
+int ensemble_server_wait(ens_server* s, int64_t id);
+int ensemble_server_drain(ens_server* s);
+
+int ensemble_server_stats(const ens_server* s, ens_server_stats* out);
+
+/* Waits for in-flight work, then frees the server's streams and buffers. */
+int ensemble_server_destroy(ens_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,9 +68,30 @@ class Loss(C.Structure):
     _fields_ = [("kind", C.c_int32), ("data", C.c_void_p), ("scale", C.c_double)]
 
 
+class Job(C.Structure):
+    _fields_ = [("prob", Problem), ("ivp", Ivp), ("loss", Loss), ("steps_hint", C.c_int64),
+                ("y_save", C.c_void_p), ("lane_status", C.c_void_p), ("grad_params", C.c_void_p),
+                ("grad_y0", C.c_void_p), ("loss_out", C.c_void_p)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("retried", C.c_int64), ("running", C.c_int64), ("waiting", C.c_int64),
+                ("lanes_completed", C.c_int64), ("p50_latency_s", C.c_double),
+                ("p99_latency_s", C.c_double), ("mean_latency_s", C.c_double),
+                ("busy_s", C.c_double), ("throughput", C.c_double),
+                ("pool_in_use", C.c_size_t), ("pool_peak", C.c_size_t),
+                ("pool_arena", C.c_size_t)]
+
+
+JOB_WAITING, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, -1
+
 EXPORTS = ("ensemble_solve", "ensemble_record_bytes", "ensemble_record",
            "ensemble_replay_mesh", "ensemble_mesh_export", "ensemble_adjoint",
            "ensemble_adjoint_workspace_bytes", "ensemble_record_stats",
+           "ensemble_server_create", "ensemble_server_submit", "ensemble_server_progress",
+           "ensemble_server_poll", "ensemble_server_wait", "ensemble_server_drain",
+           "ensemble_server_stats", "ensemble_server_destroy",
            "ensemble_last_error")
 
 _lib = None
@@ -98,6 +119,15 @@ def load(build_if_missing=True):
                                      Ptr, C.c_size_t, Ptr]
     lib.ensemble_adjoint_workspace_bytes.argtypes = [C.POINTER(Record), C.POINTER(C.c_size_t)]
     lib.ensemble_record_stats.argtypes = [C.POINTER(Record), C.POINTER(Stats), Ptr]
+    S = C.c_void_p
+    lib.ensemble_server_create.argtypes = [Ptr, C.c_size_t, C.c_int32, C.POINTER(S)]
+    lib.ensemble_server_submit.argtypes = [S, C.POINTER(Job), C.POINTER(C.c_int64)]
+    lib.ensemble_server_progress.argtypes = [S, C.POINTER(C.c_int32)]
+    lib.ensemble_server_poll.argtypes = [S, C.c_int64, C.POINTER(C.c_int32)]
+    lib.ensemble_server_wait.argtypes = [S, C.c_int64]
+    lib.ensemble_server_drain.argtypes = [S]
+    lib.ensemble_server_stats.argtypes = [S, C.POINTER(ServerStats)]
+    lib.ensemble_server_destroy.argtypes = [S]
     lib.ensemble_last_error.argtypes = []
     lib.ensemble_last_error.restype = C.c_char_p
     for f in EXPORTS[:-1]:

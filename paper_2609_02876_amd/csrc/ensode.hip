@@ -657,3 +657,5 @@ int ensemble_record_stats(const ens_record* r, ens_stats* out, void* stream) {
 }
 
 }  // extern "C"
+
+#include "server.h"

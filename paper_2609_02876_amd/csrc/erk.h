@@ -488,13 +488,13 @@ __device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
 // CKPT (checkpointed tape): a page covers R.page_steps accepted steps and
 // holds the state before its first step followed by the step sizes only.
 template <class Sys, class Tab, class T, int MODE, bool CKPT>
-__global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
+__device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block) {
   constexpr int D = Sys::D, NP = Sys::NP;
   constexpr int RB = TapeRec<T, D>::BYTES;
   constexpr int YB = StateBytes<T, D>::BYTES;
   const int K = CKPT ? a.rec.page_steps : PAGE_STEPS;
   const int64_t n = a.ivp.n;
-  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tr = block * blockDim.x + threadIdx.x;
   // save times in LDS (lane-varying index, short latency); slot n_save holds
   // +inf so that "no save left" needs no branch
   __shared__ double s_times[65];
@@ -778,13 +778,13 @@ __device__ __forceinline__ void save_cotangent(const AdjArgs& a, int s,
 // bits), then walks it backward.  Replay steps and reverse steps share one
 // loop iteration so that lanes at different phases do not serialize.
 template <class Sys, class Tab, class T, bool SHARED, bool CKPT>
-__global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
+__device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block) {
   constexpr int D = Sys::D, NP = Sys::NP, SU = Tab::SU;
   constexpr int RB = TapeRec<T, D>::BYTES;
   constexpr int YB = StateBytes<T, D>::BYTES;
   const int K = CKPT ? a.rec.page_steps : PAGE_STEPS;
   const int64_t n = a.ivp.n;
-  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tr = block * blockDim.x + threadIdx.x;
   const bool valid = tr < n;
   const RecView& R = a.rec;
   const bool ok = valid && R.status[tr] == LANE_OK;
@@ -987,10 +987,20 @@ __global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
         if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
         __syncthreads();
       }
-      if (threadIdx.x == 0) ((T*)a.workspace)[(int64_t)blockIdx.x * NP + c] = red[0];
+      if (threadIdx.x == 0) ((T*)a.workspace)[block * NP + c] = red[0];
       __syncthreads();
     }
   }
+}
+
+template <class Sys, class Tab, class T, int MODE, bool CKPT>
+__global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
+  erk_forward_body<Sys, Tab, T, MODE, CKPT>(a, blockIdx.x);
+}
+
+template <class Sys, class Tab, class T, bool SHARED, bool CKPT>
+__global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
+  erk_adjoint_body<Sys, Tab, T, SHARED, CKPT>(a, blockIdx.x);
 }
 
 // Sum of the per-block partials of shared-parameter gradients, in a fixed

@@ -637,37 +637,40 @@ __global__ void __launch_bounds__(64 * UDE_ADJ_WAVES) ude_adjoint_kernel(const A
       for (int c = 0; c < D; ++c) w[c] = lam[c];
     }
 
-    // reverse through the stages (every lane; zero cotangent where idle)
+    // reverse through the stages (every lane, zero cotangent where idle);
+    // skipped when no lane of the wavefront reverses a step (segment replays)
     T Yb[SU][D], lin[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) lin[c] = w[c];
+    if (__any(rev)) {
 #pragma unroll
-    for (int j = SU - 1; j >= 0; --j) {
-      T kb[D];
+      for (int j = SU - 1; j >= 0; --j) {
+        T kb[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        T acc = T(0);
-        bool first = true;
-        if (Tab::B[j] != 0.0) {
-          acc = T(Tab::B[j]) * w[c];
-          first = false;
-        }
+        for (int c = 0; c < D; ++c) {
+          T acc = T(0);
+          bool first = true;
+          if (Tab::B[j] != 0.0) {
+            acc = T(Tab::B[j]) * w[c];
+            first = false;
+          }
 #pragma unroll
-        for (int l2 = j + 1; l2 < SU; ++l2) {
-          if (Tab::A[l2][j] != 0.0) {
-            if (first) {
-              acc = T(Tab::A[l2][j]) * Yb[l2][c];
-              first = false;
-            } else {
-              acc = fmaT(T(Tab::A[l2][j]), Yb[l2][c], acc);
+          for (int l2 = j + 1; l2 < SU; ++l2) {
+            if (Tab::A[l2][j] != 0.0) {
+              if (first) {
+                acc = T(Tab::A[l2][j]) * Yb[l2][c];
+                first = false;
+              } else {
+                acc = fmaT(T(Tab::A[l2][j]), Yb[l2][c], acc);
+              }
             }
           }
+          kb[c] = T(hh) * acc;
         }
-        kb[c] = T(hh) * acc;
-      }
-      Sys::vjp(Y[j], p, kb, Yb[j], g);
+        Sys::vjp(Y[j], p, kb, Yb[j], g);
 #pragma unroll
-      for (int c = 0; c < D; ++c) lin[c] = lin[c] + Yb[j][c];
+        for (int c = 0; c < D; ++c) lin[c] = lin[c] + Yb[j][c];
+      }
     }
     if (!rev) continue;
 
