@@ -34,12 +34,42 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--traffic", default=None,
-                    help="JSON with measured HBM bytes per launch of the dominant kernel")
+                    help="JSON with measured HBM bytes per launch of the kernels (default: "
+                         "profiles/<workload>_traffic.json when its source hash matches)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy MIB MiB on the device before the timed steps (a kernel of known "
+                         "traffic for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serve-jobs", type=int, default=120,
                     help="jobs in the serving workload (--workload serve_mix)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="offered loads (fractions of the one-shot capacity)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: measured traffic is used only for the build it
+    was measured on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2609_02876_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(path, workload):
+    """Measured HBM bytes per launch {record, adjoint}, or None when absent
+    or taken on other kernel sources."""
+    if path is None:
+        path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    if tr.get("source_hash") != kernel_source_hash():
+        return None
+    return tr
 
 
 def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
@@ -143,6 +173,14 @@ def main():
             events[2].record(stream)
         return rec, gp, gy, ll
 
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device=dev)
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         rec, gp, gy, ll = step()
     torch.cuda.synchronize()
@@ -178,15 +216,16 @@ def main():
     f_dom, ms_dom = (f_adj, adj_ms) if dominant == "adjoint" else (f_rec, rec_ms)
     achieved = f_dom / (ms_dom * 1e-3) / 1e12
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        tr = json.load(open(args.traffic))
+    tr = load_traffic(args.traffic, args.workload)
+    if tr is not None and tr.get("n") == n:
         traffic = tr.get(dominant)
     if cfg["system"] == "ude":
         bound, peak = "mfma", PEAK_FP32_TFLOPS
         kname = f"ude_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel (f32)"
     else:
         bound, peak = "alu", (PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS)
-        kname = f"erk_{dominant}_kernel ({cfg['system']}, {cfg['method']}, {'f32' if f32 else 'f64'})"
+        kname = (f"erk_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel "
+                 f"({cfg['system']}, {cfg['method']}, {'f32' if f32 else 'f64'})")
     out = {
         "metric": METRIC if args.workload == "lorenz_2p20_t10" else "trajectory-gradients/s (fwd+adjoint)",
         "value": value,

@@ -782,10 +782,12 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   constexpr int D = Sys::D, NP = Sys::NP, SU = Tab::SU;
   constexpr int RB = TapeRec<T, D>::BYTES;
   constexpr int YB = StateBytes<T, D>::BYTES;
+  constexpr int CH = RB / 16;
   const int K = CKPT ? a.rec.page_steps : PAGE_STEPS;
   const int64_t n = a.ivp.n;
   const int64_t tr = block * blockDim.x + threadIdx.x;
   const bool valid = tr < n;
+  __shared__ uint4 s_rd[TAPE_GROUP * CH * 256];
   const RecView& R = a.rec;
   const bool ok = valid && R.status[tr] == LANE_OK;
   T* gpo = (T*)a.grad_p;
@@ -826,6 +828,10 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   // Tape position of the step record of mesh step i (h_i, y_{i-1}).
   int32_t i = S;
   int slot = S > 0 ? (S - 1) % K : 0;
+  // Tape reads: the TAPE_GROUP records of a 128-byte line are loaded into
+  // LDS together (chunk-major, as in the record) when the sweep enters the
+  // line, so each line is fetched once although it serves TAPE_GROUP steps.
+  int grp = -1;  // first slot of the staged group; -1: none
 
   // checkpointed tape: segment replay state
   char* scr = CKPT ? (char*)a.scratch + (int64_t)tr * K * RB : nullptr;
@@ -839,6 +845,7 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
     rebuild = true;
     j_rb = 0;
     seg_len = len;
+    grp = -1;
   };
   if (CKPT && S > 0) start_segment(slot + 1);
 
@@ -865,10 +872,23 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
         hh = ((const double*)(R.pages + (int64_t)page * R.page_bytes + YB))[j_rb];
 #pragma unroll
         for (int c = 0; c < D; ++c) yb[c] = y_rb[c];
-      } else if (CKPT) {
-        load_rec<T, D>(scr + slot * RB, hh, yb);
       } else {
-        load_rec<T, D>(R.pages + (int64_t)page * R.page_bytes + slot * RB, hh, yb);
+        const int g0 = slot & ~(TAPE_GROUP - 1);
+        if (g0 != grp) {
+          const char* base = CKPT ? scr : R.pages + (int64_t)page * R.page_bytes;
+          const uint4* src = reinterpret_cast<const uint4*>(
+              __builtin_assume_aligned(base + g0 * RB, 16));
+#pragma unroll
+          for (int q = 0; q < TAPE_GROUP * CH; ++q) s_rd[q * 256 + threadIdx.x] = src[q];
+          grp = g0;
+        }
+        RecBuf<T, D> b;
+        uint4* dst = reinterpret_cast<uint4*>(&b);
+#pragma unroll
+        for (int q = 0; q < CH; ++q) dst[q] = s_rd[((slot - g0) * CH + q) * 256 + threadIdx.x];
+        hh = b.h;
+#pragma unroll
+        for (int c = 0; c < D; ++c) yb[c] = b.y[c];
       }
     }
 
@@ -954,6 +974,7 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
       if (--slot < 0 && i > 0) {
         page = prev_page(R, page);
         slot = K - 1;
+        grp = -1;
         if (CKPT) start_segment(K);
       }
     }
@@ -998,8 +1019,18 @@ __global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
   erk_forward_body<Sys, Tab, T, MODE, CKPT>(a, blockIdx.x);
 }
 
+// Blocks per CU the compiler is asked to fit in the reverse sweep: 3 for the
+// FP64 Lorenz / Tsit5 sweep (3 waves per SIMD), which otherwise lands a few
+// registers above that occupancy; no request for the others.
+template <class Sys, class Tab, class T>
+struct AdjBlocks {
+  static constexpr int value =
+      (Sys::ID == 1 && Tab::ORDER == 5 && !Tab::ROS && sizeof(T) == 8) ? 3 : 1;
+};
+
 template <class Sys, class Tab, class T, bool SHARED, bool CKPT>
-__global__ void __launch_bounds__(256) erk_adjoint_kernel(const AdjArgs a) {
+__global__ void __launch_bounds__(256, (AdjBlocks<Sys, Tab, T>::value))
+    erk_adjoint_kernel(const AdjArgs a) {
   erk_adjoint_body<Sys, Tab, T, SHARED, CKPT>(a, blockIdx.x);
 }
 
