@@ -540,14 +540,14 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
                        : initial_step<Sys, Tab, T>(y, p, k1, t0, t1, rtol, atol);
   }
 
-  T yp[D], k1p[D];  // base state (and its slope) of the last accepted step
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    yp[c] = y[c];
-    k1p[c] = k1[c];
-  }
+  // Side steps of the save times.  After a step is accepted whose interval
+  // holds save times, the new state is held back (yn, kn at tn) and the
+  // following iterations take the side steps from the unchanged base (y, k1
+  // at t); the last one commits the new state.  So every evaluation starts
+  // from (y, k1), with no per-iteration select between two bases.
+  T yn[D], kn[D];
+  double tn = t0;
   if constexpr (MODE != MODE_SOLVE) R.first_page[tr] = -1;
-  double tp = t0;
   int next_save = 0;
   // running pointers to this lane's next save-state slots
   T* ys_out = ysv + tr;
@@ -560,6 +560,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   bool prev_rej = false;
   int32_t page = -1;
   char* pg = nullptr;
+  int slot = 0, kpage = 0;  // position of the next taped step: S = K kpage + slot
 
   while (status == LANE_OK &&
          (side || (MODE == MODE_FROZEN ? (S < S_mesh) : (t < t1)))) {
@@ -587,46 +588,41 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         hh = h;
       }
     } else {
-      hh = ts - tp;
+      hh = ts - t;
     }
 
-    // one evaluation of the step map from the selected base
-    T yb[D], ynew[D], klast[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) yb[c] = side ? yp[c] : y[c];
+    // one evaluation of the step map from the base (y, k1)
+    T ynew[D], klast[D];
     double err = 0.0;
     if constexpr (Tab::ROS) {
       // a side step onto the base point itself is the identity (1/(gamma h)
-      // would divide by zero): evaluate at a harmless h and keep yb
+      // would divide by zero): evaluate at a harmless h and keep y
       const bool zero = (hh == 0.0);
       T W[D * D], u[Tab::S][D];
       int piv[D];
-      ros_step<Sys, Tab, T>(yb, p, T(zero ? 1.0 : hh), W, piv, u, ynew);
+      ros_step<Sys, Tab, T>(y, p, T(zero ? 1.0 : hh), W, piv, u, ynew);
 #pragma unroll
-      for (int c = 0; c < D; ++c) ynew[c] = zero ? yb[c] : ynew[c];
-      if constexpr (MODE != MODE_FROZEN) err = ros_err<D, T>(yb, ynew, u[Tab::S - 1], rtol, atol);
+      for (int c = 0; c < D; ++c) ynew[c] = zero ? y[c] : ynew[c];
+      if constexpr (MODE != MODE_FROZEN) err = ros_err<D, T>(y, ynew, u[Tab::S - 1], rtol, atol);
     } else {
       T kb[D];
       if constexpr (Tab::FSAL) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) kb[c] = side ? k1p[c] : k1[c];
+        for (int c = 0; c < D; ++c) kb[c] = k1[c];
       } else {
-        Sys::rhs(yb, p, kb);
+        Sys::rhs(y, p, kb);
       }
       T Yunused[Tab::S][D];
       T ylast[D];
       double esum[D];
       step_push<Sys, Tab, T, Tab::S, false, !Tab::FSAL, MODE != MODE_FROZEN>(
-          yb, kb, p, T(hh), Yunused, ylast, klast, ynew, esum);
+          y, kb, p, T(hh), Yunused, ylast, klast, ynew, esum);
       if constexpr (Tab::FSAL) {
 #pragma unroll
         for (int c = 0; c < D; ++c) ynew[c] = ylast[c];
       }
-      if constexpr (MODE != MODE_FROZEN) err = err_norm_sum<T, D>(yb, ynew, hh, esum, rtol, atol);
+      if constexpr (MODE != MODE_FROZEN) err = err_norm_sum<T, D>(y, ynew, hh, esum, rtol, atol);
     }
-    double fac0 = 0.0;
-    // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
-    if constexpr (MODE != MODE_FROZEN) fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
 
     if (side) {
 #pragma unroll
@@ -640,14 +636,23 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       }
       ++next_save;
       ts = s_times[next_save];
-      side = ts < t;
+      side = ts < tn;
+      if (!side) {  // the last save of the interval: commit the new state
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          y[c] = yn[c];
+          if constexpr (Tab::FSAL) k1[c] = kn[c];
+        }
+        t = tn;
+      }
       continue;
     }
 
+    // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
+    double fac0 = 0.0;
+    if constexpr (MODE != MODE_FROZEN) fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
     if (MODE == MODE_FROZEN || err <= 1.0) {
       if constexpr (MODE != MODE_SOLVE) {
-        const int slot = S % K;
-        const int kpage = S / K;
         const bool need = (slot == 0);
         const bool over = need && (kpage >= R.static_pages);
         const uint64_t got = wave_bump(&R.counters[CNT_PAGES], over);
@@ -673,51 +678,57 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
           pg = R.pages + (int64_t)page * R.page_bytes;
         }
         if constexpr (CKPT) {
-          if (need) store_state<T, D>(pg, yb);
+          if (need) store_state<T, D>(pg, y);
           s_h[(slot % H_GROUP) * 256 + threadIdx.x] = hh;
           if (slot % H_GROUP == H_GROUP - 1)
             flush_h(s_h, H_GROUP, pg + YB + (slot - (H_GROUP - 1)) * 8);
         } else {
-          stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, yb);
+          stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, y);
           if (slot % TAPE_GROUP == TAPE_GROUP - 1)
             flush_recs<T, D>(s_tape, TAPE_GROUP, pg + (slot - (TAPE_GROUP - 1)) * RB);
         }
+        if (++slot == K) {
+          slot = 0;
+          ++kpage;
+        }
       }
       ++S;
-      tp = t;
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        yp[c] = y[c];
-        k1p[c] = k1[c];
-        y[c] = ynew[c];
-      }
-      if constexpr (Tab::FSAL) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) k1[c] = klast[c];
-      }
-      t = last ? t1 : t + hh;
+      const double tnew = last ? t1 : t + hh;
       if constexpr (MODE != MODE_FROZEN) {
         h = hh * fmax(0.2, fmin(prev_rej ? 1.0 : 10.0, fac0));
         prev_rej = false;
       }
-      side = ts < t;
+      side = ts < tnew;
+      if (side) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          yn[c] = ynew[c];
+          if constexpr (Tab::FSAL) kn[c] = klast[c];
+        }
+        tn = tnew;
+      } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          y[c] = ynew[c];
+          if constexpr (Tab::FSAL) k1[c] = klast[c];
+        }
+        t = tnew;
+      }
     } else {
       h = hh * fmax(0.2, fac0);
       prev_rej = true;
     }
   }
 
-  // records of an unfinished group
+  // records of an unfinished group (S = K kpage + slot; groups never
+  // straddle a page because K is a multiple of the group size)
   if constexpr (MODE != MODE_SOLVE) {
     if constexpr (CKPT) {
       const int rem = S % H_GROUP;
-      if (rem > 0 && pg != nullptr) flush_h(s_h, rem, pg + YB + ((S - rem) % K) * 8);
+      if (rem > 0 && pg != nullptr) flush_h(s_h, rem, pg + YB + (slot - rem) * 8);
     } else {
       const int rem = S % TAPE_GROUP;
-      if (rem > 0 && pg != nullptr) {
-        const int slot0 = (S - rem) % K;
-        flush_recs<T, D>(s_tape, rem, pg + slot0 * RB);
-      }
+      if (rem > 0 && pg != nullptr) flush_recs<T, D>(s_tape, rem, pg + (slot - rem) * RB);
     }
   }
 
@@ -1014,8 +1025,17 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   }
 }
 
+// Blocks per CU the compiler is asked to fit in the record of the FP64
+// Lorenz / Tsit5 ensemble (4: four waves per SIMD); no request otherwise.
+template <class Sys, class Tab, class T>
+struct FwdBlocks {
+  static constexpr int value =
+      (Sys::ID == 1 && Tab::ORDER == 5 && !Tab::ROS && sizeof(T) == 8) ? 4 : 1;
+};
+
 template <class Sys, class Tab, class T, int MODE, bool CKPT>
-__global__ void __launch_bounds__(256) erk_forward_kernel(const FwdArgs a) {
+__global__ void __launch_bounds__(256, (FwdBlocks<Sys, Tab, T>::value))
+    erk_forward_kernel(const FwdArgs a) {
   erk_forward_body<Sys, Tab, T, MODE, CKPT>(a, blockIdx.x);
 }
 
