@@ -798,7 +798,10 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   const int64_t n = a.ivp.n;
   const int64_t tr = block * blockDim.x + threadIdx.x;
   const bool valid = tr < n;
-  __shared__ uint4 s_rd[TAPE_GROUP * CH * 256];
+  // tape lines staged through LDS for records of up to 32 bytes; larger
+  // records (their systems run at one wave per SIMD) are read directly
+  constexpr bool STAGE = CH <= 2;
+  __shared__ uint4 s_rd[STAGE ? TAPE_GROUP * CH * 256 : 1];
   const RecView& R = a.rec;
   const bool ok = valid && R.status[tr] == LANE_OK;
   T* gpo = (T*)a.grad_p;
@@ -883,6 +886,8 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
         hh = ((const double*)(R.pages + (int64_t)page * R.page_bytes + YB))[j_rb];
 #pragma unroll
         for (int c = 0; c < D; ++c) yb[c] = y_rb[c];
+      } else if constexpr (!STAGE) {
+        load_rec<T, D>((CKPT ? scr : R.pages + (int64_t)page * R.page_bytes) + slot * RB, hh, yb);
       } else {
         const int g0 = slot & ~(TAPE_GROUP - 1);
         if (g0 != grp) {
