@@ -661,33 +661,42 @@ __global__ void __launch_bounds__(64 * UDE_ADJ_WAVES) ude_adjoint_kernel(const A
 #pragma unroll
     for (int c = 0; c < D; ++c) lin[c] = w[c];
     if (__any(rev)) {
-#pragma unroll
+      // One stage per trip of a loop that is not unrolled, so that one copy
+      // of the VJP (and its registers) serves all stages; the stage arrays
+      // are read and written by selects over the constant stage index.
+      // Tsit5's b_j and a_lj (l > j) are all nonzero, so the sum is
+      // b_j w + a_{j+1,j} Ybar_{j+1} + ... in index order, as unrolled.
+      static_assert(Tab::B[0] != 0.0 && Tab::B[5] != 0.0 && Tab::A[5][4] != 0.0 &&
+                        Tab::A[5][0] != 0.0 && Tab::A[4][0] != 0.0,
+                    "dense lower triangle expected");
+#pragma unroll 1
       for (int j = SU - 1; j >= 0; --j) {
-        T kb[D];
+        T kb[D], Yj[D], Ybj[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-          T acc = T(0);
-          bool first = true;
-          if (Tab::B[j] != 0.0) {
-            acc = T(Tab::B[j]) * w[c];
-            first = false;
-          }
+          T yj = Y[0][c];
 #pragma unroll
-          for (int l2 = j + 1; l2 < SU; ++l2) {
-            if (Tab::A[l2][j] != 0.0) {
-              if (first) {
-                acc = T(Tab::A[l2][j]) * Yb[l2][c];
-                first = false;
-              } else {
-                acc = fmaT(T(Tab::A[l2][j]), Yb[l2][c], acc);
-              }
-            }
+          for (int q = 1; q < SU; ++q) yj = (q == j) ? Y[q][c] : yj;
+          Yj[c] = yj;
+          T acc = T(Tab::B[0]) * w[c];
+#pragma unroll
+          for (int q = 1; q < SU; ++q) acc = (q == j) ? T(Tab::B[q]) * w[c] : acc;
+#pragma unroll
+          for (int l2 = 1; l2 < SU; ++l2) {
+            T a = T(0);
+#pragma unroll
+            for (int q = 0; q < l2; ++q) a = (q == j) ? T(Tab::A[l2][q]) : a;
+            acc = (l2 > j) ? fmaT(a, Yb[l2][c], acc) : acc;
           }
           kb[c] = T(hh) * acc;
         }
-        Sys::vjp(Y[j], p, kb, Yb[j], g);
+        Sys::vjp(Yj, p, kb, Ybj, g);
 #pragma unroll
-        for (int c = 0; c < D; ++c) lin[c] = lin[c] + Yb[j][c];
+        for (int c = 0; c < D; ++c) {
+          lin[c] = lin[c] + Ybj[c];
+#pragma unroll
+          for (int q = 0; q < SU; ++q) Yb[q][c] = (q == j) ? Ybj[c] : Yb[q][c];
+        }
       }
     }
     if (!rev) continue;
