@@ -291,7 +291,7 @@ constexpr int32_t LANE_IDLE = -1;  // a lane past the end of the ensemble
 // record with a wave-uniform loop -- lanes whose trajectory is done take
 // zero-length steps until the whole wavefront is done.
 template <int MODE, bool CKPT>
-__global__ void __launch_bounds__(256) ude_forward_kernel(const FwdArgs a) {
+__global__ void __launch_bounds__(256, 2) ude_forward_kernel(const FwdArgs a) {
   using Sys = LvUde;
   using Tab = Tsit5;
   using T = float;
