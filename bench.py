@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB MiB on the device before the timed steps (a kernel of known "
                          "traffic for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--write-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU run: turn the counter output of two rocprofv3 --pmc runs of this "
+                         "script (FETCH_SIZE, then WRITE_SIZE, both with --copy-calibration) into "
+                         "profiles/<workload>_traffic.json")
     ap.add_argument("--serve-jobs", type=int, default=120,
                     help="jobs in the serving workload (--workload serve_mix)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
@@ -70,6 +74,55 @@ def load_traffic(path, workload):
     if tr.get("source_hash") != kernel_source_hash():
         return None
     return tr
+
+
+def write_traffic(fetch_dir, write_dir, workload, n, mib):
+    """HBM bytes per launch of the record and the sweep kernel, from rocprofv3
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch).  Each counter is scaled by
+    known / counted for the calibration copy of `mib` MiB (the device copy
+    kernel with the largest count); the full-size dispatches of each kernel
+    (the largest grid: the pool-sizing pilot is smaller) are averaged."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+        if not rows:
+            raise SystemExit(f"no {counter} rows under {d}")
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not copies:
+            raise SystemExit(f"no calibration copy in {d} (run with --copy-calibration)")
+        factor = (mib << 10) / max(copies)
+        out = {}
+        for part, key in (("record", "_forward_kernel<"), ("adjoint", "_adjoint_kernel<")):
+            ks = [r for r in rows if key in r["Kernel_Name"]]
+            if not ks:
+                raise SystemExit(f"no {part} kernel rows under {d}")
+            g = max(int(r["Grid_Size"]) for r in ks)
+            vals = [float(r["Counter_Value"]) for r in ks if int(r["Grid_Size"]) == g]
+            out[part] = {"kib": sum(vals) / len(vals), "dispatches": len(vals), "grid": g}
+        return out, factor
+
+    fe, ff = read(fetch_dir, "FETCH_SIZE")
+    wr, wf = read(write_dir, "WRITE_SIZE")
+    tr = {"workload": workload, "n": n, "source_hash": kernel_source_hash(),
+          "calibration": {"copy_mib": mib, "fetch_factor": ff, "write_factor": wf}}
+    for part in ("record", "adjoint"):
+        fb, wb = fe[part]["kib"] * 1024 * ff, wr[part]["kib"] * 1024 * wf
+        tr[part] = fb + wb
+        tr[part + "_detail"] = {"fetch_bytes": fb, "write_bytes": wb,
+                                "fetch_kib_counted": fe[part]["kib"],
+                                "write_kib_counted": wr[part]["kib"],
+                                "dispatches": fe[part]["dispatches"],
+                                "grid_threads": fe[part]["grid"]}
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(tr, f, indent=1)
+        f.write("\n")
+    print(json.dumps(tr))
 
 
 def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
@@ -106,6 +159,10 @@ def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        from paper_2609_02876_amd import workloads as W
+        n = args.n or W.WORKLOADS[args.workload]["n"]
+        return write_traffic(*args.write_traffic, args.workload, n, args.copy_calibration or 1024)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ensemble "
               "shards by trajectory with no exchange, so more GPUs are not exercised here.",

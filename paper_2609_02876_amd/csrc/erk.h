@@ -445,7 +445,7 @@ __device__ __forceinline__ void flush_h(const double* s_h, int count, char* hp) 
   if (q < count) reinterpret_cast<double*>(hp)[q] = s_h[q * 256 + threadIdx.x];
 }
 
-constexpr int TAPE_GROUP = 4;  // step records staged per lane before a write
+constexpr int TAPE_GROUP = 4;  // step records per lane written together
 
 // Put one record into this lane's staging slots starting at chunk q0.
 template <class T, int D>
@@ -498,11 +498,12 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   // save times in LDS (lane-varying index, short latency); slot n_save holds
   // +inf so that "no save left" needs no branch
   __shared__ double s_times[65];
-  // Tape staging: each lane collects GROUP consecutive step records here and
-  // writes them out together as whole cache lines.  Chunk-major layout
-  // (chunk, lane) keeps the 16-byte LDS accesses free of bank conflicts.
+  // Tape staging: each lane collects the first GROUP - 1 step records of a
+  // group here and writes them, together with the last one straight from
+  // registers, as whole cache lines.  Chunk-major layout (chunk, lane) keeps
+  // the 16-byte LDS accesses free of bank conflicts.
   constexpr int CH = TapeRec<T, D>::BYTES / 16;
-  __shared__ uint4 s_tape[(MODE == MODE_SOLVE || CKPT) ? 1 : TAPE_GROUP * CH * 256];
+  __shared__ uint4 s_tape[(MODE == MODE_SOLVE || CKPT) ? 1 : (TAPE_GROUP - 1) * CH * 256];
   // checkpointed tape: step sizes staged H_GROUP at a time (one 128-byte line)
   __shared__ double s_h[CKPT ? H_GROUP * 256 : 1];
   if (threadIdx.x < 65)
@@ -683,9 +684,13 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
           if (slot % H_GROUP == H_GROUP - 1)
             flush_h(s_h, H_GROUP, pg + YB + (slot - (H_GROUP - 1)) * 8);
         } else {
-          stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, y);
-          if (slot % TAPE_GROUP == TAPE_GROUP - 1)
-            flush_recs<T, D>(s_tape, TAPE_GROUP, pg + (slot - (TAPE_GROUP - 1)) * RB);
+          if (slot % TAPE_GROUP == TAPE_GROUP - 1) {
+            char* gp = pg + (slot - (TAPE_GROUP - 1)) * RB;
+            flush_recs<T, D>(s_tape, TAPE_GROUP - 1, gp);
+            store_rec<T, D>(gp + (TAPE_GROUP - 1) * RB, hh, y);
+          } else {
+            stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, y);
+          }
         }
         if (++slot == K) {
           slot = 0;
@@ -1031,7 +1036,8 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
 }
 
 // Blocks per CU the compiler is asked to fit in the record of the FP64
-// Lorenz / Tsit5 ensemble (4: four waves per SIMD); no request otherwise.
+// Lorenz / Tsit5 ensemble (4: four waves per SIMD; five need a 96-register
+// budget that spills and runs 50 % slower); no request otherwise.
 template <class Sys, class Tab, class T>
 struct FwdBlocks {
   static constexpr int value =
