@@ -807,6 +807,11 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   // records (their systems run at one wave per SIMD) are read directly
   constexpr bool STAGE = CH <= 2;
   __shared__ uint4 s_rd[STAGE ? TAPE_GROUP * CH * 256 : 1];
+  // Rosenbrock factors of d >= 6 held in LDS during the transposed solves
+  // (64 doubles a lane for d = 8 would otherwise push the reverse step past
+  // the register file into scratch); one wave per SIMD either way
+  constexpr bool W_LDS = Tab::ROS && D >= 6;
+  __shared__ T s_W[W_LDS ? D * D * 256 : 1];
   const RecView& R = a.rec;
   const bool ok = valid && R.status[tr] == LANE_OK;
   T* gpo = (T*)a.grad_p;
@@ -920,7 +925,9 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
     T W[NW], u[NU][D];
     int piv[D];
     T Y[NY][D], ys[D];
-    if constexpr (Tab::ROS) {
+    if constexpr (W_LDS) {
+      ros_step_lds<Sys, Tab, T>(yb, p, T(hh), LdsMat<T>{s_W}, piv, u, ys);
+    } else if constexpr (Tab::ROS) {
       ros_step<Sys, Tab, T>(yb, p, T(hh), W, piv, u, ys);
     } else {
       T k0[D], ylast[D], klast[D];
@@ -946,8 +953,19 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
 
     // reverse through the stages: kbar_j = h (b_j w + sum_{l>j} a_lj Ybar_l)
     T Yb[NY][D], lin[D];
-    if constexpr (Tab::ROS) {
-      ros_step_vjp<Sys, Tab, T>(yb, p, T(hh), W, piv, u, w, lin, gp);
+    if constexpr (W_LDS) {
+      const LdsMat<T> Wl{s_W};
+      // the reverse recomputes the stage states and Jacobian terms from
+      // (y, u) rather than keeping the forward's copies live
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        opaque(yb[c]);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) opaque(u[q][c]);
+      }
+      ros_step_vjp<Sys, Tab, T, LdsMat<T>>(yb, p, T(hh), Wl, piv, u, w, lin, gp);
+    } else if constexpr (Tab::ROS) {
+      ros_step_vjp<Sys, Tab, T, T[NW]>(yb, p, T(hh), W, piv, u, w, lin, gp);
     } else {
 #pragma unroll
     for (int c = 0; c < D; ++c) lin[c] = w[c];

@@ -90,9 +90,47 @@ __device__ __forceinline__ void permute_bwd(const int (&piv)[D], T* v) {
   }
 }
 
-// x = W^{-1} b in place: L z = P b forward, then U x = z backward.
+// The factors of one lane held in LDS: element e at base[e * 256 + lane]
+// (consecutive lanes on consecutive words, so a wave's access is one
+// conflict-free sweep).  Indexing as for a register array.
+template <class T>
+struct LdsMat {
+  T* base;
+  __device__ __forceinline__ T operator[](int e) const { return base[e * 256 + threadIdx.x]; }
+};
+
+// Before each solve from LDS: a compiler memory barrier, so that every solve
+// reads the factors afresh instead of the compiler merging the reads of
+// successive solves (which would keep all the factors in registers).
+template <class T>
+__device__ __forceinline__ void reload_point(const LdsMat<T>&) {
+  __asm__ __volatile__("" ::: "memory");
+}
+template <class A>
+__device__ __forceinline__ void reload_point(const A&) {}
+
+// An optimisation barrier on a value: the compiler must treat x as changed,
+// so expressions of it formed afterwards are computed afresh instead of
+// reusing (and keeping alive) equal ones formed before.  No instruction.
+template <class T>
+__device__ __forceinline__ void opaque(T& x) {
+  __asm__ __volatile__("" : "+v"(x));
+}
+
+// Copy register factors into a lane's LDS slots.  The empty asm with a
+// memory clobber keeps the compiler from forwarding the stored values to the
+// later reads, which would keep the factors live in registers after all.
 template <int D, class T>
-__device__ __forceinline__ void lu_solve(const T (&W)[D * D], const int (&piv)[D], T* x) {
+__device__ __forceinline__ void put_lds(const T (&W)[D * D], const LdsMat<T>& M) {
+#pragma unroll
+  for (int e = 0; e < D * D; ++e) M.base[e * 256 + threadIdx.x] = W[e];
+  __asm__ __volatile__("" ::: "memory");
+}
+
+// x = W^{-1} b in place: L z = P b forward, then U x = z backward.
+template <int D, class T, class Mat>
+__device__ __forceinline__ void lu_solve(const Mat& W, const int (&piv)[D], T* x) {
+  reload_point(W);
   permute_fwd<D, T>(piv, x);
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -111,8 +149,10 @@ __device__ __forceinline__ void lu_solve(const T (&W)[D * D], const int (&piv)[D
 }
 
 // z = W^{-T} b in place: U^T v = b forward, L^T w = v backward, z = P^T w.
-template <int D, class T>
-__device__ __forceinline__ void lu_solve_t(const T (&W)[D * D], const int (&piv)[D], T* z) {
+// W: the factors as a register array or an LdsMat.
+template <int D, class T, class Mat>
+__device__ __forceinline__ void lu_solve_t(const Mat& W, const int (&piv)[D], T* z) {
+  reload_point(W);
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     T acc = z[i];
@@ -132,11 +172,13 @@ __device__ __forceinline__ void lu_solve_t(const T (&W)[D * D], const int (&piv)
 
 // The increments u_1..u_s of one step from y with step h (h != 0), the
 // factors left in W/piv for the reverse, and y_new = Y_s + u_s.
-template <class Sys, class Tab, class T>
-__device__ __forceinline__ void ros_step(const T* y, const T* p, T h, T (&W)[Sys::D * Sys::D],
-                                         int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D], T* ynew) {
+// The stages after the factorisation; W: the factors as a register array or
+// an LdsMat.
+template <class Sys, class Tab, class T, class Mat>
+__device__ __forceinline__ void ros_stages(const T* y, const T* p, T h, const Mat& W,
+                                           const int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D],
+                                           T* ynew) {
   constexpr int D = Sys::D, NS = Tab::S;
-  ros_factor<Sys, Tab, T>(y, p, h, W, piv);
   const T hinv = T(1.0) / h;
   T Yi[D];
 #pragma unroll
@@ -169,22 +211,42 @@ __device__ __forceinline__ void ros_step(const T* y, const T* p, T h, T (&W)[Sys
       }
       u[i][c] = first ? F[c] : fmaT(acc, hinv, F[c]);
     }
-    lu_solve<D, T>(W, piv, u[i]);
+    lu_solve<D, T, Mat>(W, piv, u[i]);
   }
 #pragma unroll
   for (int c = 0; c < D; ++c) ynew[c] = Yi[c] + u[NS - 1][c];
 }
 
-// Reverse of one step (W, piv, u from ros_step at the same y, h): with the
+template <class Sys, class Tab, class T>
+__device__ __forceinline__ void ros_step(const T* y, const T* p, T h, T (&W)[Sys::D * Sys::D],
+                                         int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D], T* ynew) {
+  ros_factor<Sys, Tab, T>(y, p, h, W, piv);
+  ros_stages<Sys, Tab, T, T[Sys::D * Sys::D]>(y, p, h, W, piv, u, ynew);
+}
+
+// The same step with the factors moved to this lane's LDS slots right after
+// the factorisation (the same values, so the same results), for systems
+// whose factors crowd the registers of the reverse sweep.
+template <class Sys, class Tab, class T>
+__device__ __forceinline__ void ros_step_lds(const T* y, const T* p, T h, const LdsMat<T>& Wl,
+                                             int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D],
+                                             T* ynew) {
+  T W[Sys::D * Sys::D];
+  ros_factor<Sys, Tab, T>(y, p, h, W, piv);
+  put_lds<Sys::D, T>(W, Wl);
+  ros_stages<Sys, Tab, T, LdsMat<T>>(y, p, h, Wl, piv, u, ynew);
+}
+
+// Reverse of one step (W, piv, u from ros_step at the same y, h; W as a
+// register array or an LdsMat): with the
 // output cotangent w, lam_in = d(y_new)/dy^T w and gp += d(y_new)/dp^T w.
 //   ubar_i = M_i w + sum_{l>i} (A_li Ybar_l + C_li rbar_l / h)   (l from s down)
 //   rbar_i = W^{-T} ubar_i,  Ybar_i = f_y(Y_i)^T rbar_i,  gp += f_p(Y_i)^T rbar_i
 //   lam_in = w + sum_i Ybar_i + d/dy sum_i rbar_i^T J(y) u_i,
 // the last term (and its p part, into gp) from each stage in turn.  Stage
 // cotangents are pushed into running sums as they are formed.
-template <class Sys, class Tab, class T>
-__device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h,
-                                             const T (&W)[Sys::D * Sys::D],
+template <class Sys, class Tab, class T, class Mat>
+__device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h, const Mat& W,
                                              const int (&piv)[Sys::D],
                                              const T (&u)[Tab::S][Sys::D], const T* w,
                                              T* lam_in, T* gp) {
@@ -208,7 +270,7 @@ __device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h,
     T rb[D], tb[D], Yi[D], Yb[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) rb[c] = ub[i][c];
-    lu_solve_t<D, T>(W, piv, rb);
+    lu_solve_t<D, T, Mat>(W, piv, rb);
 #pragma unroll
     for (int c = 0; c < D; ++c) tb[c] = hinv * rb[c];
 #pragma unroll
