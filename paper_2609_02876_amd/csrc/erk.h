@@ -788,6 +788,34 @@ __device__ __forceinline__ void save_cotangent(const AdjArgs& a, int s,
   }
 }
 
+// Slot (trajectory offset in the block) this lane sweeps.  The block's 256
+// lanes take its trajectories in increasing order of their step counts (ties
+// by index; failed and absent ones first), so each wavefront gets sweeps of
+// nearly equal length and few lanes idle while the longest one finishes.  A
+// trajectory's results do not depend on the lane that computes it.
+__device__ __forceinline__ int sweep_slot(const RecView& R, int64_t base, int64_t n) {
+  __shared__ int4 s_key4[64];
+  __shared__ int s_slot[256];
+  int32_t* s_key = reinterpret_cast<int32_t*>(s_key4);
+  const int me = threadIdx.x;
+  const int64_t t = base + me;
+  const int32_t key = (t < n && R.status[t] == LANE_OK) ? R.steps[t] : -1;
+  s_key[me] = key;
+  __syncthreads();
+  int rank = 0;
+  for (int j4 = 0; j4 < 64; ++j4) {
+    const int4 v = s_key4[j4];
+    const int j = 4 * j4;
+    rank += (v.x < key || (v.x == key && j < me)) ? 1 : 0;
+    rank += (v.y < key || (v.y == key && j + 1 < me)) ? 1 : 0;
+    rank += (v.z < key || (v.z == key && j + 2 < me)) ? 1 : 0;
+    rank += (v.w < key || (v.w == key && j + 3 < me)) ? 1 : 0;
+  }
+  s_slot[rank] = me;
+  __syncthreads();
+  return s_slot[me];
+}
+
 // CKPT: the tape holds one state per page (segment) and the step sizes; the
 // sweep first replays each segment forward into this trajectory's scratch
 // page (full step records, the same arithmetic as the record, so the same
@@ -801,7 +829,9 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   constexpr int CH = RB / 16;
   const int K = CKPT ? a.rec.page_steps : PAGE_STEPS;
   const int64_t n = a.ivp.n;
-  const int64_t tr = block * blockDim.x + threadIdx.x;
+  const int64_t base = block * 256;  // blocks of 256 lanes
+  const int slot_in_block = sweep_slot(a.rec, base, n);
+  const int64_t tr = base + slot_in_block;
   const bool valid = tr < n;
   // tape lines staged through LDS for records of up to 32 bytes; larger
   // records (their systems run at one wave per SIMD) are read directly
@@ -1036,12 +1066,12 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
       a.loss_out[tr] = !ok ? NAN : (a.loss_kind == LOSS_COTANGENT ? 0.0 : loss);
   }
   if constexpr (SHARED) {
-    // shared parameters: fixed-order tree over the block's lanes (failed
-    // trajectories contribute nothing), one partial per block
+    // shared parameters: fixed-order tree over the block's trajectories in
+    // index order (failed ones contribute nothing), one partial per block
     __shared__ T red[256];
 #pragma unroll
     for (int c = 0; c < NP; ++c) {
-      red[threadIdx.x] = ok ? gp[c] : T(0);
+      red[slot_in_block] = ok ? gp[c] : T(0);
       __syncthreads();
       for (int off = 128; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
