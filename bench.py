@@ -147,11 +147,16 @@ def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
                       params_shared=shared)
         return time.perf_counter() - t
 
-    m = 256 if cfg["system"] == "ude" else 2048
-    dt = run(m)
-    m2 = int(min(len(y0), max(m, m * target_s / max(dt, 1e-3))))
-    m2 = max(m, (m2 // 64) * 64)
+    # grow the sample until it takes about target_s (small samples run below
+    # the threads' full rate, so one extrapolation falls short)
+    m2 = 256 if cfg["system"] == "ude" else 2048
     dt2 = run(m2)
+    for _ in range(3):
+        if dt2 >= 0.7 * target_s or m2 >= len(y0):
+            break
+        m2 = int(min(len(y0), m2 * target_s / max(dt2, 1e-3)))
+        m2 = max(64, (m2 // 64) * 64)
+        dt2 = run(m2)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": m2 / dt2, "unit": "trajectory-gradients/s", "cores": cores, "kind": "oracle",
             "sample": f"first {m2} trajectories of the workload, record + adjoint, {dt2:.1f} s"}
