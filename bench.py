@@ -81,7 +81,8 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib):
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch).  Each counter is scaled by
     known / counted for the calibration copy of `mib` MiB (the device copy
     kernel with the largest count); the full-size dispatches of each kernel
-    (the largest grid: the pool-sizing pilot is smaller) are averaged."""
+    (the largest grid: the pool-sizing pilot is smaller; the instantiation
+    dispatched most often) are averaged."""
     import csv
     import glob
 
@@ -101,7 +102,12 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib):
             if not ks:
                 raise SystemExit(f"no {part} kernel rows under {d}")
             g = max(int(r["Grid_Size"]) for r in ks)
-            vals = [float(r["Counter_Value"]) for r in ks if int(r["Grid_Size"]) == g]
+            ks = [r for r in ks if int(r["Grid_Size"]) == g]
+            # the instantiation dispatched most often: the timed launches (a
+            # forward-only solve of the same size, e.g. for targets, runs once)
+            names = [r["Kernel_Name"] for r in ks]
+            top = max(set(names), key=names.count)
+            vals = [float(r["Counter_Value"]) for r in ks if r["Kernel_Name"] == top]
             out[part] = {"kib": sum(vals) / len(vals), "dispatches": len(vals), "grid": g}
         return out, factor
 
