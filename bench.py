@@ -76,7 +76,7 @@ def load_traffic(path, workload):
     return tr
 
 
-def write_traffic(fetch_dir, write_dir, workload, n, mib):
+def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
     """HBM bytes per launch of the record and the sweep kernel, from rocprofv3
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch).  Each counter is scaled by
     known / counted for the calibration copy of `mib` MiB (the device copy
@@ -123,12 +123,14 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib):
                                 "write_kib_counted": wr[part]["kib"],
                                 "dispatches": fe[part]["dispatches"],
                                 "grid_threads": fe[part]["grid"]}
-    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
-    os.makedirs(os.path.dirname(path), exist_ok=True)
+    if path is None:
+        path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     with open(path, "w") as f:
         json.dump(tr, f, indent=1)
         f.write("\n")
     print(json.dumps(tr))
+    return tr
 
 
 def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
