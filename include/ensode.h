@@ -238,10 +238,11 @@ int ensemble_mesh_export(const ens_record* rec, double* h, int32_t* steps,
  * Trajectories whose record status is not ENS_LANE_OK get NaN per-trajectory
  * gradients and loss; with shared parameters they contribute nothing to the
  * sum.  Shared parameters (problem.params_shared) give grad_params [P],
- * summed over trajectories in a fixed order (run-to-run identical); they need
- * a device workspace of ensemble_adjoint_workspace_bytes bytes (otherwise
- * workspace may be NULL).  The ivp must describe the same ensemble as the
- * record. */
+ * summed over trajectories in a fixed order (run-to-run identical).  Shared
+ * parameters and a checkpointed tape need a caller-owned, 256-byte aligned
+ * device workspace of at least ensemble_adjoint_workspace_bytes bytes, not
+ * used by a concurrent call (otherwise workspace may be NULL; a missing, too
+ * small or misaligned workspace is ENS_EINVAL).  The ivp must describe the same ensemble as the record. */
 int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
                      const ens_record* rec, const ens_loss* loss,
                      void* grad_params, void* grad_y0, double* loss_out,
