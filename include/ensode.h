@@ -248,6 +248,25 @@ int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
                      void* grad_params, void* grad_y0, double* loss_out,
                      void* workspace, size_t workspace_bytes, void* stream);
 
+/* Forward mode on the recorded mesh (paper, Section 4, forward mode for few
+ * inputs; the mesh held fixed as in Section 3.1): the directional derivative
+ * of each trajectory's save states, and of its loss, along the tangent
+ * (dy0 [dim][n], dparams [P][n]) of its initial state and parameters, by a
+ * dual-number replay.  dy0 and dparams may be NULL (zero tangent); y_save_dot
+ * [n_save][dim][n] (device, dtype) and loss_dot [n] (device, double) may be
+ * NULL.  With the same unit tangent in every trajectory, one call gives every
+ * trajectory's derivative with respect to that input: P calls give the full
+ * per-trajectory gradient.  loss_dot needs loss (same kinds as
+ * ensemble_adjoint): 2 scale sum y . ydot (SUMSQ), 2 scale sum (y - target)
+ * . ydot (MSE_TARGET), sum c . ydot (COTANGENT).  Per-trajectory parameters
+ * only; built for Lorenz, Van der Pol and the damped rotation (Tsit5, Vern7;
+ * F64, F32) and Robertson and the damped rotation (Rodas4, F64); otherwise
+ * ENS_EUNSUPPORTED.  Trajectories whose record failed get NaN.  Full and
+ * checkpointed tapes alike (only the mesh is read). */
+int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* rec,
+                 const void* dy0, const void* dparams, const ens_loss* loss,
+                 void* y_save_dot, double* loss_dot, void* stream);
+
 /* Workspace ensemble_adjoint needs for this record: per-block partial sums
  * for shared parameters, plus one segment of step records per trajectory for
  * a checkpointed tape (0 for a full tape with per-trajectory parameters). */

@@ -255,6 +255,31 @@ def ensemble_adjoint(handle, loss="sumsq", data=None, scale=1.0, want_y0=True,
     return gp, gy, ll
 
 
+def ensemble_jvp(handle, dy0=None, dparams=None, loss="sumsq", data=None, scale=1.0,
+                 want_states=True, want_loss=True):
+    """Forward mode on the recorded mesh: (y_save_dot [n_save, d, n] or None,
+    loss_dot [n] or None) along the tangent dy0 [d, n], dparams [P, n]
+    (None: zero).  Per-trajectory parameters only."""
+    spec = handle.spec
+    if loss not in _LOSS:
+        raise ValueError(f"loss must be one of {sorted(_LOSS)}")
+    for name, t, shape in (("dy0", dy0, (spec.d, spec.n)), ("dparams", dparams, (spec.npar, spec.n)),
+                           ("loss data", data, (spec.n_save, spec.d, spec.n))):
+        if t is not None:
+            _require_gpu(t)
+            if t.dtype != spec.dtype or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {list(shape)} {spec.dtype} tensor")
+    dev = spec.y0.device
+    ysd = (torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=dev)
+           if want_states else None)
+    ld = torch.empty(spec.n, dtype=torch.float64, device=dev) if want_loss else None
+    lo = A.Loss(_LOSS[loss], data.data_ptr() if data is not None else None, float(scale))
+    A.check(A.load().ensemble_jvp(C.byref(spec.prob), C.byref(spec.ivp), C.byref(handle.rec),
+                                  _ptr(dy0), _ptr(dparams), C.byref(lo), _ptr(ysd), _ptr(ld),
+                                  _stream()))
+    return ysd, ld
+
+
 def ensemble_record_stats(handle):
     st = A.Stats()
     A.check(A.load().ensemble_record_stats(C.byref(handle.rec), C.byref(st), _stream()))

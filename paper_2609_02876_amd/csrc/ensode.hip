@@ -11,6 +11,7 @@
 
 #include "ensode.h"
 #include "erk.h"
+#include "jvp.h"
 #include "ude.h"
 
 using namespace ens;
@@ -631,6 +632,58 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
                          (T*)grad_params);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
+  });
+}
+
+int ensemble_jvp(const ens_problem* p, const ens_ivp* v, const ens_record* r,
+                 const void* dy0, const void* dparams, const ens_loss* loss,
+                 void* y_save_dot, double* loss_dot, void* stream) {
+  SysInfo si;
+  int rc;
+  if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
+  if ((rc = check_ivp(v, true)) != ENS_OK) return rc;
+  if ((rc = check_record_matches(p, v, r)) != ENS_OK) return rc;
+  if (p->params_shared)
+    return fail(ENS_EUNSUPPORTED, "forward mode takes per-trajectory parameters");
+  if (p->system == ENS_SYS_LV_UDE || p->system == ENS_SYS_HIRES)
+    return fail(ENS_EUNSUPPORTED,
+                "forward mode is built for the systems with few inputs per trajectory "
+                "(not HIRES or the UDE)");
+  int kind = -1;
+  if (loss_dot) {
+    if (!loss) return fail(ENS_EINVAL, "loss_dot needs a loss");
+    if (loss->kind != ENS_LOSS_SUMSQ && loss->kind != ENS_LOSS_MSE_TARGET &&
+        loss->kind != ENS_LOSS_COTANGENT)
+      return fail(ENS_EINVAL, "unknown loss kind %d", loss->kind);
+    if (loss->kind != ENS_LOSS_SUMSQ && !loss->data)
+      return fail(ENS_EINVAL, "loss data is NULL");
+    kind = loss->kind;
+  }
+  JvpArgs ja{};
+  ja.ivp = ivp_args(p, v);
+  ja.rec = view_of(r);
+  ja.dy0 = dy0;
+  ja.dp = dparams;
+  ja.loss_kind = kind;
+  ja.loss_data = kind >= 0 ? loss->data : nullptr;
+  ja.scale = kind >= 0 ? loss->scale : 1.0;
+  ja.ys_dot = y_save_dot;
+  ja.loss_dot = loss_dot;
+  const bool ck = r->ckpt_every > 0;
+  ja.rec_b = ck ? (int64_t)8 : (int64_t)r->rec_bytes;
+  ja.h_off = ck ? (int64_t)state_bytes(r->dtype, r->dim) : (int64_t)0;
+  hipStream_t st = (hipStream_t)stream;
+  return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
+    using Sys = decltype(s);
+    using Tab = decltype(m);
+    using T = decltype(t);
+    if constexpr (Sys::ID == Hires::ID) {
+      return fail(ENS_EUNSUPPORTED, "forward mode is not built for HIRES");
+    } else {
+      hipLaunchKernelGGL((jvp_kernel<Sys, Tab, T>), dim3(grid_of(v->n)), dim3(BLOCK), 0, st, ja);
+      hipError_t e = hipGetLastError();
+      return e == hipSuccess ? ENS_OK : hip_fail(e, "jvp launch");
+    }
   });
 }
 

@@ -200,13 +200,15 @@ __device__ __forceinline__ void step_push(const T* y, const T* k0, const T* p, T
           Zb[c] = fmaT(T(Tab::B[l]), kc[c], Zb[c]);
       }
     }
-    if (WANT_E && Tab::EW[l] != 0.0) {
+    if constexpr (WANT_E) {
+      if (Tab::EW[l] != 0.0) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        if (first_ew<Tab>() == l)
-          e[c] = Tab::EW[l] * (double)kc[c];
-        else
-          e[c] = fmaT(Tab::EW[l], (double)kc[c], e[c]);
+        for (int c = 0; c < D; ++c) {
+          if (first_ew<Tab>() == l)
+            e[c] = Tab::EW[l] * (double)kc[c];
+          else
+            e[c] = fmaT(Tab::EW[l], (double)kc[c], e[c]);
+        }
       }
     }
   }

@@ -15,6 +15,14 @@
 
 namespace ens {
 
+// c ? a : b for the values the factorisation moves by selects (a separate
+// function so that a scalar type made of several parts can select them part
+// by part).
+template <class T>
+__device__ __forceinline__ T pick(bool c, T a, T b) {
+  return c ? a : b;
+}
+
 // W = I/(gamma h) - J(y) factored as P W = L U (unit L below the diagonal,
 // U on and above it).  The pivot of column k is the first row i >= k with
 // the largest |W_ik|; piv[k] records it.
@@ -36,7 +44,7 @@ __device__ __forceinline__ void ros_factor(const T* y, const T* p, T h, T (&W)[S
     for (int i = k + 1; i < D; ++i) {
       const T v = fabs(W[i * D + k]);
       const bool gt = v > best;
-      best = gt ? v : best;
+      best = pick(gt, v, best);
       pk = gt ? i : pk;
     }
     piv[k] = pk;
@@ -46,8 +54,8 @@ __device__ __forceinline__ void ros_factor(const T* y, const T* p, T h, T (&W)[S
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         const T a = W[k * D + j], b = W[i * D + j];
-        W[k * D + j] = sw ? b : a;
-        W[i * D + j] = sw ? a : b;
+        W[k * D + j] = pick(sw, b, a);
+        W[i * D + j] = pick(sw, a, b);
       }
     }
 #pragma unroll
@@ -69,8 +77,8 @@ __device__ __forceinline__ void permute_fwd(const int (&piv)[D], T* v) {
     for (int i = k + 1; i < D; ++i) {
       const bool sw = (piv[k] == i);
       const T a = v[k], b = v[i];
-      v[k] = sw ? b : a;
-      v[i] = sw ? a : b;
+      v[k] = pick(sw, b, a);
+      v[i] = pick(sw, a, b);
     }
   }
 }
@@ -84,8 +92,8 @@ __device__ __forceinline__ void permute_bwd(const int (&piv)[D], T* v) {
     for (int i = k + 1; i < D; ++i) {
       const bool sw = (piv[k] == i);
       const T a = v[k], b = v[i];
-      v[k] = sw ? b : a;
-      v[i] = sw ? a : b;
+      v[k] = pick(sw, b, a);
+      v[i] = pick(sw, a, b);
     }
   }
 }
