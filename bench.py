@@ -29,6 +29,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lorenz_2p20_t10")
+    ap.add_argument("--mode", choices=("reverse", "forward"), default="reverse",
+                    help="gradient by the reverse sweep (default) or by forward-mode passes, "
+                         "one per parameter, on the recorded mesh")
     ap.add_argument("--n", type=int, default=None, help="override the trajectory count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -97,10 +100,13 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
             raise SystemExit(f"no calibration copy in {d} (run with --copy-calibration)")
         factor = (mib << 10) / max(copies)
         out = {}
-        for part, key in (("record", "_forward_kernel<"), ("adjoint", "_adjoint_kernel<")):
+        for part, key in (("record", "_forward_kernel<"), ("adjoint", "_adjoint_kernel<"),
+                          ("jvp", "jvp_kernel<")):
             ks = [r for r in rows if key in r["Kernel_Name"]]
             if not ks:
-                raise SystemExit(f"no {part} kernel rows under {d}")
+                if part == "record":
+                    raise SystemExit(f"no record kernel rows under {d}")
+                continue
             g = max(int(r["Grid_Size"]) for r in ks)
             ks = [r for r in ks if int(r["Grid_Size"]) == g]
             # the instantiation dispatched most often: the timed launches (a
@@ -115,7 +121,7 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
     wr, wf = read(write_dir, "WRITE_SIZE")
     tr = {"workload": workload, "n": n, "source_hash": kernel_source_hash(),
           "calibration": {"copy_mib": mib, "fetch_factor": ff, "write_factor": wf}}
-    for part in ("record", "adjoint"):
+    for part in [q for q in ("record", "adjoint", "jvp") if q in fe and q in wr]:
         fb, wb = fe[part]["kib"] * 1024 * ff, wr[part]["kib"] * 1024 * wf
         tr[part] = fb + wb
         tr[part + "_detail"] = {"fetch_bytes": fb, "write_bytes": wb,
@@ -175,7 +181,8 @@ def main():
     if args.write_traffic:
         from paper_2609_02876_amd import workloads as W
         n = args.n or W.WORKLOADS[args.workload]["n"]
-        return write_traffic(*args.write_traffic, args.workload, n, args.copy_calibration or 1024)
+        key = args.workload + ("_forward" if args.mode == "forward" else "")
+        return write_traffic(*args.write_traffic, key, n, args.copy_calibration or 1024)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ensemble "
               "shards by trajectory with no exchange, so more GPUs are not exercised here.",
@@ -190,6 +197,8 @@ def main():
 
     if args.workload == "serve_mix":
         return serve_bench(args)
+    if args.mode == "forward":
+        return forward_bench(args)
     cfg, y0, p, st = W.make(args.workload, n=args.n)
     n = cfg["n"]
     save = list(st) if cfg["n_save"] else None
@@ -334,6 +343,147 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, args.cpu_seconds, cap_cpu, tgt_host,
                                            scale)
+    print(json.dumps(out), flush=True)
+
+
+def forward_bench(args):
+    """Record + one forward-mode pass per parameter (the same unit tangent in
+    every trajectory), each pass returning every trajectory's derivative of
+    the loss with respect to that parameter: the per-trajectory parameter
+    gradient by forward mode on the recorded mesh."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2609_02876_amd import binding as B
+    from paper_2609_02876_amd import flops
+    from paper_2609_02876_amd import workloads as W
+
+    cfg, y0, p, st = W.make(args.workload, n=args.n)
+    if cfg.get("shared") or cfg["system"] in ("ude", "hires"):
+        raise SystemExit("forward mode is built for per-trajectory parameters of Lorenz, "
+                         "Van der Pol, the damped rotation and Robertson")
+    n = cfg["n"]
+    save = list(st) if cfg["n_save"] else None
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    f32 = cfg.get("dtype", "f64") == "f32"
+    tdt = torch.float32 if f32 else torch.float64
+    y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=tdt, device=dev)
+    p_d = torch.tensor(np.ascontiguousarray(p.T), dtype=tdt, device=dev)
+    npar = p.shape[1]
+    args_common = (cfg["system"], cfg["method"], y0_d, p_d, cfg["t0"], cfg["t1"], cfg["rtol"],
+                   cfg["atol"])
+    m = min(n, 8192)
+    pilot = B.ensemble_record(cfg["system"], cfg["method"], y0_d[:, :m].contiguous(),
+                              p_d[:, :m].contiguous(), cfg["t0"], cfg["t1"], cfg["rtol"],
+                              cfg["atol"], save_times=save, steps_hint=4096)
+    s_pilot = pilot.steps().double()
+    cap_cpu = int(s_pilot.max().item() * 1.5) + 64
+    hint = B.steps_hint_for(float(s_pilot.mean().item()), margin=1.12)
+    del pilot
+    nbytes = B.ensemble_record_bytes(cfg["system"], cfg["method"], n, cfg["t0"], cfg["t1"], hint,
+                                     cfg["n_save"], tdt, 0)
+    pool = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    tangents = []
+    for k in range(npar):
+        t = torch.zeros((npar, n), dtype=tdt, device=dev)
+        t[k] = 1.0
+        tangents.append(t)
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        if events:
+            events[0].record(stream)
+        rec = B.ensemble_record(*args_common, save_times=save, pool=pool, steps_per_traj=hint)
+        if events:
+            events[1].record(stream)
+        grads = [B.ensemble_jvp(rec, None, t, want_states=False)[1] for t in tangents]
+        if events:
+            events[2].record(stream)
+        return rec, grads
+
+    for _ in range(args.warmup):
+        rec, grads = step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rec, grads = step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bad = int((rec.status != 0).sum().item())
+    if bad:
+        raise RuntimeError(f"{bad} trajectories did not finish (status != OK)")
+    rec_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    fwd_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    pass_ms = fwd_ms / npar
+    stats = B.ensemble_record_stats(rec)
+    n_saves = n * (cfg["n_save"] or 1)
+    f_rec = flops.record_flops(cfg["method"], cfg["system"], stats["trials"],
+                               stats["steps_accepted"], stats["side_steps"])
+    f_pass = flops.jvp_flops(cfg["method"], cfg["system"], stats["steps_accepted"],
+                             stats["side_steps"], n_saves)
+    dominant = "jvp" if fwd_ms >= rec_ms else "record"
+    f_dom, ms_dom = (f_pass, pass_ms) if dominant == "jvp" else (f_rec, rec_ms)
+    achieved = f_dom / (ms_dom * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
+    traffic = None
+    tr = load_traffic(args.traffic, args.workload + "_forward")
+    if tr is not None and tr.get("n") == n:
+        traffic = tr.get(dominant)
+    ms_per_step = wall * 1e3 / args.steps
+    out = {
+        "metric": "trajectory-gradients/s (record + forward mode, one pass per parameter)",
+        "value": n * args.steps / wall, "unit": "trajectory-gradients/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if f32 else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "mode": "forward", "system": cfg["system"],
+                   "method": cfg["method"], "n": n, "t_span": [cfg["t0"], cfg["t1"]],
+                   "rtol": cfg["rtol"], "atol": cfg["atol"], "n_save": cfg["n_save"],
+                   "passes": npar, "loss": "sum of squared save states",
+                   "gradient": "per-trajectory params, one forward pass each"},
+        "roofline": {"bound": "alu",
+                     "kernel": (f"jvp_kernel ({cfg['system']}, {cfg['method']})"
+                                if dominant == "jvp" else
+                                f"erk_forward_kernel ({cfg['system']}, {cfg['method']})"),
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic},
+        "kernels_ms": {"record": rec_ms, "jvp_per_pass": pass_ms},
+        "algorithmic_flop": {"record": f_rec, "jvp_per_pass": f_pass,
+                             "total_tflops": (f_rec + npar * f_pass) / (ms_per_step * 1e-3) / 1e12},
+    }
+    if not args.no_cpu_baseline:
+        so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON,
+              "linear": O.LINEAR}[cfg["system"]]
+        mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS}[cfg["method"]]
+
+        def run(mm):
+            t = time.perf_counter()
+            r = O.record(so, mo, y0[:mm], p[:mm], cfg["t0"], cfg["t1"], cfg["rtol"], cfg["atol"],
+                         save_t=save, cap=cap_cpu)
+            for k in range(npar):
+                dp = np.zeros_like(p[:mm])
+                dp[:, k] = 1.0
+                ys, dys = O.replay_dual(so, mo, y0[:mm], p[:mm], np.zeros_like(y0[:mm]), dp, r)
+                np.sum(2.0 * ys * dys, axis=(1, 2))
+            return time.perf_counter() - t
+
+        m2 = 2048
+        dt2 = run(m2)
+        for _ in range(3):
+            if dt2 >= 0.7 * args.cpu_seconds or m2 >= n:
+                break
+            m2 = int(min(n, m2 * args.cpu_seconds / max(dt2, 1e-3)))
+            m2 = max(64, (m2 // 64) * 64)
+            dt2 = run(m2)
+        out["cpu_baseline"] = {
+            "value": m2 / dt2, "unit": "trajectory-gradients/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "kind": "oracle",
+            "sample": f"first {m2} trajectories, record + {npar} dual-number replays, {dt2:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

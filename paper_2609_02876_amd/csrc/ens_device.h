@@ -13,6 +13,27 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
+// Products and fmas with a factor that is a constant of the method (c) or of
+// the step (the step size h and 1/h): the mesh is fixed, so these factors
+// carry no tangent in forward mode, where a dual-number type overloads them.
+// For plain scalars they are the ordinary operations.
+template <class T>
+__device__ __forceinline__ T cmul(double c, T x) {
+  return T(c) * x;
+}
+template <class T>
+__device__ __forceinline__ T cfma(double c, T x, T acc) {
+  return fmaT(T(c), x, acc);
+}
+template <class T>
+__device__ __forceinline__ T hfma(T h, T x, T acc) {  // fma(h, x, acc)
+  return fmaT(h, x, acc);
+}
+template <class T>
+__device__ __forceinline__ T fmah(T x, T h, T acc) {  // fma(x, h, acc)
+  return fmaT(x, h, acc);
+}
+
 enum : int32_t {
   LANE_OK = 0,
   LANE_MAX_STEPS = 1,

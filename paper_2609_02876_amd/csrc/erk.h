@@ -174,7 +174,7 @@ __device__ __forceinline__ void step_push(const T* y, const T* k0, const T* p, T
     if (l > 0) {
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        Yl[c] = fmaT(h, Z[l][c], y[c]);
+        Yl[c] = hfma(h, Z[l][c], y[c]);
         if (KEEP_Y) Y[l][c] = Yl[c];
       }
       Sys::rhs(Yl, p, kc);
@@ -185,9 +185,9 @@ __device__ __forceinline__ void step_push(const T* y, const T* k0, const T* p, T
 #pragma unroll
         for (int c = 0; c < D; ++c) {
           if (first_a<Tab>(j) == l)
-            Z[j][c] = T(Tab::A[j][l]) * kc[c];
+            Z[j][c] = cmul(Tab::A[j][l], kc[c]);
           else
-            Z[j][c] = fmaT(T(Tab::A[j][l]), kc[c], Z[j][c]);
+            Z[j][c] = cfma(Tab::A[j][l], kc[c], Z[j][c]);
         }
       }
     }
@@ -195,9 +195,9 @@ __device__ __forceinline__ void step_push(const T* y, const T* k0, const T* p, T
 #pragma unroll
       for (int c = 0; c < D; ++c) {
         if (first_b<Tab>() == l)
-          Zb[c] = T(Tab::B[l]) * kc[c];
+          Zb[c] = cmul(Tab::B[l], kc[c]);
         else
-          Zb[c] = fmaT(T(Tab::B[l]), kc[c], Zb[c]);
+          Zb[c] = cfma(Tab::B[l], kc[c], Zb[c]);
       }
     }
     if constexpr (WANT_E) {
@@ -216,7 +216,7 @@ __device__ __forceinline__ void step_push(const T* y, const T* k0, const T* p, T
   for (int c = 0; c < D; ++c) {
     ylast[c] = Yl[c];
     klast[c] = kc[c];
-    if (WANT_B) yn[c] = fmaT(h, Zb[c], y[c]);
+    if (WANT_B) yn[c] = hfma(h, Zb[c], y[c]);
   }
 }
 

@@ -198,7 +198,7 @@ __device__ __forceinline__ void ros_stages(const T* y, const T* p, T h, const Ma
 #pragma unroll
       for (int j = 0; j < i; ++j) {
         if (Tab::A[i][j] != 0.0) {
-          acc = first ? T(Tab::A[i][j]) * u[j][c] : fmaT(T(Tab::A[i][j]), u[j][c], acc);
+          acc = first ? cmul(Tab::A[i][j], u[j][c]) : cfma(Tab::A[i][j], u[j][c], acc);
           first = false;
         }
       }
@@ -213,11 +213,11 @@ __device__ __forceinline__ void ros_stages(const T* y, const T* p, T h, const Ma
 #pragma unroll
       for (int j = 0; j < i; ++j) {
         if (Tab::C[i][j] != 0.0) {
-          acc = first ? T(Tab::C[i][j]) * u[j][c] : fmaT(T(Tab::C[i][j]), u[j][c], acc);
+          acc = first ? cmul(Tab::C[i][j], u[j][c]) : cfma(Tab::C[i][j], u[j][c], acc);
           first = false;
         }
       }
-      u[i][c] = first ? F[c] : fmaT(acc, hinv, F[c]);
+      u[i][c] = first ? F[c] : fmah(acc, hinv, F[c]);
     }
     lu_solve<D, T, Mat>(W, piv, u[i]);
   }

@@ -49,6 +49,10 @@ SYSTEMS = {
     "ude": (2, 2382, 7082),
 }
 
+# forward mode: flops of the right-hand side in dual numbers (a sum 2, a
+# product 4, an fma 6: value plus tangent by the product rule)
+RHS_DUAL = {"lorenz": 24, "vdp": 16, "linear": 20, "robertson": 26}
+
 # (jacobian flops, flops of d/d(y, p) of u^T J v) for the stiff path
 JACOBIANS = {
     "robertson": (5, 24),
@@ -135,3 +139,43 @@ def record_flops(method, system, trials, accepted, side_steps):
 def adjoint_flops(method, system, accepted, side_steps, zero_sides):
     u = per_unit(method, system)
     return u["adj_step"] * accepted + u["adj_side"] * side_steps + u["adj_zero"] * zero_sides
+
+
+# Jacobian entries in dual numbers (Rodas4 forward mode)
+JAC_DUAL = {"robertson": 18, "linear": 0}
+
+
+def _ros_jvp_per_step(method, system):
+    """A Rodas4 step in dual numbers: the Jacobian, the LU and every solve
+    with variable operands (a division or an fma 6, a product 4, a sum 2),
+    the stage combinations with constant coefficients twice."""
+    t = ROS_TABLEAUX[method]
+    D = SYSTEMS[system][0]
+    S = t["S"]
+    lu = sum(6 * m + 6 * m * m for m in range(1, D))
+    factor = JAC_DUAL[system] + 2 + 2 * D + lu
+    solve = 6 * D * D
+    stage_in = sum(2 * z for z in t["a_nnz"]) * D
+    stage_rhs = sum(2 * w + 1 for w in t["c_nnz"] if w) * D
+    return factor + 1 + S * solve + 2 * stage_in + S * RHS_DUAL[system] + 2 * stage_rhs + 2 * D
+
+
+def jvp_per_step(method, system):
+    """One replay step of the forward mode (explicit pairs): the stages'
+    right-hand sides in dual numbers, and the stage and update combinations
+    twice (the tangent of a combination with constant coefficients is the
+    same combination of tangents)."""
+    if method in ROS_TABLEAUX:
+        return _ros_jvp_per_step(method, system)
+    t = TABLEAUX[method]
+    D = SYSTEMS[system][0]
+    SU, rows = t["SU"], t["rows"]
+    combos = (sum(_combo(len(rows[i])) for i in range(1, SU)) + _combo(len(t["b"]))) * D
+    return SU * RHS_DUAL[system] + 2 * combos
+
+
+def jvp_flops(method, system, accepted, side_steps, n_saves):
+    """A forward-mode pass: every mesh step and every nonzero save step, plus
+    the loss tangent (one fma per save component)."""
+    D = SYSTEMS[system][0]
+    return jvp_per_step(method, system) * (accepted + side_steps) + 2 * D * n_saves
