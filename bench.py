@@ -99,6 +99,9 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
         if not copies:
             raise SystemExit(f"no calibration copy in {d} (run with --copy-calibration)")
         factor = (mib << 10) / max(copies)
+        if not 0.25 <= factor <= 4.0:
+            raise SystemExit(f"the largest copy in {d} counts {max(copies):.0f} KiB, not near "
+                             f"{mib << 10} KiB: no calibration copy of {mib} MiB in this run")
         out = {}
         for part, key in (("record", "_forward_kernel<"), ("adjoint", "_adjoint_kernel<"),
                           ("jvp", "jvp_kernel<")):
@@ -253,13 +256,7 @@ def main():
         return rec, gp, gy, ll
 
     if args.copy_calibration:
-        src = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device=dev)
-        src.fill_(1)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(args.copy_calibration, dev)
     for _ in range(args.warmup):
         rec, gp, gy, ll = step()
     torch.cuda.synchronize()
@@ -346,6 +343,19 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def calibration_copy(mib, dev):
+    """A device copy of known size in the profiled run: the reference for
+    scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def forward_bench(args):
     """Record + one forward-mode pass per parameter (the same unit tangent in
     every trajectory), each pass returning every trajectory's derivative of
@@ -391,6 +401,8 @@ def forward_bench(args):
         t[k] = 1.0
         tangents.append(t)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        calibration_copy(args.copy_calibration, dev)
 
     def step(events=None):
         if events:
