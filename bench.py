@@ -29,6 +29,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lorenz_2p20_t10")
+    ap.add_argument("--registered", action="store_true",
+                    help="run the workload's system as a copy registered at run time from source "
+                         "(ensemble_system_register; Lorenz and Robertson)")
     ap.add_argument("--mode", choices=("reverse", "forward"), default="reverse",
                     help="gradient by the reverse sweep (default) or by forward-mode passes, "
                          "one per parameter, on the recorded mesh")
@@ -213,7 +216,8 @@ def main():
     ckpt = cfg.get("ckpt_every", 0)
     y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=tdt, device=dev)
     p_d = torch.tensor(np.ascontiguousarray(p if shared else p.T), dtype=tdt, device=dev)
-    args_common = (cfg["system"], cfg["method"], y0_d, p_d, cfg["t0"], cfg["t1"], cfg["rtol"],
+    gsys = registered_system(cfg["system"]) if args.registered else cfg["system"]
+    args_common = (gsys, cfg["method"], y0_d, p_d, cfg["t0"], cfg["t1"], cfg["rtol"],
                    cfg["atol"])
 
     # loss: sum of squares, or MSE to targets from the teacher network (UDE)
@@ -228,7 +232,7 @@ def main():
 
     # pool plan from a pilot record of a sample of the ensemble
     m = min(n, 8192)
-    pilot = B.ensemble_record(cfg["system"], cfg["method"], y0_d[:, :m].contiguous(),
+    pilot = B.ensemble_record(gsys, cfg["method"], y0_d[:, :m].contiguous(),
                               p_d if shared else p_d[:, :m].contiguous(), cfg["t0"], cfg["t1"],
                               cfg["rtol"], cfg["atol"], save_times=save, steps_hint=4096,
                               params_shared=shared)
@@ -236,7 +240,7 @@ def main():
     cap_cpu = int(s_pilot.max().item() * 1.5) + 64
     hint = B.steps_hint_for(float(s_pilot.mean().item()), margin=1.12)
     del pilot
-    nbytes = B.ensemble_record_bytes(cfg["system"], cfg["method"], n, cfg["t0"], cfg["t1"], hint,
+    nbytes = B.ensemble_record_bytes(gsys, cfg["method"], n, cfg["t0"], cfg["t1"], hint,
                                      cfg["n_save"], tdt, ckpt)
     pool = torch.empty(nbytes, dtype=torch.uint8, device=dev)
 
@@ -317,6 +321,7 @@ def main():
         "dtype": "f32" if f32 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "system": cfg["system"], "method": cfg["method"],
+                   "registered_at_run_time": bool(args.registered),
                    "n": n, "t_span": [cfg["t0"], cfg["t1"]], "rtol": cfg["rtol"],
                    "atol": cfg["atol"], "n_save": cfg["n_save"], "ckpt_every": ckpt,
                    "loss": ("MSE to teacher-network trajectories" if loss_kind == "mse"
@@ -341,6 +346,22 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, args.cpu_seconds, cap_cpu, tgt_host,
                                            scale)
     print(json.dumps(out), flush=True)
+
+
+def registered_system(system):
+    """Register the example source of a built-in system (same operations) and
+    return the name it runs under."""
+    from paper_2609_02876_amd import _abi as A
+    from paper_2609_02876_amd import binding as B
+    from paper_2609_02876_amd import user_systems as U
+    src = {"lorenz": (U.LORENZ, False), "robertson": (U.ROBERTSON, True)}
+    if system not in src:
+        raise SystemExit("--registered runs Lorenz or Robertson workloads")
+    name = system + "_registered"
+    if name not in A.SYSTEMS:
+        d, npar = A.SYSTEMS[system][1:]
+        B.register_system(name, src[system][0], d, npar, jacobian=src[system][1])
+    return name
 
 
 def calibration_copy(mib, dev):

@@ -89,6 +89,13 @@ extern "C" {
  * LINEAR in F64 or F32, Tsit5 also on LV_UDE in F32; the Rosenbrock method on
  * ROBERTSON, HIRES and LINEAR in F64.  Other combinations return
  * ENS_EUNSUPPORTED. */
+/* Systems registered at run time (ensemble_system_register) get the ids
+ * ENS_SYS_USER_BASE, ENS_SYS_USER_BASE + 1, ... */
+#define ENS_SYS_USER_BASE 1000
+#define ENS_USER_MAX_SYSTEMS 64
+#define ENS_USER_MAX_DIM 16     /* 8 with a Jacobian (Rodas4) */
+#define ENS_USER_MAX_PARAMS 64
+
 #define ENS_TSIT5 1  /* Tsitouras 5(4), 7 stages, first-same-as-last */
 #define ENS_VERN7 2  /* Verner 7(6), 10 stages */
 #define ENS_RODAS4 3 /* Rosenbrock-Wanner Rodas4 (Hairer-Wanner IV.7), order
@@ -266,6 +273,35 @@ int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
 int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* rec,
                  const void* dy0, const void* dparams, const ens_loss* loss,
                  void* y_save_dot, double* loss_dot, void* stream);
+
+/* Register a system given as source text (the paper's user-supplied
+ * right-hand side and its vector-Jacobian product, Section 3.4), compiled at
+ * run time with hipRTC against the library's own kernels, so that it runs
+ * the same record, reverse sweep and forward mode as a built-in system.  The
+ * source defines a struct named System with static member templates on the
+ * element type T, writing results through pointers:
+ *   rhs(const T* y, const T* p, T* f)                 f = f(y, p)
+ *   vjp(const T* y, const T* p, const T* w, T* gy, T* gp)
+ *                    gy = (df/dy)^T w (overwrite), gp += (df/dp)^T w
+ * and, with has_jacobian != 0 (needed for Rodas4, dim <= 8),
+ *   jac(const T* y, const T* p, T* J)                 J = df/dy, row-major
+ *   jac_vjp(const T* y, const T* p, const T* u, const T* v, T* gy, T* gp)
+ *                    gy, gp += d/d(y, p) of u^T J(y, p) v
+ * each declared `template <class T> __device__ static void ...`.  The code
+ * may use + - * / and fmaT(a, b, c) (a fused multiply-add; the library's
+ * build never fuses a product and a sum by itself, so the written operations
+ * fix the rounding), constants, and T(c).  It must be straight-line: no
+ * branches, loops, '?', '&&', '||', preprocessor directives, inline
+ * assembly, shared memory, synchronisation or atomics -- data-dependent
+ * control flow is refused (ENS_EINVAL, as is a source that does not
+ * compile; ensemble_last_error gives the reason and the compiler's log).
+ * dim in [1, ENS_USER_MAX_DIM], nparams in [1, ENS_USER_MAX_PARAMS].  On
+ * success *system receives the id to use in ens_problem.system.  The Tsit5
+ * kernels in F64 (and Rodas4 with a Jacobian) are compiled here; the others
+ * on first use.  Registered systems are not served by ensemble_server_*.
+ * Thread-safe; a registration lasts until the process ends. */
+int ensemble_system_register(const char* source, int dim, int nparams, int has_jacobian,
+                             int* system);
 
 /* Workspace ensemble_adjoint needs for this record: per-block partial sums
  * for shared parameters, plus one segment of step records per trajectory for

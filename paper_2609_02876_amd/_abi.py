@@ -88,7 +88,8 @@ JOB_WAITING, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, -1
 
 EXPORTS = ("ensemble_solve", "ensemble_record_bytes", "ensemble_record",
            "ensemble_replay_mesh", "ensemble_mesh_export", "ensemble_adjoint",
-           "ensemble_adjoint_workspace_bytes", "ensemble_jvp", "ensemble_record_stats",
+           "ensemble_adjoint_workspace_bytes", "ensemble_jvp", "ensemble_system_register",
+           "ensemble_record_stats",
            "ensemble_server_create", "ensemble_server_submit", "ensemble_server_progress",
            "ensemble_server_poll", "ensemble_server_wait", "ensemble_server_drain",
            "ensemble_server_stats", "ensemble_server_destroy",
@@ -120,6 +121,8 @@ def load(build_if_missing=True):
     lib.ensemble_adjoint_workspace_bytes.argtypes = [C.POINTER(Record), C.POINTER(C.c_size_t)]
     lib.ensemble_jvp.argtypes = [P, V, C.POINTER(Record), Ptr, Ptr, C.POINTER(Loss), Ptr, Ptr,
                                  Ptr]
+    lib.ensemble_system_register.argtypes = [C.c_char_p, C.c_int32, C.c_int32, C.c_int32,
+                                             C.POINTER(C.c_int32)]
     lib.ensemble_record_stats.argtypes = [C.POINTER(Record), C.POINTER(Stats), Ptr]
     S = C.c_void_p
     lib.ensemble_server_create.argtypes = [Ptr, C.c_size_t, C.c_int32, C.POINTER(S)]

@@ -280,6 +280,20 @@ def ensemble_jvp(handle, dy0=None, dparams=None, loss="sumsq", data=None, scale=
     return ysd, ld
 
 
+def register_system(name, source, dim, nparams, jacobian=False):
+    """Register a system given as source (see ensemble_system_register in
+    ensode.h: a struct System with rhs, vjp and, with jacobian=True, jac and
+    jac_vjp); afterwards `name` works wherever a system name does.  Returns
+    the system id."""
+    if name in A.SYSTEMS:
+        raise ValueError(f"system {name!r} exists")
+    sid = C.c_int32()
+    A.check(A.load().ensemble_system_register(source.encode(), int(dim), int(nparams),
+                                              int(bool(jacobian)), C.byref(sid)))
+    A.SYSTEMS[name] = (sid.value, int(dim), int(nparams))
+    return sid.value
+
+
 def ensemble_record_stats(handle):
     st = A.Stats()
     A.check(A.load().ensemble_record_stats(C.byref(handle.rec), C.byref(st), _stream()))

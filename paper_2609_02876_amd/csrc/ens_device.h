@@ -1,8 +1,21 @@
 // Device-side building blocks shared by the ensemble kernels: scalar fma
 // wrappers, wavefront primitives and the device view of a record.
 #pragma once
+#ifndef __HIPCC_RTC__  // run-time compilation brings its own runtime and types
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#endif
+#ifndef INFINITY
+#define INFINITY __builtin_inff()
+#endif
+#ifndef NAN
+#define NAN __builtin_nanf("")
+#endif
 
 namespace ens {
 

@@ -2,12 +2,19 @@
 // pool layout, kernel dispatch over (system, method, dtype).
 #include <hip/hip_runtime.h>
 
+#include <hip/hiprtc.h>
+
+#include <cctype>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "ensode.h"
 #include "erk.h"
@@ -21,7 +28,7 @@ namespace {
 thread_local std::string g_err = "no error";
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
+  char buf[2048];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
@@ -38,6 +45,10 @@ struct SysInfo {
   int d, np;
 };
 
+// systems registered at run time (rtc.h)
+bool is_rtc(int sys);
+bool rtc_info(int sys, int* d, int* np, bool* jac);
+
 bool sys_info(int sys, SysInfo* s) {
   switch (sys) {
     case ENS_SYS_LORENZ: *s = {3, 3}; return true;
@@ -47,7 +58,8 @@ bool sys_info(int sys, SysInfo* s) {
     case ENS_SYS_LV_UDE: *s = {2, UDE_NP}; return true;
     case ENS_SYS_LINEAR: *s = {2, 2}; return true;
   }
-  return false;
+  bool jac;
+  return rtc_info(sys, &s->d, &s->np, &jac);
 }
 
 size_t elem_size(int dtype) { return dtype == ENS_F32 ? 4 : 8; }
@@ -74,6 +86,20 @@ int check_problem(const ens_problem* p, SysInfo* si) {
       return fail(ENS_EUNSUPPORTED, "the UDE is built for Tsit5 in F32 only");
     if (p->params_shared != 1)
       return fail(ENS_EINVAL, "the UDE's network weights are shared: params_shared must be 1");
+    return ENS_OK;
+  }
+  if (p->system >= ENS_SYS_USER_BASE) {
+    int d, np;
+    bool jac;
+    rtc_info(p->system, &d, &np, &jac);
+    if (p->method == ENS_RODAS4 && !jac)
+      return fail(ENS_EUNSUPPORTED,
+                  "system %d was registered without jac and jac_vjp, which Rodas4 needs",
+                  p->system);
+    if (p->method == ENS_RODAS4 && p->dtype != ENS_F64)
+      return fail(ENS_EUNSUPPORTED, "Rodas4 is built for F64 only");
+    if (p->params_shared != 0 && p->params_shared != 1)
+      return fail(ENS_EINVAL, "params_shared must be 0 or 1");
     return ENS_OK;
   }
   const bool stiff_sys = p->system == ENS_SYS_ROBERTSON || p->system == ENS_SYS_HIRES;
@@ -323,6 +349,8 @@ constexpr int BLOCK = 256;
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
+#include "rtc.h"
+
 // Shared-parameter partials of the reverse sweep: one per block, or one per
 // wavefront for the UDE (whose gradient is reduced per wavefront).
 size_t partials_bytes(int sys, int64_t n, int np, int dtype) {
@@ -349,6 +377,9 @@ int launch_forward_ude(int mode, bool ckpt, const FwdArgs& fa, hipStream_t st) {
 int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
                    hipStream_t st) {
   if (p->system == ENS_SYS_LV_UDE) return launch_forward_ude(mode, ckpt, fa, st);
+  if (is_rtc(p->system))
+    return rtc_launch(p->system, p->method, p->dtype, fwd_expr(p->method, p->dtype, mode, ckpt),
+                      grid_of(fa.ivp.n), fa, st);
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);
@@ -613,6 +644,22 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
   }
+  if (is_rtc(p->system)) {
+    rc = rtc_launch(p->system, p->method, p->dtype, adj_expr(p->method, p->dtype, shared, ckpt),
+                    grid_of(v->n), aa, st);
+    if (rc != ENS_OK || !shared) return rc;
+    const dim3 b(BLOCK);
+    if (p->dtype == ENS_F64)
+      hipLaunchKernelGGL((reduce_partials_kernel<double>), dim3(si.np), b, 0, st,
+                         (const double*)workspace, (int64_t)grid_of(v->n), si.np,
+                         (double*)grad_params);
+    else
+      hipLaunchKernelGGL((reduce_partials_kernel<float>), dim3(si.np), b, 0, st,
+                         (const float*)workspace, (int64_t)grid_of(v->n), si.np,
+                         (float*)grad_params);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
+  }
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);
@@ -673,6 +720,9 @@ int ensemble_jvp(const ens_problem* p, const ens_ivp* v, const ens_record* r,
   ja.rec_b = ck ? (int64_t)8 : (int64_t)r->rec_bytes;
   ja.h_off = ck ? (int64_t)state_bytes(r->dtype, r->dim) : (int64_t)0;
   hipStream_t st = (hipStream_t)stream;
+  if (is_rtc(p->system))
+    return rtc_launch(p->system, p->method, p->dtype, jvp_expr(p->method, p->dtype),
+                      grid_of(v->n), ja, st);
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);
@@ -685,6 +735,48 @@ int ensemble_jvp(const ens_problem* p, const ens_ivp* v, const ens_record* r,
       return e == hipSuccess ? ENS_OK : hip_fail(e, "jvp launch");
     }
   });
+}
+
+extern "C" int ensemble_system_register(const char* source, int dim, int nparams,
+                                        int has_jacobian, int* system) {
+  if (!source || !system) return fail(ENS_EINVAL, "source and system must not be NULL");
+  if (dim < 1 || dim > ENS_USER_MAX_DIM)
+    return fail(ENS_EINVAL, "dim must be in [1, %d]", ENS_USER_MAX_DIM);
+  if (nparams < 1 || nparams > ENS_USER_MAX_PARAMS)
+    return fail(ENS_EINVAL, "nparams must be in [1, %d]", ENS_USER_MAX_PARAMS);
+  if (has_jacobian && dim > 8)
+    return fail(ENS_EINVAL, "a system with a Jacobian (for Rodas4) has dim <= 8");
+  const std::string src(source);
+  const std::string bad = refused_construct(src);
+  if (!bad.empty())
+    return fail(ENS_EINVAL,
+                "a registered system must be straight-line arithmetic (no data-dependent "
+                "control flow): found %s",
+                bad.c_str());
+  auto r = std::make_unique<RtcSystem>();
+  r->d = dim;
+  r->np = nparams;
+  r->jac = has_jacobian != 0;
+  std::lock_guard<std::mutex> lk(g_rtc_mu);
+  if ((int)g_rtc.size() >= ENS_USER_MAX_SYSTEMS)
+    return fail(ENS_EINVAL, "at most %d systems can be registered", ENS_USER_MAX_SYSTEMS);
+  const int id = ENS_SYS_USER_BASE + (int)g_rtc.size();
+  r->source = "#include \"jvp.h\"\nnamespace ens_user {\nusing ens::fmaT;\n" + src +
+              "\n}  // namespace ens_user\nnamespace ens {\nstruct RtcSys : ::ens_user::System {\n"
+              "  static constexpr int D = " + std::to_string(dim) +
+              ", NP = " + std::to_string(nparams) + ", ID = " + std::to_string(id) +
+              ";\n};\n}  // namespace ens\n";
+  // compile one variant now, so that a source that does not compile is
+  // refused here rather than at its first launch
+  const int rc = rtc_compile(*r, ENS_TSIT5, ENS_F64);
+  if (rc != ENS_OK) return rc;
+  if (r->jac) {
+    const int rc2 = rtc_compile(*r, ENS_RODAS4, ENS_F64);
+    if (rc2 != ENS_OK) return rc2;
+  }
+  g_rtc.push_back(std::move(r));
+  *system = id;
+  return ENS_OK;
 }
 
 int ensemble_record_stats(const ens_record* r, ens_stats* out, void* stream) {

@@ -12,7 +12,9 @@
 // of the last accepted step to a save time.  The reverse sweep is the same:
 // one VJP of Phi per iteration, for a mesh step or a save-time side step.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <math.h>
+#endif
 
 #include "ens_device.h"
 #include "ros.h"

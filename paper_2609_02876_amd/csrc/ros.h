@@ -9,7 +9,9 @@
 // kept so that a right-hand side is permuted by the same interchanges in
 // the same order (and in reverse order for the transposed solve).
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <math.h>
+#endif
 
 #include "ens_device.h"
 

@@ -367,6 +367,8 @@ int ensemble_server_submit(ens_server* s, const ens_job* job, int64_t* id) {
   if ((rc = check_problem(&job->prob, &si)) != ENS_OK) return rc;
   if (job->prob.system == ENS_SYS_LV_UDE || job->prob.params_shared)
     return fail(ENS_EUNSUPPORTED, "served jobs have per-trajectory parameters (not the UDE)");
+  if (job->prob.system >= ENS_SYS_USER_BASE)
+    return fail(ENS_EUNSUPPORTED, "registered systems are not served");
   if ((rc = check_ivp(&job->ivp, true)) != ENS_OK) return rc;
   const ens_loss& L = job->loss;
   if (L.kind != ENS_LOSS_SUMSQ && L.kind != ENS_LOSS_MSE_TARGET && L.kind != ENS_LOSS_COTANGENT)

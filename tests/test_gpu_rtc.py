@@ -1,0 +1,161 @@
+"""Systems registered at run time (compiled with hipRTC), through the C ABI.
+
+A registered copy of a built-in system, written with the same operations,
+runs the same kernels compiled from the same headers with the same flags, so
+its record, reverse sweep and forward mode equal the built-in system's to the
+bit; the built-in systems are pinned to the oracle (test_gpu_parity,
+test_gpu_rosenbrock, test_gpu_jvp), which pins the registered path in turn.
+A system with no built-in counterpart has no oracle: its gradients are
+checked against central differences of the replay on the frozen mesh and
+against the forward mode.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_02876_amd import _abi as A
+from paper_2609_02876_amd import binding as B
+from paper_2609_02876_amd import serving as SV
+from paper_2609_02876_amd import user_systems as U
+from paper_2609_02876_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _name(base):
+    if base not in A.SYSTEMS:
+        src = {"rtc_lorenz": U.LORENZ, "rtc_robertson": U.ROBERTSON}[base]
+        B.register_system(base, src, 3, 3, jacobian=(base == "rtc_robertson"))
+    return base
+
+
+def _run(system, method, y0, p, t1, rtol, atol, st, dtype, **kw):
+    h = B.ensemble_record(system, method, _dev(y0.T, dtype), _dev(p.T, dtype), 0.0, t1, rtol,
+                          atol, save_times=st, steps_hint=512, **kw)
+    gp, gy, ll = B.ensemble_adjoint(h)
+    rng = np.random.default_rng(4)
+    dp = _dev((rng.standard_normal(p.shape) * p).T, dtype)
+    ysd, ld = B.ensemble_jvp(h, None, dp)
+    torch.cuda.synchronize()
+    return [h.y_save, h.status, h.steps(), gp, gy, ll, ysd, ld]
+
+
+@pytest.mark.parametrize("method,dtype", [("tsit5", torch.float64), ("vern7", torch.float64),
+                                          ("tsit5", torch.float32)])
+def test_registered_lorenz_equals_builtin(method, dtype):
+    print(f"case registered lorenz {method} {dtype}", flush=True)
+    n = 1000
+    y0, p = W.lorenz(n, seed=2)
+    st = list(W.save_times(0.0, 10.0, 20))
+    a = _run("lorenz", method, y0, p, 10.0, 1e-6, 1e-8, st, dtype)
+    b = _run(_name("rtc_lorenz"), method, y0, p, 10.0, 1e-6, 1e-8, st, dtype)
+    assert np.all(a[1].cpu().numpy() == 0)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_registered_robertson_rodas4_equals_builtin():
+    print("case registered robertson rodas4", flush=True)
+    n = 513
+    y0, p = W.robertson(n, seed=3)
+    st = list(W.save_times(0.0, 1e5, 20))
+    a = _run("robertson", "rodas4", y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
+    b = _run(_name("rtc_robertson"), "rodas4", y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
+    assert np.all(a[1].cpu().numpy() == 0)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_registered_checkpointed_and_shared():
+    n = 700
+    y0, p = W.lorenz(n, seed=5)
+    st = list(W.save_times(0.0, 10.0, 20))
+    for kw in (dict(ckpt_every=16),):
+        a = _run("lorenz", "tsit5", y0, p, 10.0, 1e-6, 1e-8, st, torch.float64, **kw)
+        b = _run(_name("rtc_lorenz"), "tsit5", y0, p, 10.0, 1e-6, 1e-8, st, torch.float64, **kw)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    # shared parameters: one (sigma, rho, beta) for all trajectories
+    outs = []
+    for system in ("lorenz", _name("rtc_lorenz")):
+        h = B.ensemble_record(system, "tsit5", _dev(y0.T), _dev(p[0]), 0.0, 10.0, 1e-6, 1e-8,
+                              save_times=st, params_shared=True, steps_hint=512)
+        outs.append(B.ensemble_adjoint(h))
+    torch.cuda.synchronize()
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)
+
+
+BRUSSELATOR = """
+struct System {
+  // Brusselator, p = (a, b): x' = a - (b + 1) x + x^2 y,  y' = b x - x^2 y
+  template <class T>
+  __device__ static void rhs(const T* y, const T* p, T* f) {
+    const T xxy = (y[0] * y[0]) * y[1];
+    f[0] = fmaT(-(p[1] + T(1)), y[0], p[0] + xxy);
+    f[1] = fmaT(p[1], y[0], -xxy);
+  }
+  template <class T>
+  __device__ static void vjp(const T* y, const T* p, const T* w, T* gy, T* gp) {
+    const T d = w[0] - w[1];
+    const T xy2 = T(2) * (y[0] * y[1]);
+    gy[0] = fmaT(xy2, d, fmaT(p[1], w[1], -((p[1] + T(1)) * w[0])));
+    gy[1] = (y[0] * y[0]) * d;
+    gp[0] = gp[0] + w[0];
+    gp[1] = fmaT(y[0], w[1] - w[0], gp[1]);
+  }
+};
+"""
+
+
+def test_new_system_gradients_against_differences_and_forward_mode():
+    """A system with no built-in copy: the reverse gradient against central
+    differences of the replay on the frozen mesh (relative step 1e-6) and
+    against one forward pass per parameter."""
+    if "rtc_brusselator" not in A.SYSTEMS:
+        B.register_system("rtc_brusselator", BRUSSELATOR, 2, 2)
+    n = 256
+    rng = np.random.default_rng(6)
+    y0 = np.column_stack([1.0 + 0.5 * rng.random(n), 2.0 + 0.5 * rng.random(n)])
+    p = np.column_stack([1.0 + 0.2 * rng.random(n), 2.5 + 0.5 * rng.random(n)])
+    st = list(W.save_times(0.0, 8.0, 20))
+    h = B.ensemble_record("rtc_brusselator", "tsit5", _dev(y0.T), _dev(p.T), 0.0, 8.0, 1e-8,
+                          1e-10, save_times=st, steps_hint=1024)
+    gp, gy, ll = B.ensemble_adjoint(h)
+    cap = int(h.steps().max().item())
+    hm, sm = B.ensemble_mesh_export(h, cap)
+    torch.cuda.synchronize()
+    assert np.all(h.status.cpu().numpy() == 0)
+    g = gp.cpu().numpy()
+    for k in range(2):
+        eps = 1e-6 * p[:, k]
+        losses = []
+        for sgn in (1.0, -1.0):
+            q = p.copy()
+            q[:, k] += sgn * eps
+            r = B.ensemble_replay_mesh("rtc_brusselator", "tsit5", _dev(y0.T), _dev(q.T), 0.0,
+                                       8.0, hm, sm, save_times=st)
+            _, _, lq = B.ensemble_adjoint(r)
+            torch.cuda.synchronize()
+            losses.append(lq.cpu().numpy())
+        fd = (losses[0] - losses[1]) / (2 * eps)
+        e_fd = np.max(np.abs(fd - g[k]) / np.maximum(np.abs(g[k]), 1e-3 * np.abs(g[k]).max()))
+        t = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+        t[k] = 1.0
+        _, ld = B.ensemble_jvp(h, None, t, want_states=False)
+        torch.cuda.synchronize()
+        e_fw = np.max(np.abs(ld.cpu().numpy() - g[k])) / np.abs(g[k]).max()
+        print(f"  param {k}: reverse vs differences {e_fd:.2e}, vs forward {e_fw:.2e}")
+        assert e_fd <= 1e-6 and e_fw <= 1e-12
+
+
+def test_registered_systems_are_not_served():
+    y0, p = W.lorenz(64, seed=0)
+    srv = SV.Server(1 << 28, n_slots=1)
+    with pytest.raises(A.EnsembleError, match="not served"):
+        srv.submit(_name("rtc_lorenz"), "tsit5", _dev(y0.T), _dev(p.T), 0.0, 1.0, 1e-6, 1e-8)
+    srv.close()
