@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 LORENZ, VDP, ROBERTSON, HIRES, LV_UDE, LINEAR = 1, 2, 3, 4, 5, 6
-TSIT5, VERN7, RODAS = 1, 2, 3
+TSIT5, VERN7, RODAS, ROS23 = 1, 2, 3, 4
 ST_OK, ST_MAX_STEPS, ST_DT_UNDERFLOW, ST_NONFINITE, ST_NOSPACE = 0, 1, 2, 3, 4
 LOSS_SUMSQ, LOSS_MSE_TARGET, LOSS_COTANGENT = 0, 1, 2
 
@@ -50,8 +50,10 @@ def _load():
         lib.oracle_rhs.argtypes = [I, _d, _d, _d]
         lib.oracle_jac.argtypes = [I, _d, _d, _d]
         lib.oracle_jac_vjp.argtypes = [I, _d, _d, _d, _d, _d, _d]
-        lib.oracle_ros_tableau.argtypes = [_d, _d, _d, _d, C.POINTER(I), C.POINTER(I)]
+        lib.oracle_ros_tableau.argtypes = [I, _d, _d, _d, _d, _d, C.POINTER(I), C.POINTER(I),
+                                           C.POINTER(I)]
         lib.oracle_vjp.argtypes = [I, _d, _d, _d, _d, _d]
+        lib.oracle_ros_trial.argtypes = [I, I, _d, _d, D, _d, _d]
         lib.oracle_record.argtypes = [I, I, I, I, _d, _d, D, D, D, D, D, L, I, _d, L,
                                       _d, _i32, _i32, _i32, _d, _d, _i64]
         lib.oracle_replay.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d, _d]
@@ -125,12 +127,27 @@ def jac_vjp(system, y, p, u, v):
     return gy, gp
 
 
-def ros_tableau():
-    g = C.c_double(); a = np.zeros(36); c = np.zeros(36); m = np.zeros(6)
-    o, q = C.c_int(), C.c_int()
-    s = _load().oracle_ros_tableau(C.byref(g), _p(a), _p(c), _p(m), C.byref(o), C.byref(q))
-    return dict(s=s, gamma=g.value, a=a.reshape(6, 6)[:s, :s].copy(),
-                c=c.reshape(6, 6)[:s, :s].copy(), m=m[:s].copy(), order=o.value, q_emb=q.value)
+def ros_tableau(method=RODAS):
+    """A Rosenbrock method in transformed form (a, c, m, error weights e;
+    the first su stages enter y_new)."""
+    g = C.c_double(); a = np.zeros(36); c = np.zeros(36); m = np.zeros(6); e = np.zeros(6)
+    o, q, su = C.c_int(), C.c_int(), C.c_int()
+    s = _load().oracle_ros_tableau(method, C.byref(g), _p(a), _p(c), _p(m), _p(e), C.byref(o),
+                                   C.byref(q), C.byref(su))
+    if s < 0:
+        raise ValueError(f"not a Rosenbrock method: {method}")
+    return dict(s=s, su=su.value, gamma=g.value, a=a[:s * s].reshape(s, s).copy(),
+                c=c[:s * s].reshape(s, s).copy(), m=m[:s].copy(), e=e[:s].copy(),
+                order=o.value, q_emb=q.value)
+
+
+def ros_trial(method, system, y, p, h):
+    """One Rosenbrock trial step: (y_new, error estimate vector)."""
+    y, p = _f64(y), _f64(p)
+    yn = np.zeros_like(y); e = np.zeros_like(y)
+    if _load().oracle_ros_trial(method, system, _p(y), _p(p), float(h), _p(yn), _p(e)) != 0:
+        raise ValueError("oracle_ros_trial rejected its arguments")
+    return yn, e
 
 
 def vjp(system, y, p, w):

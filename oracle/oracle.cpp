@@ -544,6 +544,7 @@ static void erk_phi(const ERK& m, int sys, int d, const T* y, const P* p, T h,
 // guess for m^(-1/k) is scaled by 2^(-j/k) 2^(-q), then four Newton steps
 // y <- y + (y / k) (1 - x y^k) on f(y) = y^(-k) - x.  Arguments below
 // 1e-300 are raised to it (the controller clamps the factor long before).
+static const double TWO_NEG_3[3] = {1.0, 0.7937005259840998, 0.6299605249474366};
 static const double TWO_NEG_4[4] = {1.0, 0.8408964152537145, 0.7071067811865476,
                                     0.5946035575013605};
 static const double TWO_NEG_5[5] = {1.0, 0.8705505632961241, 0.757858283255199,
@@ -562,8 +563,9 @@ static const double TWO_NEG_8[8] = {1.0, 0.9170040432046712, 0.8408964152537145,
 static double root_inv(double x, int k) {
   if (std::isnan(x) || x < 0.0) return NAN;
   if (std::isinf(x)) return 0.0;
-  if (k < 4 || k > 8) return NAN;
-  const double* c = k == 4   ? TWO_NEG_4
+  if (k < 3 || k > 8) return NAN;
+  const double* c = k == 3   ? TWO_NEG_3
+                    : k == 4 ? TWO_NEG_4
                     : k == 5 ? TWO_NEG_5
                     : k == 6 ? TWO_NEG_6
                     : k == 7 ? TWO_NEG_7
@@ -912,17 +914,24 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
 // the step's start, the systems are autonomous):
 //   Y_i = y + sum_{j<i} a_ij u_j,   W u_i = f(Y_i) + (1/h) sum_{j<i} c_ij u_j,
 //   y_new = Y_6 + u_6,   error estimate e = u_6.
+// Rosenbrock23 (below) is written in the same form.  Fields: s stages, of
+// which the first su enter y_new (y_new = y + sum_{j<su} m_j u_j); the error
+// estimate is sum_j e_j u_j; new_at_input: y_new is the input Y_s of the
+// last stage (formed as that stage's input), otherwise y_new = Y_s + u_s.
 struct ROS {
-  int s, order, q_emb;
+  int s, su, order, q_emb;
+  bool new_at_input;
   double gamma;
   double a[6][6];
   double c[6][6];
   double m[6];
+  double e[6];
 };
 
 static ROS make_rodas4() {
   ROS r{};
-  r.s = 6; r.order = 4; r.q_emb = 3; r.gamma = 0.25;
+  r.s = 6; r.su = 6; r.order = 4; r.q_emb = 3; r.gamma = 0.25;
+  r.new_at_input = false;
   r.a[1][0] = 1.544;
   r.a[2][0] = 0.9466785280815826;  r.a[2][1] = 0.2557011698983284;
   r.a[3][0] = 3.314825187068521;   r.a[3][1] = 2.896124015972201;
@@ -942,10 +951,51 @@ static ROS make_rodas4() {
   r.c[5][4] = -6.058818238834054;
   for (int j = 0; j < 5; ++j) r.m[j] = r.a[5][j];
   r.m[5] = 1.0;
+  r.e[5] = 1.0;
   return r;
 }
 static const ROS RODAS4 = make_rodas4();
-static bool is_ros(int method) { return method == 3; }
+
+// Rosenbrock23 (Shampine & Reichelt 1997, the method of MATLAB's ode23s) for
+// an autonomous f, with d = 1/(2 + sqrt 2) and e32 = 6 + sqrt 2:
+//   W = I - h d J,  k1 = W^{-1} f(y),  F1 = f(y + h k1 / 2),
+//   k2 = W^{-1}(F1 - k1) + k1,  y_new = y + h k2,  F2 = f(y_new),
+//   k3 = W^{-1}(F2 - e32 (k2 - F1) - 2 (k1 - f(y))),
+//   error estimate (h/6)(k1 - 2 k2 + k3).
+// With W k1 = f(y) and W k2 = F1 - h d J k1 the differences of f-values are
+// J-terms, k1 - f(y) = h d J k1 and k2 - F1 = h d J (k2 - k1), so in the
+// increments K_i = h k_i it is the Rosenbrock method
+//   (I - d h J) K_i = h f(y + sum alpha_ij K_j) + h J sum gamma_ij K_j
+// with alpha_21 = 1/2, alpha_32 = 1, gamma_21 = -d,
+// gamma_31 = (e32 - 2) d, gamma_32 = -e32 d, b = (0, 1, 0) and error weights
+// (1, -2, 1)/6.  The transformed form (u = Gamma K, Gamma = (gamma_ij) with
+// d on the diagonal) has Gamma^{-1} = (1/d) [[1,0,0],[1,1,0],[2,e32,1]], so
+//   a = alpha Gamma^{-1}:   a_21 = 1/(2d), a_31 = a_32 = 1/d,
+//   c = diag(1/d) - Gamma^{-1}:  c_21 = -1/d, c_31 = -2/d, c_32 = -e32/d,
+//   m = b Gamma^{-1} = (1/d, 1/d, 0)  (y_new = Y_3, the third stage input),
+//   error weights (1, e32 - 2, 1)/(6d).
+// Order 2; the error estimate is O(h^3), so the controller's root is the
+// third (q_emb = 2).  Values: the doubles nearest the exact numbers.
+static ROS make_ros23() {
+  ROS r{};
+  r.s = 3; r.su = 2; r.order = 2; r.q_emb = 2;
+  r.new_at_input = true;
+  r.gamma = 0.2928932188134525;
+  r.a[1][0] = 1.7071067811865475;
+  r.a[2][0] = 3.414213562373095;   r.a[2][1] = 3.414213562373095;
+  r.c[1][0] = -3.414213562373095;
+  r.c[2][0] = -6.82842712474619;   r.c[2][1] = -25.31370849898476;
+  r.m[0] = 3.414213562373095;      r.m[1] = 3.414213562373095;
+  r.e[0] = 0.5690355937288492;     r.e[1] = 3.080880229039762;
+  r.e[2] = 0.5690355937288492;
+  return r;
+}
+static const ROS ROS23 = make_ros23();
+
+static const ROS* ros_of(int method) {
+  return method == 3 ? &RODAS4 : method == 4 ? &ROS23 : nullptr;
+}
+static bool is_ros(int method) { return ros_of(method) != nullptr; }
 
 inline double absval(double x) { return std::fabs(x); }
 inline double absval(Dual x) { return std::fabs(x.v); }
@@ -1006,12 +1056,12 @@ static void lu_solve_t(int d, const double* LU, const int* perm, const double* b
   for (int i = 0; i < d; ++i) z[perm[i]] = v[i];
 }
 
-// One Rodas4 step from y with step h; stage inputs Y, increments u and the
-// factors are returned for the reverse sweep.  y_new = Y_6 + u_6.
+// One Rosenbrock step of method m from y with step h; stage inputs Y,
+// increments u and the factors are returned for the reverse sweep.
+// y_new = Y_s + u_s (Rodas4) or Y_s (Rosenbrock23).
 template <class T, class P>
-static void ros_step(int sys, int d, const T* y, const P* p, T h, T* ynew,
+static void ros_step(const ROS& m, int sys, int d, const T* y, const P* p, T h, T* ynew,
                      T Y[6][DMAX], T u[6][DMAX], T* LU, int* perm) {
-  const ROS& m = RODAS4;
   jac(sys, y, p, LU);
   const T dg = T(1.0) / (T(m.gamma) * h);
   for (int i = 0; i < d * d; ++i) LU[i] = -LU[i];
@@ -1043,22 +1093,37 @@ static void ros_step(int sys, int d, const T* y, const P* p, T h, T* ynew,
     }
     lu_solve(d, LU, perm, r, u[i]);
   }
-  for (int c = 0; c < d; ++c) ynew[c] = Y[m.s - 1][c] + u[m.s - 1][c];
+  for (int c = 0; c < d; ++c)
+    ynew[c] = m.new_at_input ? Y[m.s - 1][c] : Y[m.s - 1][c] + u[m.s - 1][c];
+}
+
+// Error estimate e = sum_j e_j u_j (Rodas4: u_6 itself).
+static void ros_errvec(const ROS& m, int d, const double u[6][DMAX], double* e) {
+  for (int c = 0; c < d; ++c) {
+    double acc = 0.0;
+    bool first = true;
+    for (int j = 0; j < m.s; ++j) {
+      if (m.e[j] == 0.0) continue;
+      if (first) { acc = m.e[j] * u[j][c]; first = false; }
+      else acc = fma(m.e[j], u[j][c], acc);
+    }
+    e[c] = acc;
+  }
 }
 
 template <class T, class P>
-static void ros_phi(int sys, int d, const T* y, const P* p, T h, T* ynew) {
+static void ros_phi(const ROS& m, int sys, int d, const T* y, const P* p, T h, T* ynew) {
   if (value_of(h) == 0.0) {  // a zero-length step is the identity (skipped)
     for (int c = 0; c < d; ++c) ynew[c] = y[c];
     return;
   }
   T Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
   int perm[DMAX];
-  ros_step(sys, d, y, p, h, ynew, Y, u, LU, perm);
+  ros_step(m, sys, d, y, p, h, ynew, Y, u, LU, perm);
 }
 
 static void ros_record_lane(const RecordArgs& A, int lane) {
-  const ROS& m = RODAS4;
+  const ROS& m = *ros_of(A.method);
   const int d = A.d, sys = A.sys;
   const double* p = A.params_shared ? A.p : A.p + (int64_t)lane * A.np;
   double y[DMAX], f0[DMAX];
@@ -1097,11 +1162,12 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
     if (t + h >= A.t1) { h = A.t1 - t; last = true; }
     double ynew[DMAX], Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
     int perm[DMAX];
-    ros_step(sys, d, y, p, h, ynew, Y, u, LU, perm);
-    double sc[DMAX];
+    ros_step(m, sys, d, y, p, h, ynew, Y, u, LU, perm);
+    double sc[DMAX], e[DMAX];
     for (int c = 0; c < d; ++c)
       sc[c] = fma(A.rtol, std::fmax(std::fabs(y[c]), std::fabs(ynew[c])), A.atol);
-    const double err = rms_norm(d, u[m.s - 1], sc);
+    ros_errvec(m, d, u, e);
+    const double err = rms_norm(d, e, sc);
     const double fac0 = 0.9 * root_inv(err, kroot);
     if (err <= 1.0) {
       if (S >= A.cap) { status = ST_NOSPACE; break; }
@@ -1110,7 +1176,7 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
       while (next_save < A.n_save && A.save_t[next_save] < tnew) {
         double dt = A.save_t[next_save] - t;
         double ys[DMAX];
-        ros_phi(sys, d, y, p, dt, ys);
+        ros_phi(m, sys, d, y, p, dt, ys);
         sidx[next_save] = (int32_t)S;
         sdt[next_save] = dt;
         for (int c = 0; c < d; ++c) ysv[next_save * d + c] = ys[c];
@@ -1131,7 +1197,7 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
       sidx[next_save] = (int32_t)S;
       sdt[next_save] = A.save_t[next_save] - t;
       double ys[DMAX];
-      ros_phi(sys, d, y, p, sdt[next_save], ys);
+      ros_phi(m, sys, d, y, p, sdt[next_save], ys);
       for (int c = 0; c < d; ++c) ysv[next_save * d + c] = ys[c];
       ++next_save;
     }
@@ -1141,36 +1207,37 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
   A.n_trial[lane] = trials;
 }
 
-// Reverse sweep through one Rodas4 step with output cotangent lam:
+// Reverse sweep through one Rosenbrock step with output cotangent lam:
 //   ubar_i = m_i lam + sum_{l>i} (a_li Ybar_l + c_li t_l),  t_l = rbar_l / h
 // (the sum over l runs from the last stage down, as the sweep forms them)
 //   rbar_i = W^{-T} ubar_i,  Ybar_i = J(Y_i)^T rbar_i,  p_bar += f_p(Y_i)^T rbar_i
 //   lam_in = lam + sum_i Ybar_i + d/dy sum_i rbar_i^T J(y) u_i  (J is at y)
 // with p_bar also receiving d/dp of rbar_i^T J u_i.  Stages run i = 6..1 and
-// each stage adds its f_p term, then its J_p term, to p_bar.
-static void ros_step_vjp(int sys, int d, const double* y, const double* p, double h,
-                         const double* lam, double* lam_in, double* gp) {
-  const ROS& m = RODAS4;
+// each stage adds its f_p term, then its J_p term, to p_bar.  Only the su
+// stages that enter y_new are reversed: a later stage (Rosenbrock23's third,
+// which serves the error estimate alone) has a zero cotangent.
+static void ros_step_vjp(const ROS& m, int sys, int d, const double* y, const double* p,
+                         double h, const double* lam, double* lam_in, double* gp) {
   if (h == 0.0) {
     for (int c = 0; c < d; ++c) lam_in[c] = lam[c];
     return;
   }
   double ynew[DMAX], Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
   int perm[DMAX];
-  ros_step(sys, d, y, p, h, ynew, Y, u, LU, perm);
+  ros_step(m, sys, d, y, p, h, ynew, Y, u, LU, perm);
   const double hinv = 1.0 / h;
   double Yb[6][DMAX], rb[6][DMAX], tb[6][DMAX], gJ[DMAX];
   for (int c = 0; c < d; ++c) {
     lam_in[c] = lam[c];
     gJ[c] = 0.0;
   }
-  for (int i = m.s - 1; i >= 0; --i) {
+  for (int i = m.su - 1; i >= 0; --i) {
     double ub[DMAX];
     for (int c = 0; c < d; ++c) {
       double acc = 0.0;
       bool first = true;
       if (m.m[i] != 0.0) { acc = m.m[i] * lam[c]; first = false; }
-      for (int l = m.s - 1; l > i; --l) {  // in the order the sweep forms them
+      for (int l = m.su - 1; l > i; --l) {  // in the order the sweep forms them
         if (m.a[l][i] != 0.0) {
           if (first) { acc = m.a[l][i] * Yb[l][c]; first = false; }
           else acc = fma(m.a[l][i], Yb[l][c], acc);
@@ -1194,13 +1261,13 @@ static void ros_step_vjp(int sys, int d, const double* y, const double* p, doubl
 // ------------------------------------------------------- method dispatch --
 template <class T, class P>
 static void phi_any(int method, int sys, int d, const T* y, const P* p, T h, T* ynew) {
-  if (is_ros(method)) ros_phi(sys, d, y, p, h, ynew);
+  if (is_ros(method)) ros_phi(*ros_of(method), sys, d, y, p, h, ynew);
   else erk_phi(*erk_of(method), sys, d, y, p, h, ynew);
 }
 
 static void step_vjp_any(int method, int sys, int d, const double* y, const double* p,
                          double h, const double* lam, double* lam_in, double* gp) {
-  if (is_ros(method)) ros_step_vjp(sys, d, y, p, h, lam, lam_in, gp);
+  if (is_ros(method)) ros_step_vjp(*ros_of(method), sys, d, y, p, h, lam, lam_in, gp);
   else erk_step_vjp(*erk_of(method), sys, d, y, p, h, lam, lam_in, gp);
 }
 
@@ -1254,13 +1321,18 @@ int oracle_jac_vjp(int sys, const double* y, const double* p, const double* u,
   return 0;
 }
 
-// Rodas4 in transformed form: gamma, a[s*s], c[s*s], m[s]; returns s.
-int oracle_ros_tableau(double* gamma, double* a, double* c, double* m, int* order,
-                       int* q_emb) {
-  const ROS& r = RODAS4;
+// A Rosenbrock method (3: Rodas4, 4: Rosenbrock23) in transformed form:
+// gamma, a[s*s], c[s*s], m[s], error weights e[s], su; returns s.
+int oracle_ros_tableau(int method, double* gamma, double* a, double* c, double* m,
+                       double* e, int* order, int* q_emb, int* su) {
+  const ROS* rp = ros_of(method);
+  if (!rp) return -1;
+  const ROS& r = *rp;
   *gamma = r.gamma;
+  *su = r.su;
   for (int i = 0; i < r.s; ++i) {
     m[i] = r.m[i];
+    e[i] = r.e[i];
     for (int j = 0; j < r.s; ++j) {
       a[i * r.s + j] = r.a[i][j];
       c[i * r.s + j] = r.c[i][j];
@@ -1269,6 +1341,22 @@ int oracle_ros_tableau(double* gamma, double* a, double* c, double* m, int* orde
   *order = r.order;
   *q_emb = r.q_emb;
   return r.s;
+}
+
+// One trial step of a Rosenbrock method from y with step h: y_new and the
+// error estimate vector (before scaling).
+int oracle_ros_trial(int method, int sys, const double* y, const double* p, double h,
+                     double* ynew, double* err) {
+  const ROS* rp = ros_of(method);
+  const int d = sys_dim(sys);
+  if (!rp || d < 0 || (sys != SYS_ROBERTSON && sys != SYS_HIRES && sys != SYS_LINEAR) ||
+      h == 0.0)
+    return -1;
+  double Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
+  int perm[DMAX];
+  ros_step(*rp, sys, d, y, p, h, ynew, Y, u, LU, perm);
+  ros_errvec(*rp, d, u, err);
+  return 0;
 }
 
 int oracle_vjp(int sys, const double* y, const double* p, const double* w,
