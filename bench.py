@@ -151,7 +151,7 @@ def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
     import oracle as O
     so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON, "hires": O.HIRES,
           "linear": O.LINEAR, "ude": O.LV_UDE}[cfg["system"]]
-    mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS}[cfg["method"]]
+    mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}[cfg["method"]]
     save = list(st)
     shared = cfg.get("shared", False)
 
@@ -491,7 +491,7 @@ def forward_bench(args):
     if not args.no_cpu_baseline:
         so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON,
               "linear": O.LINEAR}[cfg["system"]]
-        mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS}[cfg["method"]]
+        mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}[cfg["method"]]
 
         def run(mm):
             t = time.perf_counter()

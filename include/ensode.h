@@ -86,20 +86,25 @@ extern "C" {
 #define ENS_SYS_LINEAR 6    /* d = 2, P = 2: (a, w) */
 
 /* Methods (paper, Section 3.2).  The explicit pairs run on LORENZ, VDP and
- * LINEAR in F64 or F32, Tsit5 also on LV_UDE in F32; the Rosenbrock method on
- * ROBERTSON, HIRES and LINEAR in F64.  Other combinations return
- * ENS_EUNSUPPORTED. */
+ * LINEAR in F64 or F32, Tsit5 also on LV_UDE in F32; the Rosenbrock methods
+ * (Rodas4, Rosenbrock23) on ROBERTSON, HIRES and LINEAR in F64.  Other
+ * combinations return ENS_EUNSUPPORTED. */
 /* Systems registered at run time (ensemble_system_register) get the ids
  * ENS_SYS_USER_BASE, ENS_SYS_USER_BASE + 1, ... */
 #define ENS_SYS_USER_BASE 1000
 #define ENS_USER_MAX_SYSTEMS 64
-#define ENS_USER_MAX_DIM 16     /* 8 with a Jacobian (Rodas4) */
+#define ENS_USER_MAX_DIM 16     /* 8 with a Jacobian (Rosenbrock methods) */
 #define ENS_USER_MAX_PARAMS 64
 
 #define ENS_TSIT5 1  /* Tsitouras 5(4), 7 stages, first-same-as-last */
 #define ENS_VERN7 2  /* Verner 7(6), 10 stages */
 #define ENS_RODAS4 3 /* Rosenbrock-Wanner Rodas4 (Hairer-Wanner IV.7), order
                         4(3), 6 stages, one LU of I/(gamma h) - J per step */
+#define ENS_ROS23 4  /* Rosenbrock23 (Shampine-Reichelt, the paper's default
+                        stiff method for fused fields, Section 3.2): order 2
+                        with an O(h^3) error estimate, 3 stages in a trial
+                        step and 2 in a replay, one LU per step; autonomous
+                        fields only (all built-in stiff systems are) */
 
 #define ENS_F64 1
 #define ENS_F32 2
@@ -108,7 +113,7 @@ extern "C" {
 
 typedef struct {
   int32_t system;        /* ENS_SYS_* */
-  int32_t method;        /* ENS_TSIT5 / ENS_VERN7 / ENS_RODAS4 */
+  int32_t method;        /* ENS_TSIT5 / ENS_VERN7 / ENS_RODAS4 / ENS_ROS23 */
   int32_t dtype;         /* ENS_F64 / ENS_F32 */
   int32_t dim;           /* must equal the system's state dimension */
   int32_t nparams;       /* must equal the system's parameter count */
@@ -267,7 +272,8 @@ int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
  * ensemble_adjoint): 2 scale sum y . ydot (SUMSQ), 2 scale sum (y - target)
  * . ydot (MSE_TARGET), sum c . ydot (COTANGENT).  Per-trajectory parameters
  * only; built for Lorenz, Van der Pol and the damped rotation (Tsit5, Vern7;
- * F64, F32) and Robertson and the damped rotation (Rodas4, F64); otherwise
+ * F64, F32) and Robertson and the damped rotation (Rodas4, Rosenbrock23;
+ * F64); otherwise
  * ENS_EUNSUPPORTED.  Trajectories whose record failed get NaN.  Full and
  * checkpointed tapes alike (only the mesh is read). */
 int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* rec,
@@ -283,7 +289,7 @@ int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* 
  *   rhs(const T* y, const T* p, T* f)                 f = f(y, p)
  *   vjp(const T* y, const T* p, const T* w, T* gy, T* gp)
  *                    gy = (df/dy)^T w (overwrite), gp += (df/dp)^T w
- * and, with has_jacobian != 0 (needed for Rodas4, dim <= 8),
+ * and, with has_jacobian != 0 (needed for the Rosenbrock methods, dim <= 8),
  *   jac(const T* y, const T* p, T* J)                 J = df/dy, row-major
  *   jac_vjp(const T* y, const T* p, const T* u, const T* v, T* gy, T* gp)
  *                    gy, gp += d/d(y, p) of u^T J(y, p) v
@@ -298,6 +304,7 @@ int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* 
  * dim in [1, ENS_USER_MAX_DIM], nparams in [1, ENS_USER_MAX_PARAMS].  On
  * success *system receives the id to use in ens_problem.system.  The Tsit5
  * kernels in F64 (and Rodas4 with a Jacobian) are compiled here; the others
+ * (Rosenbrock23 among them)
  * on first use.  Registered systems are not served by ensemble_server_*.
  * Thread-safe; a registration lasts until the process ends. */
 int ensemble_system_register(const char* source, int dim, int nparams, int has_jacobian,

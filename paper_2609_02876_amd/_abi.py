@@ -15,7 +15,7 @@ ENS_OK, ENS_EINVAL, ENS_EUNSUPPORTED, ENS_ENOSPACE, ENS_EHIP = 0, -1, -2, -3, -4
 LANE_OK, LANE_MAX_STEPS, LANE_DT_UNDERFLOW, LANE_NONFINITE, LANE_NOSPACE = 0, 1, 2, 3, 4
 # systems / methods / dtypes / losses
 SYS_LORENZ, SYS_VDP, SYS_ROBERTSON, SYS_HIRES, SYS_LV_UDE, SYS_LINEAR = 1, 2, 3, 4, 5, 6
-TSIT5, VERN7, RODAS4 = 1, 2, 3
+TSIT5, VERN7, RODAS4, ROS23 = 1, 2, 3, 4
 F64, F32 = 1, 2
 LOSS_SUMSQ, LOSS_MSE_TARGET, LOSS_COTANGENT = 0, 1, 2
 MAX_SAVE = 64
@@ -24,7 +24,7 @@ SYSTEMS = {"lorenz": (SYS_LORENZ, 3, 3), "vdp": (SYS_VDP, 2, 1),
            "robertson": (SYS_ROBERTSON, 3, 3), "hires": (SYS_HIRES, 8, 12),
            "ude": (SYS_LV_UDE, 2, 1218),
            "linear": (SYS_LINEAR, 2, 2)}
-METHODS = {"tsit5": TSIT5, "vern7": VERN7, "rodas4": RODAS4}
+METHODS = {"tsit5": TSIT5, "vern7": VERN7, "rodas4": RODAS4, "ros23": ROS23}
 
 
 class Problem(C.Structure):

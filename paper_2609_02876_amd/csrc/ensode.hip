@@ -70,6 +70,8 @@ size_t rec_bytes(int dtype, int d) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool is_ros_method(int m) { return m == ENS_RODAS4 || m == ENS_ROS23; }
+
 int check_problem(const ens_problem* p, SysInfo* si) {
   if (!p) return fail(ENS_EINVAL, "problem is NULL");
   if (!sys_info(p->system, si))
@@ -77,7 +79,7 @@ int check_problem(const ens_problem* p, SysInfo* si) {
   if (p->dim != si->d || p->nparams != si->np)
     return fail(ENS_EINVAL, "system %d has dim %d and %d params (got %d, %d)",
                 p->system, si->d, si->np, p->dim, p->nparams);
-  if (p->method != ENS_TSIT5 && p->method != ENS_VERN7 && p->method != ENS_RODAS4)
+  if (p->method != ENS_TSIT5 && p->method != ENS_VERN7 && !is_ros_method(p->method))
     return fail(ENS_EUNSUPPORTED, "unknown method %d", p->method);
   if (p->dtype != ENS_F64 && p->dtype != ENS_F32)
     return fail(ENS_EUNSUPPORTED, "unknown dtype %d", p->dtype);
@@ -92,24 +94,27 @@ int check_problem(const ens_problem* p, SysInfo* si) {
     int d, np;
     bool jac;
     rtc_info(p->system, &d, &np, &jac);
-    if (p->method == ENS_RODAS4 && !jac)
+    if (is_ros_method(p->method) && !jac)
       return fail(ENS_EUNSUPPORTED,
-                  "system %d was registered without jac and jac_vjp, which Rodas4 needs",
+                  "system %d was registered without jac and jac_vjp, which a Rosenbrock "
+                  "method needs",
                   p->system);
-    if (p->method == ENS_RODAS4 && p->dtype != ENS_F64)
-      return fail(ENS_EUNSUPPORTED, "Rodas4 is built for F64 only");
+    if (is_ros_method(p->method) && p->dtype != ENS_F64)
+      return fail(ENS_EUNSUPPORTED, "the Rosenbrock methods are built for F64 only");
     if (p->params_shared != 0 && p->params_shared != 1)
       return fail(ENS_EINVAL, "params_shared must be 0 or 1");
     return ENS_OK;
   }
   const bool stiff_sys = p->system == ENS_SYS_ROBERTSON || p->system == ENS_SYS_HIRES;
-  if (p->method == ENS_RODAS4) {
+  if (is_ros_method(p->method)) {
     if (!stiff_sys && p->system != ENS_SYS_LINEAR)
-      return fail(ENS_EUNSUPPORTED, "Rodas4 runs on the Robertson, HIRES and linear systems");
+      return fail(ENS_EUNSUPPORTED,
+                  "the Rosenbrock methods run on the Robertson, HIRES and linear systems");
     if (p->dtype != ENS_F64)
-      return fail(ENS_EUNSUPPORTED, "Rodas4 is built for F64 only");
+      return fail(ENS_EUNSUPPORTED, "the Rosenbrock methods are built for F64 only");
   } else if (stiff_sys) {
-    return fail(ENS_EUNSUPPORTED, "system %d is stiff: use ENS_RODAS4", p->system);
+    return fail(ENS_EUNSUPPORTED, "system %d is stiff: use ENS_RODAS4 or ENS_ROS23",
+                p->system);
   }
   if (p->params_shared != 0 && p->params_shared != 1)
     return fail(ENS_EINVAL, "params_shared must be 0 or 1");
@@ -328,15 +333,18 @@ int with_kernels(int sys, int method, int dtype, F&& f) {
     if (method == ENS_TSIT5) return by_type(sys_tag, Tsit5{});
     return by_type(sys_tag, Vern7{});
   };
-  if (method == ENS_RODAS4) {
-    if (dtype != ENS_F64) return fail(ENS_EUNSUPPORTED, "Rodas4 is built for F64 only");
+  auto by_ros = [&](auto tab_tag) -> int {
+    if (dtype != ENS_F64)
+      return fail(ENS_EUNSUPPORTED, "the Rosenbrock methods are built for F64 only");
     switch (sys) {
-      case ENS_SYS_ROBERTSON: return f(Robertson{}, Rodas4{}, double{});
-      case ENS_SYS_HIRES: return f(Hires{}, Rodas4{}, double{});
-      case ENS_SYS_LINEAR: return f(Linear{}, Rodas4{}, double{});
+      case ENS_SYS_ROBERTSON: return f(Robertson{}, tab_tag, double{});
+      case ENS_SYS_HIRES: return f(Hires{}, tab_tag, double{});
+      case ENS_SYS_LINEAR: return f(Linear{}, tab_tag, double{});
     }
-    return fail(ENS_EUNSUPPORTED, "Rodas4 is not built for system %d", sys);
-  }
+    return fail(ENS_EUNSUPPORTED, "the Rosenbrock methods are not built for system %d", sys);
+  };
+  if (method == ENS_RODAS4) return by_ros(Rodas4{});
+  if (method == ENS_ROS23) return by_ros(Ros23{});
   switch (sys) {
     case ENS_SYS_LORENZ: return by_method(Lorenz{});
     case ENS_SYS_VDP: return by_method(VanDerPol{});
@@ -745,7 +753,7 @@ extern "C" int ensemble_system_register(const char* source, int dim, int nparams
   if (nparams < 1 || nparams > ENS_USER_MAX_PARAMS)
     return fail(ENS_EINVAL, "nparams must be in [1, %d]", ENS_USER_MAX_PARAMS);
   if (has_jacobian && dim > 8)
-    return fail(ENS_EINVAL, "a system with a Jacobian (for Rodas4) has dim <= 8");
+    return fail(ENS_EINVAL, "a system with a Jacobian (for the Rosenbrock methods) has dim <= 8");
   const std::string src(source);
   const std::string bad = refused_construct(src);
   if (!bad.empty())

@@ -282,7 +282,7 @@ __device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double
   return rms<D>(e, sc);
 }
 
-// x^(-1/K) for the controller and the starting step (K = 4..8), from
+// x^(-1/K) for the controller and the starting step (K = 3..8), from
 // operations that are exactly or correctly rounded on the device and on any
 // IEEE host: x = m 2^e (m in [0.5, 1)), e = K q + j, a linear first guess
 // for m^(-1/K) times 2^(-j/K) 2^(-q), then four Newton steps
@@ -290,6 +290,10 @@ __device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double
 // the bit.  Arguments below 1e-300 are raised to it.
 template <int K>
 struct TwoNeg;
+template <>
+struct TwoNeg<3> {
+  static constexpr double c[3] = {1.0, 0.7937005259840998, 0.6299605249474366};
+};
 template <>
 struct TwoNeg<4> {
   static constexpr double c[4] = {1.0, 0.8408964152537145, 0.7071067811865476,
@@ -605,10 +609,16 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       const bool zero = (hh == 0.0);
       T W[D * D], u[Tab::S][D];
       int piv[D];
-      ros_step<Sys, Tab, T>(y, p, T(zero ? 1.0 : hh), W, piv, u, ynew);
+      // a replay on a given mesh forms only the stages that enter y_new
+      ros_step<Sys, Tab, T, (MODE == MODE_FROZEN ? Tab::SU : Tab::S)>(
+          y, p, T(zero ? 1.0 : hh), W, piv, u, ynew);
 #pragma unroll
       for (int c = 0; c < D; ++c) ynew[c] = zero ? y[c] : ynew[c];
-      if constexpr (MODE != MODE_FROZEN) err = ros_err<D, T>(y, ynew, u[Tab::S - 1], rtol, atol);
+      if constexpr (MODE != MODE_FROZEN) {
+        T e[D];
+        ros_errvec<Tab, D, T>(u, e);
+        err = ros_err<D, T>(y, ynew, e, rtol, atol);
+      }
     } else {
       T kb[D];
       if constexpr (Tab::FSAL) {
@@ -960,9 +970,9 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
     int piv[D];
     T Y[NY][D], ys[D];
     if constexpr (W_LDS) {
-      ros_step_lds<Sys, Tab, T>(yb, p, T(hh), LdsMat<T>{s_W}, piv, u, ys);
+      ros_step_lds<Sys, Tab, T, Tab::SU>(yb, p, T(hh), LdsMat<T>{s_W}, piv, u, ys);
     } else if constexpr (Tab::ROS) {
-      ros_step<Sys, Tab, T>(yb, p, T(hh), W, piv, u, ys);
+      ros_step<Sys, Tab, T, Tab::SU>(yb, p, T(hh), W, piv, u, ys);
     } else {
       T k0[D], ylast[D], klast[D];
       Sys::rhs(yb, p, k0);

@@ -108,7 +108,7 @@ __device__ __forceinline__ void jvp_phi(const DT* y, const DT* p, double h, DT* 
     const bool zero = (h == 0.0);
     DT W[D * D], u[Tab::S][D], ys[D];
     int piv[D];
-    ros_step<Sys, Tab, DT>(y, p, DT(zero ? 1.0 : h), W, piv, u, ys);
+    ros_step<Sys, Tab, DT, Tab::SU>(y, p, DT(zero ? 1.0 : h), W, piv, u, ys);
 #pragma unroll
     for (int c = 0; c < D; ++c) yn[c] = pick(zero, y[c], ys[c]);
   } else {

@@ -180,32 +180,42 @@ __device__ __forceinline__ void lu_solve_t(const Mat& W, const int (&piv)[D], T*
   permute_bwd<D, T>(piv, z);
 }
 
-// The increments u_1..u_s of one step from y with step h (h != 0), the
-// factors left in W/piv for the reverse, and y_new = Y_s + u_s.
-// The stages after the factorisation; W: the factors as a register array or
-// an LdsMat.
-template <class Sys, class Tab, class T, class Mat>
+// Stage input Y_i = y + sum_{j<i} A_ij u_j (index order, first term a
+// product, the rest fmas).
+template <class Tab, int D, class T>
+__device__ __forceinline__ void ros_input(int i, const T* y, const T (&u)[Tab::S][D], T* Yi) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < Tab::S; ++j) {
+      if (j < i && Tab::A[i][j] != 0.0) {
+        acc = first ? cmul(Tab::A[i][j], u[j][c]) : cfma(Tab::A[i][j], u[j][c], acc);
+        first = false;
+      }
+    }
+    Yi[c] = first ? y[c] : y[c] + acc;
+  }
+}
+
+// The increments u_1..u_NSC of one step from y with step h (h != 0), the
+// factors left in W/piv for the reverse, and y_new: Y_s + u_s, or the last
+// stage input Y_s (NEW_AT_INPUT).  NSC = S forms every stage (a trial step
+// needs the last for its error estimate); NSC = SU only those that enter
+// y_new (a replay).  W: the factors as a register array or an LdsMat.
+template <class Sys, class Tab, class T, class Mat, int NSC = Tab::S>
 __device__ __forceinline__ void ros_stages(const T* y, const T* p, T h, const Mat& W,
                                            const int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D],
                                            T* ynew) {
   constexpr int D = Sys::D, NS = Tab::S;
+  static_assert(NSC == NS || (NSC == Tab::SU && Tab::NEW_AT_INPUT),
+                "a step that stops short of the last stage needs y_new at its input");
   const T hinv = T(1.0) / h;
   T Yi[D];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) {
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      T acc = T(0);
-      bool first = true;
-#pragma unroll
-      for (int j = 0; j < i; ++j) {
-        if (Tab::A[i][j] != 0.0) {
-          acc = first ? cmul(Tab::A[i][j], u[j][c]) : cfma(Tab::A[i][j], u[j][c], acc);
-          first = false;
-        }
-      }
-      Yi[c] = first ? y[c] : y[c] + acc;
-    }
+  for (int i = 0; i < NSC; ++i) {
+    ros_input<Tab, D, T>(i, y, u, Yi);
     T F[D];
     Sys::rhs(Yi, p, F);
 #pragma unroll
@@ -223,28 +233,57 @@ __device__ __forceinline__ void ros_stages(const T* y, const T* p, T h, const Ma
     }
     lu_solve<D, T, Mat>(W, piv, u[i]);
   }
+  if constexpr (Tab::NEW_AT_INPUT) {
+    ros_input<Tab, D, T>(NS - 1, y, u, ynew);
+  } else {
 #pragma unroll
-  for (int c = 0; c < D; ++c) ynew[c] = Yi[c] + u[NS - 1][c];
+    for (int c = 0; c < D; ++c) ynew[c] = Yi[c] + u[NS - 1][c];
+  }
 }
 
-template <class Sys, class Tab, class T>
+template <class Sys, class Tab, class T, int NSC = Tab::S>
 __device__ __forceinline__ void ros_step(const T* y, const T* p, T h, T (&W)[Sys::D * Sys::D],
                                          int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D], T* ynew) {
   ros_factor<Sys, Tab, T>(y, p, h, W, piv);
-  ros_stages<Sys, Tab, T, T[Sys::D * Sys::D]>(y, p, h, W, piv, u, ynew);
+  ros_stages<Sys, Tab, T, T[Sys::D * Sys::D], NSC>(y, p, h, W, piv, u, ynew);
+}
+
+// Error estimate e = sum_j E_j u_j (Rodas4: u_6 itself).
+template <class Tab, int D, class T>
+__device__ __forceinline__ void ros_errvec(const T (&u)[Tab::S][D], T* e) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < Tab::S; ++j) {
+      if (Tab::E[j] != 0.0) {
+        acc = first ? cmul(Tab::E[j], u[j][c]) : cfma(Tab::E[j], u[j][c], acc);
+        first = false;
+      }
+    }
+    e[c] = acc;
+  }
 }
 
 // The same step with the factors moved to this lane's LDS slots right after
 // the factorisation (the same values, so the same results), for systems
 // whose factors crowd the registers of the reverse sweep.
-template <class Sys, class Tab, class T>
+template <class Sys, class Tab, class T, int NSC = Tab::S>
 __device__ __forceinline__ void ros_step_lds(const T* y, const T* p, T h, const LdsMat<T>& Wl,
                                              int (&piv)[Sys::D], T (&u)[Tab::S][Sys::D],
                                              T* ynew) {
   T W[Sys::D * Sys::D];
   ros_factor<Sys, Tab, T>(y, p, h, W, piv);
   put_lds<Sys::D, T>(W, Wl);
-  ros_stages<Sys, Tab, T, LdsMat<T>>(y, p, h, Wl, piv, u, ynew);
+  ros_stages<Sys, Tab, T, LdsMat<T>, NSC>(y, p, h, Wl, piv, u, ynew);
+}
+
+template <class Tab>
+constexpr bool m_nonzero_below_su() {
+  for (int i = 0; i < Tab::SU; ++i)
+    if (Tab::M[i] == 0.0) return false;
+  return true;
 }
 
 // Reverse of one step (W, piv, u from ros_step at the same y, h; W as a
@@ -254,16 +293,16 @@ __device__ __forceinline__ void ros_step_lds(const T* y, const T* p, T h, const 
 //   rbar_i = W^{-T} ubar_i,  Ybar_i = f_y(Y_i)^T rbar_i,  gp += f_p(Y_i)^T rbar_i
 //   lam_in = w + sum_i Ybar_i + d/dy sum_i rbar_i^T J(y) u_i,
 // the last term (and its p part, into gp) from each stage in turn.  Stage
-// cotangents are pushed into running sums as they are formed.
+// cotangents are pushed into running sums as they are formed.  Only the SU
+// stages that enter y_new are reversed (a stage that serves the error
+// estimate alone has a zero cotangent).
 template <class Sys, class Tab, class T, class Mat>
 __device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h, const Mat& W,
                                              const int (&piv)[Sys::D],
                                              const T (&u)[Tab::S][Sys::D], const T* w,
                                              T* lam_in, T* gp) {
-  constexpr int D = Sys::D, NS = Tab::S;
-  static_assert(Tab::M[0] != 0.0 && Tab::M[1] != 0.0 && Tab::M[2] != 0.0 &&
-                    Tab::M[3] != 0.0 && Tab::M[4] != 0.0 && Tab::M[5] != 0.0,
-                "every stage sum starts with its M term");
+  constexpr int D = Sys::D, NS = Tab::SU;
+  static_assert(m_nonzero_below_su<Tab>(), "every stage sum starts with its M term");
   const T hinv = T(1.0) / h;
   T ub[NS][D], gJ[D];
 #pragma unroll

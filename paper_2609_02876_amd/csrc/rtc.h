@@ -98,7 +98,10 @@ std::string refused_construct(const std::string& s) {
 }
 
 const char* tab_name(int method) {
-  return method == ENS_TSIT5 ? "ens::Tsit5" : method == ENS_VERN7 ? "ens::Vern7" : "ens::Rodas4";
+  return method == ENS_TSIT5   ? "ens::Tsit5"
+         : method == ENS_VERN7 ? "ens::Vern7"
+         : method == ENS_ROS23 ? "ens::Ros23"
+                               : "ens::Rodas4";
 }
 
 // Name expressions of every kernel a registered system uses with one method

@@ -79,11 +79,15 @@ struct Vern7 {
 // in the transformed variables u_i = h sum_j gamma_ij k_j (W = I/(gamma h) - J):
 //   Y_i = y + sum_{j<i} A_ij u_j,   W u_i = f(Y_i) + (1/h) sum_{j<i} C_ij u_j,
 //   y_new = Y_6 + u_6 = y + sum_j M_j u_j,   error estimate u_6.
+// Fields shared by the Rosenbrock methods: S stages, the first SU of which
+// enter y_new; NEW_AT_INPUT: y_new is the input Y_S of the last stage
+// (otherwise Y_S + u_S); the error estimate is sum_j E_j u_j.
 struct Rodas4 {
   static constexpr int S = 6;
   static constexpr int SU = 6;
   static constexpr bool FSAL = false;
   static constexpr bool ROS = true;
+  static constexpr bool NEW_AT_INPUT = false;
   static constexpr int ORDER = 4;
   static constexpr int QEMB = 3;
   static constexpr double GAMMA = 0.25;
@@ -104,6 +108,39 @@ struct Rodas4 {
        -6.058818238834054, 0}};
   static constexpr double M[6] = {1.221224509226641, 6.019134481288629, 12.53708332932087,
                                   -0.6878860361058950, 1.0, 1.0};
+  static constexpr double E[6] = {0, 0, 0, 0, 0, 1.0};
+};
+
+// Rosenbrock23 (Shampine & Reichelt 1997, MATLAB's ode23s) for autonomous
+// fields, order 2 with an O(h^3) error estimate.  With d = 1/(2 + sqrt 2) and
+// e32 = 6 + sqrt 2 the published slope form is
+//   W = I - h d J,  W k1 = f(y),  W (k2 - k1) = f(y + h k1/2) - k1,
+//   y_new = y + h k2,  W k3 = f(y_new) - e32 (k2 - f(y + h k1/2)) - 2 (k1 - f(y)),
+//   error (h/6)(k1 - 2 k2 + k3).
+// Since k1 - f(y) = h d J k1 and k2 - f(y + h k1/2) = h d J (k2 - k1), it is
+// the Rosenbrock method with gamma = d, alpha_21 = 1/2, alpha_32 = 1,
+// gamma_21 = -d, gamma_31 = (e32 - 2) d, gamma_32 = -e32 d, b = (0, 1, 0);
+// in the transformed variables (Gamma^{-1} = [[1,0,0],[1,1,0],[2,e32,1]]/d):
+//   A_21 = 1/(2d), A_31 = A_32 = 1/d;  C_21 = -1/d, C_31 = -2/d, C_32 = -e32/d;
+//   y_new = Y_3 = y + (u_1 + u_2)/d;  error (u_1 + (e32 - 2) u_2 + u_3)/(6d).
+// The third stage serves the error estimate only, so a replay takes two.
+struct Ros23 {
+  static constexpr int S = 3;
+  static constexpr int SU = 2;
+  static constexpr bool FSAL = false;
+  static constexpr bool ROS = true;
+  static constexpr bool NEW_AT_INPUT = true;
+  static constexpr int ORDER = 2;
+  static constexpr int QEMB = 2;
+  static constexpr double GAMMA = 0.2928932188134525;
+  static constexpr double A[3][3] = {{0, 0, 0},
+                                     {1.7071067811865475, 0, 0},
+                                     {3.414213562373095, 3.414213562373095, 0}};
+  static constexpr double C[3][3] = {{0, 0, 0},
+                                     {-3.414213562373095, 0, 0},
+                                     {-6.82842712474619, -25.31370849898476, 0}};
+  static constexpr double M[3] = {3.414213562373095, 3.414213562373095, 0};
+  static constexpr double E[3] = {0.5690355937288492, 3.080880229039762, 0.5690355937288492};
 };
 
 }  // namespace ens

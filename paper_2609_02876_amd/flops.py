@@ -60,10 +60,14 @@ JACOBIANS = {
     "linear": (0, 8),
 }
 
-# Rodas4: nonzero counts of the rows of A (stage inputs) and C (stage
-# right-hand sides), stages 2..6
+# Rosenbrock methods: nonzero counts of the rows of A (stage inputs) and C
+# (stage right-hand sides); SU of the S stages enter y_new; e_nnz: nonzero
+# error weights; new_at_input: y_new is the last stage's input (Rosenbrock23)
+# rather than Y_s + u_s (Rodas4)
 ROS_TABLEAUX = {
-    "rodas4": dict(S=6, a_nnz=[0, 1, 2, 3, 4, 5], c_nnz=[0, 1, 2, 3, 4, 5]),
+    "rodas4": dict(S=6, SU=6, a_nnz=[0, 1, 2, 3, 4, 5], c_nnz=[0, 1, 2, 3, 4, 5], e_nnz=1,
+                   new_at_input=False),
+    "ros23": dict(S=3, SU=2, a_nnz=[0, 1, 2], c_nnz=[0, 1, 2], e_nnz=3, new_at_input=True),
 }
 
 
@@ -77,20 +81,31 @@ def _ros_per_unit(method, system):
     t = ROS_TABLEAUX[method]
     D, F, V = SYSTEMS[system]
     J, JV = JACOBIANS[system]
-    S = t["S"]
+    S, SU = t["S"], t["SU"]
+    a_nnz, c_nnz = t["a_nnz"], t["c_nnz"]
     solve = 2 * D * D - D                       # L and U sweeps, D divisions
     factor = J + 2 + D + _lu(D)                 # jac, 1/(gamma h), diagonal, LU
-    stage_in = sum(2 * z for z in t["a_nnz"]) * D
-    stage_rhs = sum(2 * w + 1 for w in t["c_nnz"] if w) * D
-    stages = 1 + stage_in + S * F + stage_rhs + S * solve     # 1: 1/h
-    update = D                                   # y_new = Y_s + u_s
-    err = 3 * D + (3 * D + 1)
+
+    def stage_in(k):                            # inputs of the first k stages
+        return sum(2 * z for z in a_nnz[:k]) * D
+
+    def stages(k):                              # 1: 1/h
+        return 1 + stage_in(k) + k * F + sum(2 * w + 1 for w in c_nnz[:k] if w) * D + k * solve
+
+    # y_new: Y_s + u_s, or the last stage's input (counted with the stages
+    # of a trial, formed on its own after the SU stages of a replay)
+    upd_trial = 0 if t["new_at_input"] else D
+    upd_replay = 2 * a_nnz[S - 1] * D if t["new_at_input"] else D
+    e_combo = (2 * t["e_nnz"] - 1) * D if t["e_nnz"] > 1 else 0
+    err = e_combo + 3 * D + (3 * D + 1)
     controller = 7
-    trial = factor + stages + update + err + controller
-    side_fwd = factor + stages + update
-    push = sum(2 * (z + w) for z, w in zip(t["a_nnz"], t["c_nnz"])) * D
-    reverse = S * D + S * solve + S * D + stage_in + S * V + S * D + S * JV + push + D
-    adj_step = factor + stages + reverse
+    trial = factor + stages(S) + upd_trial + err + controller
+    side_fwd = factor + stages(SU) + upd_replay
+    push = sum(2 * (z + w) for z, w in zip(a_nnz[:SU], c_nnz[:SU])) * D
+    reverse = (SU * D + SU * solve + SU * D + stage_in(SU) + SU * V + SU * D + SU * JV + push
+               + D)
+    update = upd_replay
+    adj_step = factor + stages(SU) + reverse
     cot = 3 * D
     adj_side = adj_step + update + cot + D
     adj_zero = cot + D
@@ -151,13 +166,15 @@ def _ros_jvp_per_step(method, system):
     the stage combinations with constant coefficients twice."""
     t = ROS_TABLEAUX[method]
     D = SYSTEMS[system][0]
-    S = t["S"]
+    S, SU = t["S"], t["SU"]
     lu = sum(6 * m + 6 * m * m for m in range(1, D))
     factor = JAC_DUAL[system] + 2 + 2 * D + lu
     solve = 6 * D * D
-    stage_in = sum(2 * z for z in t["a_nnz"]) * D
-    stage_rhs = sum(2 * w + 1 for w in t["c_nnz"] if w) * D
-    return factor + 1 + S * solve + 2 * stage_in + S * RHS_DUAL[system] + 2 * stage_rhs + 2 * D
+    stage_in = sum(2 * z for z in t["a_nnz"][:SU]) * D
+    stage_rhs = sum(2 * w + 1 for w in t["c_nnz"][:SU] if w) * D
+    update = 2 * (2 * t["a_nnz"][S - 1] * D if t["new_at_input"] else D)
+    return (factor + 1 + SU * solve + 2 * stage_in + SU * RHS_DUAL[system] + 2 * stage_rhs
+            + update)
 
 
 def jvp_per_step(method, system):

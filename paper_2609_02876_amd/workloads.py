@@ -113,6 +113,11 @@ WORKLOADS = {
                                 t1=1e5, rtol=1e-6, atol=1e-10, n_save=20),
     "hires_2p18": dict(system="hires", method="rodas4", n=1 << 18, t0=0.0, t1=321.8122,
                        rtol=1e-6, atol=1e-10, n_save=20),
+    # the same two with Rosenbrock23 (order 2, three stages in a trial step)
+    "robertson_ros23_2p18_t1e5": dict(system="robertson", method="ros23", n=1 << 18, t0=0.0,
+                                      t1=1e5, rtol=1e-6, atol=1e-10, n_save=20),
+    "hires_ros23_2p18": dict(system="hires", method="ros23", n=1 << 18, t0=0.0,
+                             t1=321.8122, rtol=1e-6, atol=1e-10, n_save=20),
     # UDE: Lotka-Volterra + MLP 2-32-32-2 (weights shared), Tsit5, FP32,
     # rtol = atol = 1e-6, 20 save times t = 0.5 s, loss = MSE to the teacher
     # network's trajectories, tape checkpointed every 64 steps (or full)

@@ -52,7 +52,9 @@ def _ivp(**kw):
 
 @pytest.mark.parametrize("system,method,d,np_", [
     (A.SYS_ROBERTSON, A.RODAS4, 3, 3), (A.SYS_HIRES, A.RODAS4, 8, 12),
-    (A.SYS_LINEAR, A.RODAS4, 2, 2), (A.SYS_LINEAR, A.VERN7, 2, 2)])
+    (A.SYS_LINEAR, A.RODAS4, 2, 2), (A.SYS_LINEAR, A.VERN7, 2, 2),
+    (A.SYS_ROBERTSON, A.ROS23, 3, 3), (A.SYS_HIRES, A.ROS23, 8, 12),
+    (A.SYS_LINEAR, A.ROS23, 2, 2)])
 def test_supported_combinations_plan(system, method, d, np_):
     lib = _lib()
     out = C.c_size_t()
@@ -87,6 +89,8 @@ def test_record_bytes_plan():
     (dict(system=A.SYS_ROBERTSON, method=A.RODAS4, dtype=A.F32), {}, A.ENS_EUNSUPPORTED),
     (dict(system=A.SYS_ROBERTSON, method=A.TSIT5), {}, A.ENS_EUNSUPPORTED),
     (dict(system=A.SYS_HIRES, method=A.RODAS4, dim=8, nparams=3), {}, A.ENS_EINVAL),
+    (dict(method=A.ROS23), {}, A.ENS_EUNSUPPORTED),
+    (dict(system=A.SYS_ROBERTSON, method=A.ROS23, dtype=A.F32), {}, A.ENS_EUNSUPPORTED),
 ])
 def test_validation_errors(prob, ivp, code):
     lib = _lib()

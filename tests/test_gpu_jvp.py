@@ -20,7 +20,7 @@ from paper_2609_02876_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 SYS_O = {"lorenz": O.LORENZ, "vdp": O.VDP, "linear": O.LINEAR, "robertson": O.ROBERTSON}
-MET_O = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS}
+MET_O = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}
 GEN = {"lorenz": W.lorenz, "vdp": W.vdp, "linear": W.damped_rotation, "robertson": W.robertson}
 TOL = {"lorenz": (1e-6, 1e-8), "vdp": (1e-6, 1e-8), "linear": (1e-6, 1e-8),
        "robertson": (1e-6, 1e-10)}
@@ -54,7 +54,8 @@ def _oracle(system, method, y0, p, t1, st, dy, dp):
     ("lorenz", "tsit5", 10.0, 1000), ("lorenz", "vern7", 10.0, 300),
     ("vdp", "tsit5", 6.3, 600), ("vdp", "vern7", 6.3, 257),
     ("linear", "tsit5", 5.0, 65), ("robertson", "rodas4", 1e5, 257),
-    ("linear", "rodas4", 5.0, 63),
+    ("linear", "rodas4", 5.0, 63), ("robertson", "ros23", 1e5, 129),
+    ("linear", "ros23", 5.0, 63),
 ])
 def test_jvp_matches_oracle_dual_replay(system, method, t1, n):
     print(f"case jvp {system} {method} n={n}", flush=True)
@@ -65,7 +66,7 @@ def test_jvp_matches_oracle_dual_replay(system, method, t1, n):
     rtol, atol = TOL[system]
     # the GPU's own adaptive record (its mesh equals the oracle's)
     h = B.ensemble_record(system, method, _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
-                          save_times=st, steps_hint=512)
+                          save_times=st, steps_hint=2048 if method == "ros23" else 512)
     ysd, ld = B.ensemble_jvp(h, _dev(dy.T), _dev(dp.T))
     # the oracle's mesh replayed on the GPU
     cap = int(rec["S"].max())
@@ -118,7 +119,8 @@ def test_jvp_loss_kinds():
 
 
 @pytest.mark.parametrize("system,method,t1", [("lorenz", "tsit5", 10.0),
-                                              ("robertson", "rodas4", 1e5)])
+                                              ("robertson", "rodas4", 1e5),
+                                              ("robertson", "ros23", 1e5)])
 def test_forward_passes_equal_reverse_gradient(system, method, t1):
     """One pass per input with the same unit tangent in every trajectory gives
     every trajectory's gradient: P + d passes against one reverse sweep."""
@@ -128,7 +130,7 @@ def test_forward_passes_equal_reverse_gradient(system, method, t1):
     rtol, atol = TOL[system]
     st = list(W.save_times(0.0, t1, 20))
     h = B.ensemble_record(system, method, _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
-                          save_times=st, steps_hint=512)
+                          save_times=st, steps_hint=2048 if method == "ros23" else 512)
     gp, gy, ll = B.ensemble_adjoint(h)
     d, npar = y0.shape[1], p.shape[1]
     for k in range(npar + d):

@@ -1,5 +1,6 @@
-"""GPU parity of the Rosenbrock (Rodas4) path against the CPU oracle:
-Robertson and HIRES (paper, Appendix A) and the damped rotation, FP64.
+"""GPU parity of the Rosenbrock path (Rodas4 and Rosenbrock23) against the
+CPU oracle: Robertson and HIRES (paper, Appendix A) and the damped rotation,
+FP64.
 
 The device repeats the oracle's operations in the same order (LU with the
 same pivot choices, the same fma placement), so meshes, save states and
@@ -20,6 +21,10 @@ pytestmark = pytest.mark.gpu
 SYS_O = {"robertson": O.ROBERTSON, "hires": O.HIRES, "linear": O.LINEAR}
 T1 = {"robertson": 1e5, "hires": 321.8122, "linear": 8.0}
 TOL64 = 1e-11
+METHODS = [("rodas4", O.RODAS), ("ros23", O.ROS23)]
+# taped steps reserved per trajectory (Rosenbrock23, of order 2, takes about
+# four times the steps of Rodas4 at rtol 1e-6)
+HINT = {"rodas4": 512, "ros23": 2560}
 
 
 def _dev(a, dtype=torch.float64):
@@ -53,19 +58,20 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("meth,mo", METHODS)
 @pytest.mark.parametrize("system,n,rtol,atol,ns", CASES)
-def test_rodas4_record_and_adjoint_match_oracle(system, n, rtol, atol, ns):
-    print(f"case rodas4 {system} n={n} rtol={rtol} atol={atol} ns={ns}", flush=True)
+def test_ros_record_and_adjoint_match_oracle(meth, mo, system, n, rtol, atol, ns):
+    print(f"case {meth} {system} n={n} rtol={rtol} atol={atol} ns={ns}", flush=True)
     t1 = T1[system]
     y0, p = _gen(system)(n, seed=5)
     st = list(W.save_times(0.0, t1, ns)) if ns else None
     so = SYS_O[system]
-    ref = O.record(so, O.RODAS, y0, p, 0.0, t1, rtol, atol, save_t=st)
+    ref = O.record(so, mo, y0, p, 0.0, t1, rtol, atol, save_t=st)
     assert np.all(ref["status"] == O.ST_OK)
-    gp_o, gy_o, ll_o = O.adjoint(so, O.RODAS, y0, p, ref)
+    gp_o, gy_o, ll_o = O.adjoint(so, mo, y0, p, ref)
     ys_o = np.transpose(ref["y_save"], (1, 2, 0))
 
-    hd = B.ensemble_record(system, "rodas4", _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
+    hd = B.ensemble_record(system, meth, _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
                            save_times=st, steps_hint=int(ref["S"].max()) + 16)
     gp, gy, ll = B.ensemble_adjoint(hd)
     torch.cuda.synchronize()
@@ -90,7 +96,7 @@ def test_rodas4_record_and_adjoint_match_oracle(system, n, rtol, atol, ns):
     cap = max(1, int(S.max()))
     h_dev = _dev(np.ascontiguousarray(ref["h"][:, :cap].T))
     S_dev = torch.tensor(S, dtype=torch.int32, device="cuda")
-    hf = B.ensemble_replay_mesh(system, "rodas4", _dev(y0.T), _dev(p.T), 0.0, t1, h_dev, S_dev,
+    hf = B.ensemble_replay_mesh(system, meth, _dev(y0.T), _dev(p.T), 0.0, t1, h_dev, S_dev,
                                 save_times=st)
     gp2, gy2, _ = B.ensemble_adjoint(hf)
     torch.cuda.synchronize()
@@ -102,16 +108,17 @@ def test_rodas4_record_and_adjoint_match_oracle(system, n, rtol, atol, ns):
     assert e_state.max() <= TOL64 and e_gp.max() <= TOL64 and e_gy.max() <= TOL64
 
 
+@pytest.mark.parametrize("meth,mo", METHODS)
 @pytest.mark.parametrize("system,K", [("robertson", 16), ("hires", 64)])
-def test_rodas4_checkpointed_tape_gives_the_same_bits(system, K):
-    print(f"case rodas4 {system} checkpoint every {K}", flush=True)
+def test_ros_checkpointed_tape_gives_the_same_bits(meth, mo, system, K):
+    print(f"case {meth} {system} checkpoint every {K}", flush=True)
     n, t1 = 700, T1[system]
     y0, p = _gen(system)(n, seed=6)
     st = list(W.save_times(0.0, t1, 20))
-    full = B.ensemble_record(system, "rodas4", _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
-                             save_times=st, steps_hint=512)
-    ck = B.ensemble_record(system, "rodas4", _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
-                           save_times=st, steps_hint=512, ckpt_every=K)
+    full = B.ensemble_record(system, meth, _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
+                             save_times=st, steps_hint=HINT[meth])
+    ck = B.ensemble_record(system, meth, _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
+                           save_times=st, steps_hint=HINT[meth], ckpt_every=K)
     g1 = B.ensemble_adjoint(full)
     g2 = B.ensemble_adjoint(ck)
     torch.cuda.synchronize()
@@ -121,37 +128,39 @@ def test_rodas4_checkpointed_tape_gives_the_same_bits(system, K):
     assert ck.pool.numel() < full.pool.numel()
 
 
-def test_rodas4_shared_parameters_sum():
+@pytest.mark.parametrize("meth,mo", METHODS)
+def test_ros_shared_parameters_sum(meth, mo):
     n = 600
     y0, _ = W.hires(n, seed=7)
     p = np.array(W.HIRES_THETA)
     st = list(W.save_times(0.0, T1["hires"], 10))
-    print("case rodas4 hires shared params", flush=True)
-    hd = B.ensemble_record("hires", "rodas4", _dev(y0.T), _dev(p), 0.0, T1["hires"], 1e-6, 1e-10,
-                           save_times=st, params_shared=True, steps_hint=512)
+    print(f"case {meth} hires shared params", flush=True)
+    hd = B.ensemble_record("hires", meth, _dev(y0.T), _dev(p), 0.0, T1["hires"], 1e-6, 1e-10,
+                           save_times=st, params_shared=True, steps_hint=HINT[meth])
     gp, _, _ = B.ensemble_adjoint(hd)
     gp_b, _, _ = B.ensemble_adjoint(hd)
     torch.cuda.synchronize()
     assert torch.equal(gp, gp_b)  # fixed-order reduction
-    ref = O.record(O.HIRES, O.RODAS, y0, p, 0.0, T1["hires"], 1e-6, 1e-10, save_t=st,
+    ref = O.record(O.HIRES, mo, y0, p, 0.0, T1["hires"], 1e-6, 1e-10, save_t=st,
                    params_shared=True)
-    gp_o, _, _ = O.adjoint(O.HIRES, O.RODAS, y0, p, ref, params_shared=True)
+    gp_o, _, _ = O.adjoint(O.HIRES, mo, y0, p, ref, params_shared=True)
     ref_sum = gp_o.sum(axis=0)
     err = np.abs(gp.cpu().numpy() - ref_sum) / np.abs(ref_sum).max()
     print(f"  max err / max |grad| {err.max():.2e}")
     assert err.max() <= 1e-12
 
 
-def test_rodas4_save_at_t0_and_t1_and_invariants():
+@pytest.mark.parametrize("meth,mo", METHODS)
+def test_ros_save_at_t0_and_t1_and_invariants(meth, mo):
     """A save at t0 is a zero-length side step (the identity); saves at t1
     come after the last step.  Robertson conserves y0 + y1 + y2 and so the
     gradient of the total at any save is zero in k and one in y0."""
     n, t1 = 300, 1e4
     y0, p = W.robertson(n, seed=8)
     st = [0.0, 1.0, 100.0, t1]
-    print("case rodas4 robertson saves at t0/t1", flush=True)
-    hd = B.ensemble_record("robertson", "rodas4", _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
-                           save_times=st, steps_hint=256)
+    print(f"case {meth} robertson saves at t0/t1", flush=True)
+    hd = B.ensemble_record("robertson", meth, _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
+                           save_times=st, steps_hint=HINT[meth])
     ys = hd.y_save.cpu().numpy()
     assert np.array_equal(ys[0], y0.T)
     tot = ys.sum(axis=1)
@@ -165,27 +174,28 @@ def test_rodas4_save_at_t0_and_t1_and_invariants():
     assert np.abs(gy_n - len(st)).max() < 1e-11
     # against each lane's gradient scale for the sum-of-squares loss
     assert np.abs(gp_n / np.abs(gref.cpu().numpy()).max(axis=0, keepdims=True)).max() < 1e-11
-    ref = O.record(O.ROBERTSON, O.RODAS, y0, p, 0.0, t1, 1e-6, 1e-10, save_t=st)
+    ref = O.record(O.ROBERTSON, mo, y0, p, 0.0, t1, 1e-6, 1e-10, save_t=st)
     assert np.array_equal(ys, np.transpose(ref["y_save"], (1, 2, 0)))
 
 
+@pytest.mark.parametrize("meth,mo", METHODS)
 @pytest.mark.parametrize("system", ["robertson", "hires"])
-def test_rodas4_full_size_sampled(system):
+def test_ros_full_size_sampled(meth, mo, system):
     """2^18 lanes, the largest stiff ensemble, in the launch that is timed:
     64 sampled lanes against the oracle run on those lanes alone."""
     cfg, y0, p, st = W.make(f"{system}_2p18" + ("_t1e5" if system == "robertson" else ""))
     n = cfg["n"]
-    print(f"case rodas4 {system} n={n} sampled", flush=True)
-    hd = B.ensemble_record(system, "rodas4", _dev(y0.T), _dev(p.T), cfg["t0"], cfg["t1"],
-                           cfg["rtol"], cfg["atol"], save_times=list(st), steps_hint=512)
+    print(f"case {meth} {system} n={n} sampled", flush=True)
+    hd = B.ensemble_record(system, meth, _dev(y0.T), _dev(p.T), cfg["t0"], cfg["t1"],
+                           cfg["rtol"], cfg["atol"], save_times=list(st), steps_hint=HINT[meth])
     gp, gy, ll = B.ensemble_adjoint(hd)
     torch.cuda.synchronize()
     status = hd.status.cpu().numpy()
     assert np.all(status == 0)
     idx = np.sort(np.random.default_rng(9).choice(n, 64, replace=False))
-    ref = O.record(SYS_O[system], O.RODAS, y0[idx], p[idx], cfg["t0"], cfg["t1"], cfg["rtol"],
+    ref = O.record(SYS_O[system], mo, y0[idx], p[idx], cfg["t0"], cfg["t1"], cfg["rtol"],
                    cfg["atol"], save_t=list(st))
-    gp_o, gy_o, _ = O.adjoint(SYS_O[system], O.RODAS, y0[idx], p[idx], ref)
+    gp_o, gy_o, _ = O.adjoint(SYS_O[system], mo, y0[idx], p[idx], ref)
     ys = hd.y_save.cpu().numpy()[..., idx]
     ys_o = np.transpose(ref["y_save"], (1, 2, 0))
     e = max(_rel(ys, ys_o).max(), _rel(gp.cpu().numpy()[:, idx], gp_o.T).max(),

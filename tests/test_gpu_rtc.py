@@ -35,7 +35,8 @@ def _name(base):
 
 def _run(system, method, y0, p, t1, rtol, atol, st, dtype, **kw):
     h = B.ensemble_record(system, method, _dev(y0.T, dtype), _dev(p.T, dtype), 0.0, t1, rtol,
-                          atol, save_times=st, steps_hint=512, **kw)
+                          atol, save_times=st, steps_hint=2048 if method == "ros23" else 512,
+                          **kw)
     gp, gy, ll = B.ensemble_adjoint(h)
     rng = np.random.default_rng(4)
     dp = _dev((rng.standard_normal(p.shape) * p).T, dtype)
@@ -58,13 +59,14 @@ def test_registered_lorenz_equals_builtin(method, dtype):
         assert torch.equal(x, y)
 
 
-def test_registered_robertson_rodas4_equals_builtin():
-    print("case registered robertson rodas4", flush=True)
+@pytest.mark.parametrize("method", ["rodas4", "ros23"])
+def test_registered_robertson_rosenbrock_equals_builtin(method):
+    print(f"case registered robertson {method}", flush=True)
     n = 513
     y0, p = W.robertson(n, seed=3)
     st = list(W.save_times(0.0, 1e5, 20))
-    a = _run("robertson", "rodas4", y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
-    b = _run(_name("rtc_robertson"), "rodas4", y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
+    a = _run("robertson", method, y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
+    b = _run(_name("rtc_robertson"), method, y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
     assert np.all(a[1].cpu().numpy() == 0)
     for x, y in zip(a, b):
         assert torch.equal(x, y)
