@@ -1004,7 +1004,10 @@ inline double absval(Cplx x) { return std::fabs(x.real()); }
 // LU factorisation with partial pivoting, in place (row-major d x d).  The
 // pivot of column k is the first row i >= k with the largest |W_ik| (ties go
 // to the lowest row); the permutation only depends on values, so it is the
-// same in every scalar type.  l_ik = W_ik / W_kk, W_ij = fma(-l_ik, W_kj, W_ij).
+// same in every scalar type.  As LAPACK's getf2 scales a column by the
+// pivot's reciprocal: r_k = 1 / W_kk, l_ik = W_ik * r_k,
+// W_ij = fma(-l_ik, W_kj, W_ij).  The diagonal keeps r_k (not U_kk), and the
+// triangular solves multiply by it.
 template <class T>
 static void lu_factor(int d, T* W, int* perm) {
   for (int i = 0; i < d; ++i) perm[i] = i;
@@ -1017,15 +1020,18 @@ static void lu_factor(int d, T* W, int* perm) {
       for (int j = 0; j < d; ++j) std::swap(W[k * d + j], W[piv * d + j]);
       std::swap(perm[k], perm[piv]);
     }
+    const T r = T(1.0) / W[k * d + k];
+    W[k * d + k] = r;
     for (int i = k + 1; i < d; ++i) {
-      T l = W[i * d + k] / W[k * d + k];
+      T l = W[i * d + k] * r;
       W[i * d + k] = l;
       for (int j = k + 1; j < d; ++j) W[i * d + j] = fma(-l, W[k * d + j], W[i * d + j]);
     }
   }
 }
 
-// Solve W x = b with the factors (x may not alias b).
+// Solve W x = b with the factors (x may not alias b; the diagonal holds the
+// reciprocals of U's).
 template <class T>
 static void lu_solve(int d, const T* LU, const int* perm, const T* b, T* x) {
   for (int i = 0; i < d; ++i) {
@@ -1036,7 +1042,7 @@ static void lu_solve(int d, const T* LU, const int* perm, const T* b, T* x) {
   for (int i = d - 1; i >= 0; --i) {
     T acc = x[i];
     for (int j = i + 1; j < d; ++j) acc = fma(-LU[i * d + j], x[j], acc);
-    x[i] = acc / LU[i * d + i];
+    x[i] = acc * LU[i * d + i];
   }
 }
 
@@ -1046,7 +1052,7 @@ static void lu_solve_t(int d, const double* LU, const int* perm, const double* b
   for (int i = 0; i < d; ++i) {
     double acc = b[i];
     for (int j = 0; j < i; ++j) acc = fma(-LU[j * d + i], v[j], acc);
-    v[i] = acc / LU[i * d + i];
+    v[i] = acc * LU[i * d + i];
   }
   for (int i = d - 1; i >= 0; --i) {
     double acc = v[i];

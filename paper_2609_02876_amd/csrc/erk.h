@@ -1005,7 +1005,7 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
       for (int c = 0; c < D; ++c) {
         opaque(yb[c]);
 #pragma unroll
-        for (int q = 0; q < NU; ++q) opaque(u[q][c]);
+        for (int q = 0; q < (Tab::ROS ? Tab::SU : 0); ++q) opaque(u[q][c]);
       }
       ros_step_vjp<Sys, Tab, T, LdsMat<T>>(yb, p, T(hh), Wl, piv, u, w, lin, gp);
     } else if constexpr (Tab::ROS) {

@@ -26,8 +26,10 @@ __device__ __forceinline__ T pick(bool c, T a, T b) {
 }
 
 // W = I/(gamma h) - J(y) factored as P W = L U (unit L below the diagonal,
-// U on and above it).  The pivot of column k is the first row i >= k with
-// the largest |W_ik|; piv[k] records it.
+// U above it).  The pivot of column k is the first row i >= k with the
+// largest |W_ik|; piv[k] records it.  The column is scaled by the pivot's
+// reciprocal r_k = 1/U_kk (as LAPACK's getf2 does), and the diagonal keeps
+// r_k, which the triangular solves multiply by: one division per pivot.
 template <class Sys, class Tab, class T>
 __device__ __forceinline__ void ros_factor(const T* y, const T* p, T h, T (&W)[Sys::D * Sys::D],
                                            int (&piv)[Sys::D]) {
@@ -60,9 +62,11 @@ __device__ __forceinline__ void ros_factor(const T* y, const T* p, T h, T (&W)[S
         W[i * D + j] = pick(sw, a, b);
       }
     }
+    const T r = T(1.0) / W[k * D + k];
+    W[k * D + k] = r;
 #pragma unroll
     for (int i = k + 1; i < D; ++i) {
-      const T l = W[i * D + k] / W[k * D + k];
+      const T l = W[i * D + k] * r;
       W[i * D + k] = l;
 #pragma unroll
       for (int j = k + 1; j < D; ++j) W[i * D + j] = fmaT(-l, W[k * D + j], W[i * D + j]);
@@ -119,6 +123,19 @@ __device__ __forceinline__ void reload_point(const LdsMat<T>&) {
 template <class A>
 __device__ __forceinline__ void reload_point(const A&) {}
 
+
+// After a solve from LDS: its result is taken as new (an optimisation
+// barrier per component), which keeps the compiler from interleaving the
+// arithmetic of successive solves; without it the 8 x 8 reverse step holds
+// too much at once and spills about 2 KB a lane.
+template <int D, class T>
+__device__ __forceinline__ void solved_point(const LdsMat<T>&, T* x) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) __asm__ __volatile__("" : "+v"(x[c]));
+}
+template <int D, class T, class A>
+__device__ __forceinline__ void solved_point(const A&, T*) {}
+
 // An optimisation barrier on a value: the compiler must treat x as changed,
 // so expressions of it formed afterwards are computed afresh instead of
 // reusing (and keeping alive) equal ones formed before.  No instruction.
@@ -137,7 +154,8 @@ __device__ __forceinline__ void put_lds(const T (&W)[D * D], const LdsMat<T>& M)
   __asm__ __volatile__("" ::: "memory");
 }
 
-// x = W^{-1} b in place: L z = P b forward, then U x = z backward.
+// x = W^{-1} b in place: L z = P b forward, then U x = z backward (the
+// diagonal holds 1/U_kk).
 template <int D, class T, class Mat>
 __device__ __forceinline__ void lu_solve(const Mat& W, const int (&piv)[D], T* x) {
   reload_point(W);
@@ -154,7 +172,7 @@ __device__ __forceinline__ void lu_solve(const Mat& W, const int (&piv)[D], T* x
     T acc = x[i];
 #pragma unroll
     for (int j = i + 1; j < D; ++j) acc = fmaT(-W[i * D + j], x[j], acc);
-    x[i] = acc / W[i * D + i];
+    x[i] = acc * W[i * D + i];
   }
 }
 
@@ -168,7 +186,7 @@ __device__ __forceinline__ void lu_solve_t(const Mat& W, const int (&piv)[D], T*
     T acc = z[i];
 #pragma unroll
     for (int j = 0; j < i; ++j) acc = fmaT(-W[j * D + i], z[j], acc);
-    z[i] = acc / W[i * D + i];
+    z[i] = acc * W[i * D + i];
   }
 #pragma unroll
   for (int i = D - 1; i >= 0; --i) {
@@ -232,6 +250,7 @@ __device__ __forceinline__ void ros_stages(const T* y, const T* p, T h, const Ma
       u[i][c] = first ? F[c] : fmah(acc, hinv, F[c]);
     }
     lu_solve<D, T, Mat>(W, piv, u[i]);
+    solved_point<D, T>(W, u[i]);
   }
   if constexpr (Tab::NEW_AT_INPUT) {
     ros_input<Tab, D, T>(NS - 1, y, u, ynew);
@@ -320,6 +339,7 @@ __device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h, const 
 #pragma unroll
     for (int c = 0; c < D; ++c) rb[c] = ub[i][c];
     lu_solve_t<D, T, Mat>(W, piv, rb);
+    solved_point<D, T>(W, rb);
 #pragma unroll
     for (int c = 0; c < D; ++c) tb[c] = hinv * rb[c];
 #pragma unroll

@@ -72,9 +72,10 @@ ROS_TABLEAUX = {
 
 
 def _lu(D):
-    """LU with partial pivoting of a D x D matrix: for column k, D-k-1
-    multipliers (div) and (D-k-1)^2 fma updates."""
-    return sum(m * (1 + 2 * m) for m in range(1, D))
+    """LU with partial pivoting of a D x D matrix: a reciprocal per pivot;
+    for column k, D-k-1 multipliers (a product with it) and (D-k-1)^2 fma
+    updates."""
+    return D + sum(m * (1 + 2 * m) for m in range(1, D))
 
 
 def _ros_per_unit(method, system):
@@ -83,7 +84,7 @@ def _ros_per_unit(method, system):
     J, JV = JACOBIANS[system]
     S, SU = t["S"], t["SU"]
     a_nnz, c_nnz = t["a_nnz"], t["c_nnz"]
-    solve = 2 * D * D - D                       # L and U sweeps, D divisions
+    solve = 2 * D * D - D                       # L and U sweeps, D products by 1/U_kk
     factor = J + 2 + D + _lu(D)                 # jac, 1/(gamma h), diagonal, LU
 
     def stage_in(k):                            # inputs of the first k stages
@@ -167,9 +168,9 @@ def _ros_jvp_per_step(method, system):
     t = ROS_TABLEAUX[method]
     D = SYSTEMS[system][0]
     S, SU = t["S"], t["SU"]
-    lu = sum(6 * m + 6 * m * m for m in range(1, D))
+    lu = 6 * D + sum(4 * m + 6 * m * m for m in range(1, D))   # reciprocals, then products
     factor = JAC_DUAL[system] + 2 + 2 * D + lu
-    solve = 6 * D * D
+    solve = 6 * D * D - 2 * D
     stage_in = sum(2 * z for z in t["a_nnz"][:SU]) * D
     stage_rhs = sum(2 * w + 1 for w in t["c_nnz"][:SU] if w) * D
     update = 2 * (2 * t["a_nnz"][S - 1] * D if t["new_at_input"] else D)
