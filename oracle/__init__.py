@@ -54,6 +54,8 @@ def _load():
                                            C.POINTER(I)]
         lib.oracle_vjp.argtypes = [I, _d, _d, _d, _d, _d]
         lib.oracle_ros_trial.argtypes = [I, I, _d, _d, D, _d, _d]
+        lib.oracle_refresh.argtypes = [I, I, I, I, _d, _d, D, D, D, D, L, I, _d, L, _d, _i32,
+                                       D, L, _d, _i32, _i32, _i32, _d, _d, _i64, _i32]
         lib.oracle_record.argtypes = [I, I, I, I, _d, _d, D, D, D, D, D, L, I, _d, L,
                                       _d, _i32, _i32, _i32, _d, _d, _i64]
         lib.oracle_replay.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d, _d]
@@ -178,6 +180,33 @@ def record(system, method, y0, p, t0, t1, rtol, atol, save_t=None, h0=0.0,
         raise ValueError("oracle_record rejected its arguments")
     return dict(h=h, S=S, status=st, save_idx=sidx, save_dt=sdt, y_save=ys, n_trial=ntr,
                 save_t=save_t, system=system, method=method)
+
+
+def refresh(system, method, y0, p, t0, t1, rtol, atol, old, save_t=None, slack=1.0,
+            max_steps=100000, cap=None, params_shared=False):
+    """Refresh the old record's mesh (dict with h [n][cap], S [n]) at new
+    inputs: keep each lane's old steps while their error estimates stay <= slack,
+    then continue adaptively.  Returns a record dict plus drift_at (steps kept)."""
+    y0, p = _f64(y0), _f64(p)
+    n, d = y0.shape
+    fh = _f64(old["h"])
+    fS = np.ascontiguousarray(old["S"], np.int32)
+    save_t = np.array([t1] if save_t is None else save_t, dtype=np.float64)
+    ns = len(save_t)
+    if cap is None:
+        cap = 4096
+    h = np.zeros((n, cap)); S = np.zeros(n, np.int32); st = np.zeros(n, np.int32)
+    sidx = np.zeros((n, ns), np.int32); sdt = np.zeros((n, ns)); ys = np.zeros((n, ns, d))
+    ntr = np.zeros(n, np.int64); drift = np.zeros(n, np.int32)
+    rc = _load().oracle_refresh(system, method, n, int(params_shared), _p(y0), _p(p), t0, t1,
+                                rtol, atol, max_steps, ns, _p(save_t), fh.shape[1], _p(fh),
+                                _p(fS, _i32), float(slack), cap, _p(h), _p(S, _i32),
+                                _p(st, _i32), _p(sidx, _i32), _p(sdt), _p(ys), _p(ntr, _i64),
+                                _p(drift, _i32))
+    if rc != 0:
+        raise ValueError("oracle_refresh rejected its arguments")
+    return dict(h=h, S=S, status=st, save_idx=sidx, save_dt=sdt, y_save=ys, n_trial=ntr,
+                save_t=save_t, system=system, method=method, drift_at=drift)
 
 
 def _mesh(mesh):

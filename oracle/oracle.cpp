@@ -608,6 +608,15 @@ struct RecordArgs {
   double* save_dt;       // [n][n_save]  side-step size t_s - t_i(s)
   double* y_save;        // [n][n_save][d]
   int64_t* n_trial;      // [n] trials (accepted + rejected)
+  // Refresh of an old mesh (the mesh-drift policy): when follow_h is set,
+  // each lane first takes the steps of its old mesh, keeping each one whose
+  // error estimate at the new inputs is <= slack; at the first that fails
+  // the lane treats that trial as rejected and goes on adaptively from there.
+  const double* follow_h;   // [n][follow_cap] or null
+  const int32_t* follow_S;  // [n]
+  int64_t follow_cap;
+  double slack;
+  int32_t* drift_at;        // [n] or null: steps kept (= old S if none failed)
 };
 
 // Scaled RMS norm of v against the scales sc (paper, Section 2.1):
@@ -671,17 +680,25 @@ static void record_lane(const RecordArgs& A, int lane) {
   int64_t S = 0, trials = 0;
   int next_save = 0;
   bool prev_rejected = false;
+  const int64_t S_old = A.follow_h ? A.follow_S[lane] : 0;
+  bool following = S_old > 0;
+  int64_t kept = S_old;
 
   while (status == ST_OK && t < A.t1) {
     if (trials >= A.max_steps) { status = ST_MAX_STEPS; break; }
-    // a proposed step too small to advance t ends the lane
-    if (h < 16.0 * 2.220446049250313e-16 * std::fmax(std::fabs(t), 1.0)) {
-      status = ST_DT_UNDERFLOW;
-      break;
+    bool last = false;
+    if (following) {  // the old mesh's step, its last one ending at t1
+      h = A.follow_h[(int64_t)lane * A.follow_cap + S];
+      last = (S == S_old - 1);
+    } else {
+      // a proposed step too small to advance t ends the lane
+      if (h < 16.0 * 2.220446049250313e-16 * std::fmax(std::fabs(t), 1.0)) {
+        status = ST_DT_UNDERFLOW;
+        break;
+      }
+      if (t + h >= A.t1) { h = A.t1 - t; last = true; }
     }
     ++trials;
-    bool last = false;
-    if (t + h >= A.t1) { h = A.t1 - t; last = true; }
 
     double k[SMAX][DMAX], Y[SMAX][DMAX], ynew[DMAX];
     for (int c = 0; c < d; ++c) k[0][c] = k1[c];
@@ -708,8 +725,15 @@ static void record_lane(const RecordArgs& A, int lane) {
     // proposed factor 0.9 err^(-1/(q_emb+1)), bounded below by 0.2 and above
     // by 10 (1 right after a rejection); err = 0 gives the upper bound
     const double fac0 = 0.9 * root_inv(err, kroot);
+    if (following && !(err <= A.slack)) {  // the old mesh ends here: a rejected trial
+      following = false;
+      kept = S;
+      h = h * std::fmax(0.2, fac0);
+      prev_rejected = true;
+      continue;
+    }
 
-    if (err <= 1.0) {
+    if (following || err <= 1.0) {
       if (S >= A.cap) { status = ST_NOSPACE; break; }
       hrow[S] = h;
       double tnew = last ? A.t1 : t + h;
@@ -758,6 +782,7 @@ static void record_lane(const RecordArgs& A, int lane) {
   A.S_out[lane] = (int32_t)S;
   A.status_out[lane] = status;
   A.n_trial[lane] = trials;
+  if (A.drift_at) A.drift_at[lane] = (int32_t)kept;
 }
 
 // ----------------------------------------------------------------- replay --
@@ -1157,15 +1182,23 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
   int64_t S = 0, trials = 0;
   int next_save = 0;
   bool prev_rejected = false;
+  const int64_t S_old = A.follow_h ? A.follow_S[lane] : 0;
+  bool following = S_old > 0;
+  int64_t kept = S_old;
   while (status == ST_OK && t < A.t1) {
     if (trials >= A.max_steps) { status = ST_MAX_STEPS; break; }
-    if (h < 16.0 * 2.220446049250313e-16 * std::fmax(std::fabs(t), 1.0)) {
-      status = ST_DT_UNDERFLOW;
-      break;
+    bool last = false;
+    if (following) {
+      h = A.follow_h[(int64_t)lane * A.follow_cap + S];
+      last = (S == S_old - 1);
+    } else {
+      if (h < 16.0 * 2.220446049250313e-16 * std::fmax(std::fabs(t), 1.0)) {
+        status = ST_DT_UNDERFLOW;
+        break;
+      }
+      if (t + h >= A.t1) { h = A.t1 - t; last = true; }
     }
     ++trials;
-    bool last = false;
-    if (t + h >= A.t1) { h = A.t1 - t; last = true; }
     double ynew[DMAX], Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
     int perm[DMAX];
     ros_step(m, sys, d, y, p, h, ynew, Y, u, LU, perm);
@@ -1175,7 +1208,14 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
     ros_errvec(m, d, u, e);
     const double err = rms_norm(d, e, sc);
     const double fac0 = 0.9 * root_inv(err, kroot);
-    if (err <= 1.0) {
+    if (following && !(err <= A.slack)) {  // the old mesh ends here: a rejected trial
+      following = false;
+      kept = S;
+      h = h * std::fmax(0.2, fac0);
+      prev_rejected = true;
+      continue;
+    }
+    if (following || err <= 1.0) {
       if (S >= A.cap) { status = ST_NOSPACE; break; }
       hrow[S] = h;
       double tnew = last ? A.t1 : t + h;
@@ -1211,6 +1251,7 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
   A.S_out[lane] = (int32_t)S;
   A.status_out[lane] = status;
   A.n_trial[lane] = trials;
+  if (A.drift_at) A.drift_at[lane] = (int32_t)kept;
 }
 
 // Reverse sweep through one Rosenbrock step with output cotangent lam:
@@ -1384,6 +1425,33 @@ int oracle_record(int sys, int method, int n, int params_shared,
   RecordArgs A{sys, method, n, sys_dim(sys), sys_np(sys), params_shared,
                y0, p, t0, t1, rtol, atol, h0, max_steps, n_save, save_t, cap,
                h_out, S_out, status_out, save_idx, save_dt, y_save, n_trial};
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int l = 0; l < n; ++l) {
+    if (is_ros(method)) ros_record_lane(A, l);
+    else record_lane(A, l);
+  }
+  return 0;
+}
+
+// Refresh an old mesh at new inputs (the mesh-drift policy): every lane
+// keeps the steps of its old mesh (follow_h [n][follow_cap], follow_S [n])
+// while their error estimates stay <= slack, then goes on adaptively; the
+// output is a record like oracle_record's, plus drift_at [n] (steps kept).
+int oracle_refresh(int sys, int method, int n, int params_shared,
+                   const double* y0, const double* p, double t0, double t1,
+                   double rtol, double atol, int64_t max_steps,
+                   int n_save, const double* save_t, int64_t follow_cap,
+                   const double* follow_h, const int32_t* follow_S, double slack,
+                   int64_t cap, double* h_out, int32_t* S_out, int32_t* status_out,
+                   int32_t* save_idx, double* save_dt, double* y_save, int64_t* n_trial,
+                   int32_t* drift_at) {
+  if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method)) || n < 0 || n_save < 1 ||
+      n_save > 64 || !follow_h || !follow_S || follow_cap < 1)
+    return -1;
+  RecordArgs A{sys, method, n, sys_dim(sys), sys_np(sys), params_shared,
+               y0, p, t0, t1, rtol, atol, 0.0, max_steps, n_save, save_t, cap,
+               h_out, S_out, status_out, save_idx, save_dt, y_save, n_trial,
+               follow_h, follow_S, follow_cap, slack, drift_at};
 #pragma omp parallel for schedule(dynamic, 64)
   for (int l = 0; l < n; ++l) {
     if (is_ros(method)) ros_record_lane(A, l);
