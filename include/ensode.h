@@ -238,6 +238,26 @@ int ensemble_replay_mesh(const ens_problem* prob, const ens_ivp* ivp,
                          const int32_t* steps, int64_t cap, ens_record* out,
                          void* y_save, int32_t* lane_status, void* stream);
 
+/* Refresh an old mesh at new inputs: the mesh-drift policy, re-recording
+ * only what drifted (the paper's future work for long fits, Section 5).
+ * h [cap][n] and steps [n] (device) are an old mesh, as from
+ * ensemble_mesh_export; ivp carries the new y0 and parameters with the
+ * tolerances and save times.  Each trajectory takes its old steps while
+ * each one's error estimate at the new inputs (the record's scaled RMS norm)
+ * is <= slack; the first that fails counts as a rejected trial, and the
+ * trajectory goes on with the adaptive controller from there, as
+ * ensemble_record would.  A trajectory whose old steps all pass keeps its
+ * old mesh bit for bit; one with steps = 0 is recorded afresh.  Produces a
+ * record as ensemble_record does (same pool rules, lane_status, y_save);
+ * drift_at (device [n], nullable) receives the number of old steps kept
+ * (= steps[i] when none failed).  slack >= 0 (1 is the record's own test;
+ * larger keeps more old steps).  Tsit5, Vern7, Rodas4 and Rosenbrock23 on
+ * the built-in systems except the UDE; registered systems: ENS_EUNSUPPORTED. */
+int ensemble_refresh(const ens_problem* prob, const ens_ivp* ivp, const ens_tape_cfg* tape,
+                     const double* h, const int32_t* steps, int64_t cap, double slack,
+                     ens_record* out, void* y_save, int32_t* lane_status, int32_t* drift_at,
+                     void* stream);
+
 /* Export a record's mesh as the zero-padded rectangle h [cap][n] and S [n]
  * (device).  Trajectories with more than cap steps are truncated and their
  * S reports the full count. */

@@ -87,7 +87,8 @@ class ServerStats(C.Structure):
 JOB_WAITING, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, -1
 
 EXPORTS = ("ensemble_solve", "ensemble_record_bytes", "ensemble_record",
-           "ensemble_replay_mesh", "ensemble_mesh_export", "ensemble_adjoint",
+           "ensemble_replay_mesh", "ensemble_refresh", "ensemble_mesh_export",
+           "ensemble_adjoint",
            "ensemble_adjoint_workspace_bytes", "ensemble_jvp", "ensemble_system_register",
            "ensemble_record_stats",
            "ensemble_server_create", "ensemble_server_submit", "ensemble_server_progress",
@@ -115,6 +116,8 @@ def load(build_if_missing=True):
     lib.ensemble_record.argtypes = [P, V, C.POINTER(TapeCfg), C.POINTER(Record), Ptr, Ptr, Ptr]
     lib.ensemble_replay_mesh.argtypes = [P, V, C.POINTER(TapeCfg), Ptr, Ptr, C.c_int64,
                                          C.POINTER(Record), Ptr, Ptr, Ptr]
+    lib.ensemble_refresh.argtypes = [P, V, C.POINTER(TapeCfg), Ptr, Ptr, C.c_int64, C.c_double,
+                                     C.POINTER(Record), Ptr, Ptr, Ptr, Ptr]
     lib.ensemble_mesh_export.argtypes = [C.POINTER(Record), Ptr, Ptr, C.c_int64, Ptr]
     lib.ensemble_adjoint.argtypes = [P, V, C.POINTER(Record), C.POINTER(Loss), Ptr, Ptr, Ptr,
                                      Ptr, C.c_size_t, Ptr]

@@ -203,6 +203,46 @@ def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_time
     return RecordHandle(spec, pool, rec, y_save, status)
 
 
+def ensemble_refresh(system, method, y0, params, t0, t1, rtol, atol, h, steps, slack=1.0,
+                     save_times=None, h0=0.0, max_steps=0, params_shared=False, steps_hint=None,
+                     pool=None, steps_per_traj=None, ckpt_every=0):
+    """Refresh an old mesh h [cap, n] (float64), steps [n] (int32) at new
+    inputs: each trajectory keeps its old steps while their error estimates
+    stay <= slack, then records adaptively (the mesh-drift policy).
+    Returns (RecordHandle, drift_at [n] int32: old steps kept)."""
+    spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
+                 params_shared)
+    _require_gpu(h, steps)
+    if h.dtype != torch.float64 or steps.dtype != torch.int32:
+        raise ValueError("h must be float64 and steps int32")
+    if h.dim() != 2 or h.shape[1] != spec.n or steps.shape != (spec.n,):
+        raise ValueError("h must be [cap, n] and steps [n]")
+    cap = h.shape[0]
+    pool, tc = _pool_for(spec, steps_hint or cap, pool, steps_per_traj, ckpt_every)
+    rec = A.Record()
+    y_save = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
+    status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
+    drift = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
+    A.check(A.load().ensemble_refresh(C.byref(spec.prob), C.byref(spec.ivp), C.byref(tc),
+                                      _ptr(h), _ptr(steps), cap, float(slack), C.byref(rec),
+                                      _ptr(y_save), _ptr(status), _ptr(drift), _stream()))
+    return RecordHandle(spec, pool, rec, y_save, status), drift
+
+
+def refresh_record(handle, y0, params, slack=1.0, steps_hint=None):
+    """The mesh-drift policy on a record: its mesh refreshed at new y0 and
+    params with the record's own system, method, span, tolerances and save
+    times.  Returns (new RecordHandle, drift_at)."""
+    sp = handle.spec
+    h, S = ensemble_mesh_export(handle)
+    return ensemble_refresh(sp.system, sp.method, y0, params, sp.ivp.t0, sp.ivp.t1,
+                            sp.ivp.rtol, sp.ivp.atol, h, S, slack=slack,
+                            save_times=sp.save_times or None,
+                            max_steps=sp.ivp.max_steps,
+                            params_shared=bool(sp.prob.params_shared),
+                            steps_hint=steps_hint or max(int(h.shape[0]), 16))
+
+
 def ensemble_mesh_export(handle, cap=None):
     """The record's mesh as the zero-padded rectangle (h [cap, n], steps [n])."""
     n = handle.n

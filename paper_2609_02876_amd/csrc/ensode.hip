@@ -399,6 +399,10 @@ int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
       hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD, false>), g, b, 0, st, fa);
     else if (mode == MODE_RECORD)
       hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD, true>), g, b, 0, st, fa);
+    else if (mode == MODE_REFRESH && !ckpt)
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_REFRESH, false>), g, b, 0, st, fa);
+    else if (mode == MODE_REFRESH)
+      hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_REFRESH, true>), g, b, 0, st, fa);
     else if (!ckpt)
       hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_FROZEN, false>), g, b, 0, st, fa);
     else
@@ -424,7 +428,8 @@ int check_record_matches(const ens_problem* p, const ens_ivp* v,
 int record_common(const ens_problem* p, const ens_ivp* v,
                   const ens_tape_cfg* tc, int mode, const double* mesh_h,
                   const int32_t* mesh_S, int64_t cap, ens_record* out,
-                  void* y_save, int32_t* lane_status, void* stream) {
+                  void* y_save, int32_t* lane_status, void* stream, double slack = 1.0,
+                  int32_t* drift_at = nullptr) {
   SysInfo si;
   int rc;
   if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
@@ -461,6 +466,8 @@ int record_common(const ens_problem* p, const ens_ivp* v,
   fa.mesh_h = mesh_h;
   fa.mesh_S = mesh_S;
   fa.cap = cap;
+  fa.slack = slack;
+  fa.drift_at = drift_at;
   return launch_forward(p, mode, tc->ckpt_every > 0, fa, st);
 }
 
@@ -577,6 +584,20 @@ int ensemble_replay_mesh(const ens_problem* p, const ens_ivp* v,
   if (!h || !steps || cap < 1) return fail(ENS_EINVAL, "mesh h / steps / cap");
   return record_common(p, v, tc, MODE_FROZEN, h, steps, cap, out, y_save,
                        lane_status, stream);
+}
+
+int ensemble_refresh(const ens_problem* p, const ens_ivp* v, const ens_tape_cfg* tc,
+                     const double* h, const int32_t* steps, int64_t cap, double slack,
+                     ens_record* out, void* y_save, int32_t* lane_status, int32_t* drift_at,
+                     void* stream) {
+  if (!h || !steps || cap < 1) return fail(ENS_EINVAL, "mesh h / steps / cap");
+  if (!(slack >= 0.0)) return fail(ENS_EINVAL, "slack must be >= 0 (got %g)", slack);
+  if (p && p->system == ENS_SYS_LV_UDE)
+    return fail(ENS_EUNSUPPORTED, "refresh is not built for the UDE");
+  if (p && is_rtc(p->system))
+    return fail(ENS_EUNSUPPORTED, "refresh is not built for registered systems");
+  return record_common(p, v, tc, MODE_REFRESH, h, steps, cap, out, y_save, lane_status, stream,
+                       slack, drift_at);
 }
 
 int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,

@@ -25,7 +25,7 @@ namespace ens {
 
 constexpr double EPS64 = 2.220446049250313e-16;
 
-enum : int { MODE_SOLVE = 0, MODE_RECORD = 1, MODE_FROZEN = 2 };
+enum : int { MODE_SOLVE = 0, MODE_RECORD = 1, MODE_FROZEN = 2, MODE_REFRESH = 3 };
 
 // Save times travel by value in the kernel arguments (constant memory).
 struct SaveTimes {
@@ -54,9 +54,11 @@ struct FwdArgs {
   RecView rec;
   void* y_save;           // [n_save][D][n]
   int32_t* lane_status;   // [n]
-  const double* mesh_h;   // MODE_FROZEN: [cap][n]
-  const int32_t* mesh_S;  // MODE_FROZEN: [n]
+  const double* mesh_h;   // MODE_FROZEN, MODE_REFRESH: [cap][n]
+  const int32_t* mesh_S;  // MODE_FROZEN, MODE_REFRESH: [n]
   int64_t cap;
+  double slack;           // MODE_REFRESH: an old step is kept while err <= slack
+  int32_t* drift_at;      // MODE_REFRESH: [n] old steps kept, or null
 };
 
 struct AdjArgs {
@@ -492,6 +494,9 @@ __device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
 // ------------------------------------------------------- forward / record --
 // MODE_SOLVE: adaptive solve, no tape.  MODE_RECORD: adaptive solve writing
 // the tape.  MODE_FROZEN: steps taken from a given mesh, writing the tape.
+// MODE_REFRESH: the mesh-drift policy -- the given (old) mesh's steps are
+// taken while their error estimates stay <= slack; the first that fails is
+// a rejected trial, and the lane goes on adaptively from there.
 //
 // CKPT (checkpointed tape): a page covers R.page_steps accepted steps and
 // holds the state before its first step followed by the step sizes only.
@@ -537,17 +542,22 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
 
   double t = t0, h = 0.0;
   int32_t S_mesh = 0;
-  if constexpr (MODE == MODE_FROZEN) {
+  if constexpr (MODE == MODE_FROZEN || MODE == MODE_REFRESH) {
     S_mesh = a.mesh_S[tr];
     // a step count the rectangle cannot hold is refused for this lane
     if (S_mesh < 0 || (int64_t)S_mesh > a.cap) {
       S_mesh = 0;
       status = LANE_MAX_STEPS;
     }
-  } else if (status == LANE_OK) {
-    h = a.ivp.h0 > 0.0 ? fmin(a.ivp.h0, t1 - t0)
-                       : initial_step<Sys, Tab, T>(y, p, k1, t0, t1, rtol, atol);
   }
+  if constexpr (MODE != MODE_FROZEN) {
+    if (status == LANE_OK)
+      h = a.ivp.h0 > 0.0 ? fmin(a.ivp.h0, t1 - t0)
+                         : initial_step<Sys, Tab, T>(y, p, k1, t0, t1, rtol, atol);
+  }
+  // MODE_REFRESH: still on the old mesh; old steps kept so far
+  bool following = (MODE == MODE_REFRESH) && S_mesh > 0;
+  int32_t kept = S_mesh;
 
   // Side steps of the save times.  After a step is accepted whose interval
   // holds save times, the new state is held back (yn, kn at tn) and the
@@ -580,6 +590,26 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         hh = a.mesh_h[(int64_t)S * n + tr];
         last = (S == S_mesh - 1);
         ++trials;
+      } else if constexpr (MODE == MODE_REFRESH) {
+        if (trials >= a.ivp.max_steps) {
+          status = LANE_MAX_STEPS;
+          break;
+        }
+        if (following) {  // the old mesh's step, its last one ending at t1
+          h = a.mesh_h[(int64_t)S * n + tr];
+          last = (S == S_mesh - 1);
+        } else {
+          if (h < 16.0 * EPS64 * fmax(fabs(t), 1.0)) {
+            status = LANE_DT_UNDERFLOW;
+            break;
+          }
+          if (t + h >= t1) {
+            h = t1 - t;
+            last = true;
+          }
+        }
+        ++trials;
+        hh = h;
       } else {
         if (trials >= a.ivp.max_steps) {
           status = LANE_MAX_STEPS;
@@ -666,7 +696,16 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
     // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
     double fac0 = 0.0;
     if constexpr (MODE != MODE_FROZEN) fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
-    if (MODE == MODE_FROZEN || err <= 1.0) {
+    if constexpr (MODE == MODE_REFRESH) {
+      if (following && !(err <= a.slack)) {  // the old mesh ends here: a rejected trial
+        following = false;
+        kept = S;
+        h = hh * fmax(0.2, fac0);
+        prev_rej = true;
+        continue;
+      }
+    }
+    if (MODE == MODE_FROZEN || (MODE == MODE_REFRESH && following) || err <= 1.0) {
       if constexpr (MODE != MODE_SOLVE) {
         const bool need = (slot == 0);
         const bool over = need && (kpage >= R.static_pages);
@@ -771,6 +810,9 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
     R.status[tr] = status;
 #pragma unroll
     for (int c = 0; c < D; ++c) ((T*)R.y_final)[c * n + tr] = y[c];
+  }
+  if constexpr (MODE == MODE_REFRESH) {
+    if (a.drift_at) a.drift_at[tr] = kept;
   }
   if (a.lane_status) a.lane_status[tr] = status;
 }

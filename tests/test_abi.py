@@ -190,3 +190,22 @@ def test_ude_pool_plan_through_the_binding():
     assert 0 < ck < full
     assert B.plan_tape("ude", "tsit5", 4096, 0.0, 10.0, 256, 20, torch.float32,
                        budget_bytes=full - 1) == 64
+
+
+def test_refresh_rejects_bad_slack_and_the_ude():
+    """ensemble_refresh's argument checks run on the host, before any launch."""
+    lib = _lib()
+    rec = A.Record()
+    tc = A.TapeCfg(1 << 20, 1 << 20, 0, 0)
+    dummy = C.c_void_p(1 << 20)   # never dereferenced: the checks fail first
+    for slack in (-1.0, float("nan")):
+        rc = lib.ensemble_refresh(C.byref(_prob()), C.byref(_ivp()), C.byref(tc), dummy, dummy,
+                                  4, slack, C.byref(rec), dummy, None, None, None)
+        assert rc == A.ENS_EINVAL and b"slack" in lib.ensemble_last_error()
+    ude = _prob(system=A.SYS_LV_UDE, dtype=A.F32, dim=2, nparams=1218, params_shared=1)
+    rc = lib.ensemble_refresh(C.byref(ude), C.byref(_ivp()), C.byref(tc), dummy, dummy, 4, 1.0,
+                              C.byref(rec), dummy, None, None, None)
+    assert rc == A.ENS_EUNSUPPORTED
+    rc = lib.ensemble_refresh(C.byref(_prob()), C.byref(_ivp()), C.byref(tc), None, dummy, 4,
+                              1.0, C.byref(rec), dummy, None, None, None)
+    assert rc == A.ENS_EINVAL

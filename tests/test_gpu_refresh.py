@@ -1,0 +1,135 @@
+"""GPU parity of the mesh refresh (the mesh-drift policy) against the
+oracle's refresh, through the C ABI: the old mesh is the GPU's own record
+(equal to the oracle's), refreshed at perturbed parameters; meshes, steps
+kept, save states and the reverse sweep's gradients on the refreshed mesh
+are compared with the oracle's to the FP64 bar (bitwise expected)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2609_02876_amd import binding as B
+from paper_2609_02876_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SYS_O = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON, "hires": O.HIRES,
+         "linear": O.LINEAR}
+MET_O = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}
+TOL64 = 1e-11
+
+CASES = [
+    # system, method, t1, rtol, atol, n, relative parameter change
+    ("lorenz", "tsit5", 10.0, 1e-6, 1e-8, 700, 1e-3),
+    ("lorenz", "vern7", 3.0, 1e-8, 1e-10, 300, 1e-2),
+    ("vdp", "tsit5", 6.3, 1e-6, 1e-8, 257, 5e-2),
+    ("robertson", "rodas4", 1e5, 1e-6, 1e-10, 300, 5e-2),
+    ("robertson", "ros23", 1e4, 1e-5, 1e-9, 129, 5e-2),
+    ("hires", "rodas4", 321.8122, 1e-6, 1e-10, 200, 2e-2),
+]
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel(a, b):
+    num = np.linalg.norm((a - b).reshape(-1, a.shape[-1]), axis=0)
+    den = np.linalg.norm(b.reshape(-1, b.shape[-1]), axis=0)
+    return num / np.maximum(den, 1e-300)
+
+
+@pytest.mark.parametrize("system,method,t1,rtol,atol,n,dp", CASES)
+def test_refresh_matches_oracle(system, method, t1, rtol, atol, n, dp):
+    print(f"case refresh {system} {method} n={n} dp={dp}", flush=True)
+    y0, p = W.GENERATORS[system](n, seed=11)
+    st = list(W.save_times(0.0, t1, 20))
+    p2 = p * (1.0 + dp * np.random.default_rng(12).standard_normal(p.shape))
+    hint = 2048 if method == "ros23" else 1024
+    old = B.ensemble_record(system, method, _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
+                            save_times=st, steps_hint=hint)
+    h_old, S_old = B.ensemble_mesh_export(old)
+    new, drift = B.refresh_record(old, _dev(y0.T), _dev(p2.T), steps_hint=hint)
+    gp, gy, ll = B.ensemble_adjoint(new)
+    torch.cuda.synchronize()
+    assert np.all(old.status.cpu().numpy() == 0) and np.all(new.status.cpu().numpy() == 0)
+
+    mesh = dict(h=h_old.cpu().numpy().T.copy(), S=S_old.cpu().numpy())
+    ref = O.refresh(SYS_O[system], MET_O[method], y0, p2, 0.0, t1, rtol, atol, mesh,
+                    save_t=st, cap=8192)
+    gp_o, gy_o, ll_o = O.adjoint(SYS_O[system], MET_O[method], y0, p2, ref)
+    dr = drift.cpu().numpy()
+    print(f"  lanes that left the old mesh: {np.mean(dr < mesh['S']):.3f}")
+    assert np.array_equal(dr, ref["drift_at"])
+    S_new = new.steps().cpu().numpy()
+    assert np.array_equal(S_new, ref["S"])
+    hn, _ = B.ensemble_mesh_export(new, cap=int(S_new.max()))
+    hn = hn.cpu().numpy().T
+    assert np.array_equal(hn, ref["h"][:, :hn.shape[1]])
+    assert np.array_equal(new.n_trial().cpu().numpy(), ref["n_trial"])
+    ys = new.y_save.cpu().numpy()
+    ys_o = np.transpose(ref["y_save"], (1, 2, 0))
+    e = (_rel(ys, ys_o).max(), _rel(gp.cpu().numpy(), gp_o.T).max(),
+         _rel(gy.cpu().numpy(), gy_o.T).max())
+    print(f"  max rel err states {e[0]:.2e} grad_p {e[1]:.2e} grad_y0 {e[2]:.2e}")
+    assert max(e) <= TOL64
+    assert np.allclose(ll.cpu().numpy(), ll_o, rtol=1e-13, atol=0)
+
+
+def test_refresh_at_the_recorded_inputs_is_the_record_and_checkpoints_agree():
+    n, t1 = 500, 10.0
+    y0, p = W.lorenz(n, seed=13)
+    st = list(W.save_times(0.0, t1, 20))
+    print("case refresh lorenz unchanged inputs", flush=True)
+    old = B.ensemble_record("lorenz", "tsit5", _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-8,
+                            save_times=st, steps_hint=512)
+    same, drift = B.refresh_record(old, _dev(y0.T), _dev(p.T), steps_hint=512)
+    g_old = B.ensemble_adjoint(old)
+    g_same = B.ensemble_adjoint(same)
+    torch.cuda.synchronize()
+    assert torch.equal(drift, old.steps()) and torch.equal(same.steps(), old.steps())
+    assert torch.equal(same.n_trial(), old.steps())
+    assert torch.equal(same.y_save, old.y_save)
+    for a, b in zip(g_old, g_same):
+        assert torch.equal(a, b)
+    # a perturbed refresh into a checkpointed tape equals the full tape's
+    p2 = p * (1.0 + 1e-3 * np.random.default_rng(14).standard_normal(p.shape))
+    h, S = B.ensemble_mesh_export(old)
+    full, d1 = B.ensemble_refresh("lorenz", "tsit5", _dev(y0.T), _dev(p2.T), 0.0, t1, 1e-6, 1e-8,
+                                  h, S, save_times=st, steps_hint=512)
+    ck, d2 = B.ensemble_refresh("lorenz", "tsit5", _dev(y0.T), _dev(p2.T), 0.0, t1, 1e-6, 1e-8,
+                                h, S, save_times=st, steps_hint=512, ckpt_every=64)
+    ga, gb = B.ensemble_adjoint(full), B.ensemble_adjoint(ck)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2) and torch.equal(full.y_save, ck.y_save)
+    for a, b in zip(ga, gb):
+        assert torch.equal(a, b)
+
+
+def test_refresh_full_size_sampled():
+    """The 2^20 Lorenz record refreshed after a 1e-3 relative parameter step,
+    in the launch the bench times: 64 sampled trajectories against the
+    oracle's refresh of the same old meshes."""
+    cfg, y0, p, st = W.make("lorenz_2p20_t10")
+    n = cfg["n"]
+    print(f"case refresh lorenz n={n} sampled", flush=True)
+    p2 = p * (1.0 + 1e-3 * np.random.default_rng(15).standard_normal(p.shape))
+    old = B.ensemble_record("lorenz", "tsit5", _dev(y0.T), _dev(p.T), cfg["t0"], cfg["t1"],
+                            cfg["rtol"], cfg["atol"], save_times=list(st), steps_hint=352)
+    new, drift = B.refresh_record(old, _dev(y0.T), _dev(p2.T), steps_hint=352)
+    gp, gy, _ = B.ensemble_adjoint(new)
+    torch.cuda.synchronize()
+    assert np.all(new.status.cpu().numpy() == 0)
+    idx = np.sort(np.random.default_rng(16).choice(n, 64, replace=False))
+    h_old, S_old = B.ensemble_mesh_export(old)
+    mesh = dict(h=h_old.cpu().numpy()[:, idx].T.copy(), S=S_old.cpu().numpy()[idx])
+    ref = O.refresh(O.LORENZ, O.TSIT5, y0[idx], p2[idx], cfg["t0"], cfg["t1"], cfg["rtol"],
+                    cfg["atol"], mesh, save_t=list(st))
+    gp_o, gy_o, _ = O.adjoint(O.LORENZ, O.TSIT5, y0[idx], p2[idx], ref)
+    assert np.array_equal(drift.cpu().numpy()[idx], ref["drift_at"])
+    e = max(_rel(new.y_save.cpu().numpy()[..., idx], np.transpose(ref["y_save"], (1, 2, 0))).max(),
+            _rel(gp.cpu().numpy()[:, idx], gp_o.T).max(),
+            _rel(gy.cpu().numpy()[:, idx], gy_o.T).max())
+    frac = float((drift < S_old).float().mean())
+    print(f"  sampled max rel err {e:.2e}; lanes that left the old mesh {frac:.3f}")
+    assert e <= TOL64
