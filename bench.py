@@ -32,9 +32,12 @@ def parse():
     ap.add_argument("--registered", action="store_true",
                     help="run the workload's system as a copy registered at run time from source "
                          "(ensemble_system_register; Lorenz and Robertson)")
-    ap.add_argument("--mode", choices=("reverse", "forward"), default="reverse",
+    ap.add_argument("--mode", choices=("reverse", "forward", "refresh"), default="reverse",
                     help="gradient by the reverse sweep (default) or by forward-mode passes, "
-                         "one per parameter, on the recorded mesh")
+                         "one per parameter, on the recorded mesh; refresh: the mesh-drift "
+                         "policy (an old record refreshed at moved parameters, then the sweep)")
+    ap.add_argument("--refresh-step", type=float, default=1e-3,
+                    help="relative parameter change for --mode refresh (seeded normal)")
     ap.add_argument("--n", type=int, default=None, help="override the trajectory count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -205,6 +208,8 @@ def main():
         return serve_bench(args)
     if args.mode == "forward":
         return forward_bench(args)
+    if args.mode == "refresh":
+        return refresh_bench(args)
     cfg, y0, p, st = W.make(args.workload, n=args.n)
     n = cfg["n"]
     save = list(st) if cfg["n_save"] else None
@@ -375,6 +380,133 @@ def calibration_copy(mib, dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+
+def refresh_bench(args):
+    """The mesh-drift policy on one step of a fit: a record at the workload's
+    parameters (untimed), then at parameters moved by --refresh-step
+    (relative, seeded normal) the timed step refreshes the old mesh
+    (ensemble_refresh: old steps kept while they meet the tolerance, the rest
+    re-recorded) and runs the reverse sweep on it.  For context, the same
+    step with a fresh record and with the stale mesh replayed unchecked."""
+    import numpy as np
+    import torch
+
+    from paper_2609_02876_amd import binding as B
+    from paper_2609_02876_amd import flops
+    from paper_2609_02876_amd import workloads as W
+
+    cfg, y0, p, st = W.make(args.workload, n=args.n)
+    if cfg.get("shared") or cfg["system"] == "ude":
+        raise SystemExit("refresh is built for per-trajectory parameters (not the UDE)")
+    n = cfg["n"]
+    save = list(st) if cfg["n_save"] else None
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p2 = p * (1.0 + args.refresh_step * np.random.default_rng(17).standard_normal(p.shape))
+    y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=torch.float64, device=dev)
+    p_d = torch.tensor(np.ascontiguousarray(p.T), dtype=torch.float64, device=dev)
+    p2_d = torch.tensor(np.ascontiguousarray(p2.T), dtype=torch.float64, device=dev)
+    span = (cfg["t0"], cfg["t1"], cfg["rtol"], cfg["atol"])
+    m = min(n, 8192)
+    pilot = B.ensemble_record(cfg["system"], cfg["method"], y0_d[:, :m].contiguous(),
+                              p_d[:, :m].contiguous(), *span, save_times=save, steps_hint=4096)
+    hint = B.steps_hint_for(float(pilot.steps().double().mean().item()), margin=1.12)
+    del pilot
+    nbytes = B.ensemble_record_bytes(cfg["system"], cfg["method"], n, cfg["t0"], cfg["t1"],
+                                     hint, cfg["n_save"], torch.float64)
+    pools = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+    old = B.ensemble_record(cfg["system"], cfg["method"], y0_d, p_d, *span, save_times=save,
+                            pool=pools[0], steps_per_traj=hint)
+    h_old, S_old = B.ensemble_mesh_export(old)
+    stream = torch.cuda.current_stream()
+
+    def refresh_step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        rec, drift = B.ensemble_refresh(cfg["system"], cfg["method"], y0_d, p2_d, *span, h_old,
+                                        S_old, save_times=save, pool=pools[1],
+                                        steps_per_traj=hint)
+        if ev:
+            ev[1].record(stream)
+        g = B.ensemble_adjoint(rec)
+        if ev:
+            ev[2].record(stream)
+        return rec, drift, g
+
+    def other_step(kind, ev):
+        ev[0].record(stream)
+        if kind == "record":
+            rec = B.ensemble_record(cfg["system"], cfg["method"], y0_d, p2_d, *span,
+                                    save_times=save, pool=pools[1], steps_per_traj=hint)
+        else:
+            rec = B.ensemble_replay_mesh(cfg["system"], cfg["method"], y0_d, p2_d, cfg["t0"],
+                                         cfg["t1"], h_old, S_old, save_times=save,
+                                         pool=pools[1], steps_per_traj=hint)
+        ev[1].record(stream)
+        B.ensemble_adjoint(rec)
+        ev[2].record(stream)
+        return rec
+
+    for _ in range(args.warmup):
+        refresh_step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rec, drift, _ = refresh_step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if int((rec.status != 0).sum().item()):
+        raise RuntimeError("refreshed trajectories did not finish (status != OK)")
+    ref_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    stats = B.ensemble_record_stats(rec)
+    kept_all = float((drift == S_old).double().mean().item())
+    kept_steps = float(drift.double().sum().item()) / max(1.0, float(S_old.double().sum().item()))
+    ctx = {}
+    for kind in ("record", "stale_replay"):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(3)]
+        for e in ev:
+            other_step(kind, e)
+        torch.cuda.synchronize()
+        ctx[kind] = {"forward_ms": sum(e[0].elapsed_time(e[1]) for e in ev) / 3,
+                     "adjoint_ms": sum(e[1].elapsed_time(e[2]) for e in ev) / 3}
+    n_saves = n * (cfg["n_save"] or 1)
+    f_ref = flops.record_flops(cfg["method"], cfg["system"], stats["trials"],
+                               stats["steps_accepted"], stats["side_steps"])
+    f_adj = flops.adjoint_flops(cfg["method"], cfg["system"], stats["steps_accepted"],
+                                stats["side_steps"], n_saves - stats["side_steps"])
+    dominant = "adjoint" if adj_ms >= ref_ms else "refresh"
+    f_dom, ms_dom = (f_adj, adj_ms) if dominant == "adjoint" else (f_ref, ref_ms)
+    achieved = f_dom / (ms_dom * 1e-3) / 1e12
+    out = {
+        "metric": "trajectory-gradients/s (mesh refresh + adjoint)",
+        "value": n * args.steps / wall,
+        "unit": "trajectory-gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "system": cfg["system"], "method": cfg["method"],
+                   "n": n, "t_span": [cfg["t0"], cfg["t1"]], "rtol": cfg["rtol"],
+                   "atol": cfg["atol"], "n_save": cfg["n_save"],
+                   "parameter_step": args.refresh_step, "slack": 1.0},
+        "roofline": {"bound": "alu",
+                     "kernel": f"erk_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel "
+                               f"({cfg['system']}, {cfg['method']}, f64"
+                               f"{', refresh' if dominant == 'refresh' else ''})",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+        "kernels_ms": {"refresh": ref_ms, "adjoint": adj_ms},
+        "drift": {"trajectories_keeping_their_mesh": kept_all,
+                  "old_steps_kept": kept_steps,
+                  "trials_per_traj": stats["trials"] / n,
+                  "accepted_per_traj": stats["steps_accepted"] / n},
+        "context_same_step": {"fresh_record": ctx["record"],
+                              "stale_mesh_replay_unchecked": ctx["stale_replay"]},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def forward_bench(args):

@@ -558,6 +558,12 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   // MODE_REFRESH: still on the old mesh; old steps kept so far
   bool following = (MODE == MODE_REFRESH) && S_mesh > 0;
   int32_t kept = S_mesh;
+  // Given mesh: the size of the next mesh step is loaded one step ahead, so
+  // the load's latency is hidden behind a whole step's arithmetic.
+  double h_next = 0.0;
+  if constexpr (MODE == MODE_FROZEN || MODE == MODE_REFRESH) {
+    if (S_mesh > 0) h_next = a.mesh_h[tr];
+  }
 
   // Side steps of the save times.  After a step is accepted whose interval
   // holds save times, the new state is held back (yn, kn at tn) and the
@@ -587,8 +593,9 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
     bool last = false;
     if (!side) {
       if constexpr (MODE == MODE_FROZEN) {
-        hh = a.mesh_h[(int64_t)S * n + tr];
+        hh = h_next;
         last = (S == S_mesh - 1);
+        if (!last) h_next = a.mesh_h[(int64_t)(S + 1) * n + tr];
         ++trials;
       } else if constexpr (MODE == MODE_REFRESH) {
         if (trials >= a.ivp.max_steps) {
@@ -596,8 +603,9 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
           break;
         }
         if (following) {  // the old mesh's step, its last one ending at t1
-          h = a.mesh_h[(int64_t)S * n + tr];
+          h = h_next;
           last = (S == S_mesh - 1);
+          if (!last) h_next = a.mesh_h[(int64_t)(S + 1) * n + tr];
         } else {
           if (h < 16.0 * EPS64 * fmax(fabs(t), 1.0)) {
             status = LANE_DT_UNDERFLOW;
