@@ -133,3 +133,31 @@ def test_refresh_full_size_sampled():
     frac = float((drift < S_old).float().mean())
     print(f"  sampled max rel err {e:.2e}; lanes that left the old mesh {frac:.3f}")
     assert e <= TOL64
+
+
+def test_refresh_in_fp32_keeps_its_prefix_and_is_idempotent():
+    """FP32 (states and stages; h, the error norm and the controller in FP64):
+    at the recorded inputs the refresh is the record; after a parameter step
+    the kept prefix is the old mesh, and a second refresh keeps everything."""
+    n, t1 = 700, 6.3
+    y0, p = W.vdp(n, seed=17)
+    st = list(W.save_times(0.0, t1, 20))
+    f32 = torch.float32
+    print("case refresh vdp tsit5 fp32", flush=True)
+    old = B.ensemble_record("vdp", "tsit5", _dev(y0.T, f32), _dev(p.T, f32), 0.0, t1, 1e-5,
+                            1e-7, save_times=st, steps_hint=512)
+    same, d0 = B.refresh_record(old, _dev(y0.T, f32), _dev(p.T, f32), steps_hint=512)
+    p2 = p * (1.0 + 0.05 * np.random.default_rng(18).standard_normal(p.shape))
+    r1, d1 = B.refresh_record(old, _dev(y0.T, f32), _dev(p2.T, f32), steps_hint=512)
+    r2, d2 = B.refresh_record(r1, _dev(y0.T, f32), _dev(p2.T, f32), steps_hint=512)
+    torch.cuda.synchronize()
+    assert torch.equal(d0, old.steps()) and torch.equal(same.y_save, old.y_save)
+    assert np.all(r1.status.cpu().numpy() == 0)
+    k = d1.cpu().numpy()
+    assert np.any(k < old.steps().cpu().numpy())
+    h_old, _ = B.ensemble_mesh_export(old)
+    h1, _ = B.ensemble_mesh_export(r1)
+    h_old, h1 = h_old.cpu().numpy(), h1.cpu().numpy()
+    for l in range(n):
+        assert np.array_equal(h1[:k[l], l], h_old[:k[l], l])
+    assert torch.equal(d2, r1.steps()) and torch.equal(r2.y_save, r1.y_save)
