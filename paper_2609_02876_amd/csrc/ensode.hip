@@ -393,6 +393,17 @@ int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
     using Tab = decltype(m);
     using T = decltype(t);
     const dim3 g(grid_of(fa.ivp.n)), b(BLOCK);
+    if constexpr (!Tab::ROS) {
+      if (mode == MODE_RECORD && !ckpt) {
+        // the explicit pairs' full-tape record forms its save states afterwards
+        hipLaunchKernelGGL((erk_record_deferred_kernel<Sys, Tab, T>), g, b, 0, st, fa);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "record launch");
+        hipLaunchKernelGGL((erk_saves_kernel<Sys, Tab, T>), g, b, 0, st, fa);
+        e = hipGetLastError();
+        return e == hipSuccess ? ENS_OK : hip_fail(e, "save-state launch");
+      }
+    }
     if (mode == MODE_SOLVE)
       hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_SOLVE, false>), g, b, 0, st, fa);
     else if (mode == MODE_RECORD && !ckpt)

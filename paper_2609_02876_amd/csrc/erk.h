@@ -500,8 +500,17 @@ __device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
 //
 // CKPT (checkpointed tape): a page covers R.page_steps accepted steps and
 // holds the state before its first step followed by the step sizes only.
-template <class Sys, class Tab, class T, int MODE, bool CKPT>
+//
+// DEFER (MODE_RECORD with the full tape): the loop takes no save-time side
+// steps.  It notes, for each save time inside an accepted step, the step's
+// index and the offset from its start, and erk_saves_kernel then forms the
+// save states from the taped base states, all (trajectory, save) pairs in
+// parallel with the same step map: the same values, and a loop with fewer
+// iterations and less state.
+template <class Sys, class Tab, class T, int MODE, bool CKPT, bool DEFER = false>
 __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block) {
+  static_assert(!DEFER || (MODE == MODE_RECORD && !CKPT),
+                "save steps are deferred only from a full-tape record");
   constexpr int D = Sys::D, NP = Sys::NP;
   constexpr int RB = TapeRec<T, D>::BYTES;
   constexpr int YB = StateBytes<T, D>::BYTES;
@@ -764,21 +773,40 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         h = hh * fmax(0.2, fmin(prev_rej ? 1.0 : 10.0, fac0));
         prev_rej = false;
       }
-      side = ts < tnew;
-      if (side) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          yn[c] = ynew[c];
-          if constexpr (Tab::FSAL) kn[c] = klast[c];
+      if constexpr (DEFER) {
+        // saves inside this step: base index S - 1 and offset from its start
+        while (ts < tnew) {
+          *sidx_out = S - 1;
+          *sdt_out = ts - t;
+          sidx_out += n;
+          sdt_out += n;
+          ys_out += ys_stride;
+          ++next_save;
+          ts = s_times[next_save];
         }
-        tn = tnew;
-      } else {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
           y[c] = ynew[c];
           if constexpr (Tab::FSAL) k1[c] = klast[c];
         }
         t = tnew;
+      } else {
+        side = ts < tnew;
+        if (side) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            yn[c] = ynew[c];
+            if constexpr (Tab::FSAL) kn[c] = klast[c];
+          }
+          tn = tnew;
+        } else {
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            y[c] = ynew[c];
+            if constexpr (Tab::FSAL) k1[c] = klast[c];
+          }
+          t = tnew;
+        }
       }
     } else {
       h = hh * fmax(0.2, fac0);
@@ -1160,6 +1188,71 @@ template <class Sys, class Tab, class T, int MODE, bool CKPT>
 __global__ void __launch_bounds__(256, (FwdBlocks<Sys, Tab, T>::value))
     erk_forward_kernel(const FwdArgs a) {
   erk_forward_body<Sys, Tab, T, MODE, CKPT>(a, blockIdx.x);
+}
+
+// Full-tape record whose save states are formed afterwards by
+// erk_saves_kernel (explicit pairs).  Without the side steps' state the FP64
+// Lorenz / Tsit5 record needs 118 VGPRs at four blocks per CU.  Five fit
+// (96 VGPRs, one spill on the overflow-page path) but ran no faster: 2^20
+// trajectories are 16 waves per SIMD, four full rounds at four blocks and a
+// lone last round at five.
+template <class Sys, class Tab, class T>
+struct DeferBlocks {
+  static constexpr int value =
+      (Sys::ID == 1 && Tab::ORDER == 5 && !Tab::ROS && sizeof(T) == 8) ? 4 : 1;
+};
+
+template <class Sys, class Tab, class T>
+__global__ void __launch_bounds__(256, (DeferBlocks<Sys, Tab, T>::value))
+    erk_record_deferred_kernel(const FwdArgs a) {
+  erk_forward_body<Sys, Tab, T, MODE_RECORD, false, true>(a, blockIdx.x);
+}
+
+// Save states of a deferred record: for each trajectory and each save time
+// noted inside an accepted step (base index i < S), the step map from the
+// taped state y_i over the noted offset, Phi(y_i; t_s - t_i) -- the side
+// step of the paper's extra-step save (Section 3.4), formed as the reverse
+// sweep forms it.  Saves at or after the last mesh point were written by
+// the record itself.
+template <class Sys, class Tab, class T>
+__global__ void __launch_bounds__(256) erk_saves_kernel(const FwdArgs a) {
+  constexpr int D = Sys::D, NP = Sys::NP, SU = Tab::SU;
+  constexpr int RB = TapeRec<T, D>::BYTES;
+  static_assert(!Tab::ROS, "explicit pairs only");
+  const int64_t n = a.ivp.n;
+  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tr >= n) return;
+  const RecView& R = a.rec;
+  const int32_t S = R.steps[tr];
+  const int K = R.page_steps;
+  T p[NP];
+  load_params<T, NP>(a.ivp, tr, p);
+  T* ysv = (T*)a.y_save;
+  int32_t page = -1, pidx = -1;  // the page last walked to and its index
+  for (int s = 0; s < a.ivp.n_save; ++s) {
+    const int32_t i = R.save_idx[(int64_t)s * n + tr];
+    if (i < 0 || i >= S) continue;
+    const double dt = R.save_dt[(int64_t)s * n + tr];
+    const int32_t pi = i / K;
+    if (pi < R.static_pages) {
+      page = (int32_t)(tr * R.static_pages + pi);
+      pidx = pi;
+    } else {
+      if (pidx < R.static_pages || pidx > pi) {
+        page = R.first_page[tr];
+        pidx = R.static_pages;
+      }
+      for (; pidx < pi; ++pidx) page = next_page(R, tr, page);
+    }
+    T y[D], k0[D], Yd[SU][D], ylast[D], klast[D], ys[D];
+    double hdummy;
+    load_rec<T, D>(R.pages + (int64_t)page * R.page_bytes + (i % K) * RB, hdummy, y);
+    Sys::rhs(y, p, k0);
+    step_push<Sys, Tab, T, SU, true, true, false>(y, k0, p, T(dt), Yd, ylast, klast, ys,
+                                                  nullptr);
+#pragma unroll
+    for (int c = 0; c < D; ++c) ysv[((int64_t)s * D + c) * n + tr] = ys[c];
+  }
 }
 
 // Blocks per CU the compiler is asked to fit in the reverse sweep: 3 for the
