@@ -913,19 +913,13 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
   }
   loss = L.scale * loss;
 
-  // Parameter terms: the mesh steps' accumulate in gp from the last step
-  // down, the save steps' in gside from the last save down, and the two
-  // sums are added at the end (the order of the sum over steps is not fixed
-  // by the method; this one is reproducible in every sweep layout).
-  std::vector<double> gside(M.np, 0.0);
   double lam[DMAX];
   for (int c = 0; c < d; ++c) lam[c] = 0.0;
   int s = M.n_save - 1;
   for (int i = S; i >= 0; --i) {
     while (s >= 0 && sidx[s] == i) {
       double li[DMAX];
-      step_vjp_any(M.method, M.sys, d, &ys[(size_t)i * d], p, sdt[s], &wbar[s * d], li,
-                   gside.data());
+      step_vjp_any(M.method, M.sys, d, &ys[(size_t)i * d], p, sdt[s], &wbar[s * d], li, gp);
       for (int c = 0; c < d; ++c) lam[c] = lam[c] + li[c];
       --s;
     }
@@ -934,7 +928,6 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
     step_vjp_any(M.method, M.sys, d, &ys[(size_t)(i - 1) * d], p, hrow[i - 1], lam, li, gp);
     for (int c = 0; c < d; ++c) lam[c] = li[c];
   }
-  for (int k = 0; k < M.np; ++k) gp[k] = gp[k] + gside[k];
   for (int c = 0; c < d; ++c) gy0[c] = lam[c];
   return loss;
 }
