@@ -243,3 +243,30 @@ def test_small_and_ragged_sizes(n):
     assert _rel(hf.y_save.cpu().numpy(), np.transpose(ref["y_save"], (1, 2, 0))).max() <= TOL64
     assert _rel(gp.cpu().numpy(), gp_o.T).max() <= TOL64
     assert _rel(gy.cpu().numpy(), gy_o.T).max() <= TOL64
+
+
+@pytest.mark.parametrize("method", ["tsit5", "vern7"])
+def test_save_states_from_overflow_pages(method):
+    """Most taped steps in overflow pages (two reserved pages per trajectory):
+    the save states the separate save kernel forms from bases reached through
+    the page links, and the sweep's gradients, against the oracle."""
+    n, t1 = 300, 10.0
+    y0, p = W.lorenz(n, seed=21)
+    st = list(W.save_times(0.0, t1, 20))
+    print(f"case overflow pages lorenz {method} n={n}", flush=True)
+    ref = O.record(O.LORENZ, MET_O[method], y0, p, 0.0, t1, 1e-6, 1e-8, save_t=st)
+    gp_o, gy_o, _ = O.adjoint(O.LORENZ, MET_O[method], y0, p, ref)
+    nbytes = B.ensemble_record_bytes("lorenz", method, n, 0.0, t1, 3 * int(ref["S"].max()), 20)
+    pool = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    hd = _gpu_record("lorenz", method, y0, p, t1, 1e-6, 1e-8, st, pool=pool, steps_per_traj=32)
+    gp, gy, _ = B.ensemble_adjoint(hd)
+    stats = B.ensemble_record_stats(hd)
+    torch.cuda.synchronize()
+    assert np.all(hd.status.cpu().numpy() == 0)
+    assert stats["overflow_pages_used"] > 4 * n   # most pages are overflow pages
+    ys = hd.y_save.cpu().numpy()
+    ys_o = np.transpose(ref["y_save"], (1, 2, 0))
+    e = (_rel(ys, ys_o).max(), _rel(gp.cpu().numpy(), gp_o.T).max(),
+         _rel(gy.cpu().numpy(), gy_o.T).max())
+    print(f"  overflow pages {stats['overflow_pages_used']}; max rel err {e}")
+    assert max(e) <= TOL64
