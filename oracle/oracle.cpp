@@ -913,14 +913,22 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
   }
   loss = L.scale * loss;
 
+  // The save steps first, from the last save to the first: each one's
+  // cotangent for its base state (lsave) and its parameter terms (into gp);
+  // then the mesh steps from the last, each base state's cotangent taking
+  // the saves based there as the sweep reaches it (the order of the sum over
+  // steps in gp is not fixed by the method; this one every sweep layout on
+  // the device reproduces).
+  std::vector<double> lsave((size_t)M.n_save * d);
+  for (int s2 = M.n_save - 1; s2 >= 0; --s2)
+    step_vjp_any(M.method, M.sys, d, &ys[(size_t)sidx[s2] * d], p, sdt[s2], &wbar[s2 * d],
+                 &lsave[(size_t)s2 * d], gp);
   double lam[DMAX];
   for (int c = 0; c < d; ++c) lam[c] = 0.0;
   int s = M.n_save - 1;
   for (int i = S; i >= 0; --i) {
     while (s >= 0 && sidx[s] == i) {
-      double li[DMAX];
-      step_vjp_any(M.method, M.sys, d, &ys[(size_t)i * d], p, sdt[s], &wbar[s * d], li, gp);
-      for (int c = 0; c < d; ++c) lam[c] = lam[c] + li[c];
+      for (int c = 0; c < d; ++c) lam[c] = lam[c] + lsave[(size_t)s * d + c];
       --s;
     }
     if (i == 0) break;
