@@ -180,6 +180,8 @@ typedef struct {
   int32_t* links;       /* [overflow pages][2] previous / next page */
   unsigned long long* counters; /* [8] page counter and step totals */
   void* pages;          /* [n_pages][page_bytes] */
+  void* save_base;      /* [n_save][dim][n] state each save's side step starts from
+                           (the record writes it; the reverse sweep reads it) */
 } ens_record;
 
 typedef struct {
@@ -270,11 +272,13 @@ int ensemble_mesh_export(const ens_record* rec, double* h, int32_t* steps,
  * Trajectories whose record status is not ENS_LANE_OK get NaN per-trajectory
  * gradients and loss; with shared parameters they contribute nothing to the
  * sum.  Shared parameters (problem.params_shared) give grad_params [P],
- * summed over trajectories in a fixed order (run-to-run identical).  Shared
- * parameters and a checkpointed tape need a caller-owned, 256-byte aligned
- * device workspace of at least ensemble_adjoint_workspace_bytes bytes, not
- * used by a concurrent call (otherwise workspace may be NULL; a missing, too
- * small or misaligned workspace is ENS_EINVAL).  The ivp must describe the same ensemble as the record. */
+ * summed over trajectories in a fixed order (run-to-run identical).  The
+ * sweep needs a caller-owned, 256-byte aligned device workspace of at least
+ * ensemble_adjoint_workspace_bytes bytes, not used by a concurrent call (NULL
+ * only where that size is 0; a missing, too small or misaligned workspace is
+ * ENS_EINVAL).  The sweep takes the save steps first, then the mesh steps from
+ * the last; that order fixes the rounding of the parameter gradient.  The ivp
+ * must describe the same ensemble as the record. */
 int ensemble_adjoint(const ens_problem* prob, const ens_ivp* ivp,
                      const ens_record* rec, const ens_loss* loss,
                      void* grad_params, void* grad_y0, double* loss_out,
@@ -331,8 +335,9 @@ int ensemble_system_register(const char* source, int dim, int nparams, int has_j
                              int* system);
 
 /* Workspace ensemble_adjoint needs for this record: per-block partial sums
- * for shared parameters, plus one segment of step records per trajectory for
- * a checkpointed tape (0 for a full tape with per-trajectory parameters). */
+ * for shared parameters, one segment of step records per trajectory for a
+ * checkpointed tape, and each save's cotangent for the state its side step
+ * starts from ([n_save][dim][n] elements; not for the UDE). */
 int ensemble_adjoint_workspace_bytes(const ens_record* rec, size_t* bytes);
 
 /* Totals of a finished record (synchronizes the stream). */

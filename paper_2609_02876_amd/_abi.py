@@ -56,7 +56,8 @@ class Record(C.Structure):
                 ("steps", C.c_void_p), ("n_trial", C.c_void_p), ("first_page", C.c_void_p),
                 ("last_page", C.c_void_p), ("status", C.c_void_p), ("save_idx", C.c_void_p),
                 ("save_dt", C.c_void_p), ("save_times", C.c_void_p), ("y_final", C.c_void_p),
-                ("links", C.c_void_p), ("counters", C.c_void_p), ("pages", C.c_void_p)]
+                ("links", C.c_void_p), ("counters", C.c_void_p), ("pages", C.c_void_p),
+                ("save_base", C.c_void_p)]
 
 
 class Stats(C.Structure):

@@ -112,6 +112,7 @@ struct RecView {
   double* save_dt;       // [n_save][n]
   const double* save_times;
   void* y_final;         // [D][n]
+  void* save_base;       // [n_save][D][n] base state of each save's side step
   int32_t* links;        // [overflow pages][2]: previous, next page id
   unsigned long long* counters;
   char* pages;

@@ -154,7 +154,7 @@ int check_ivp(const ens_ivp* v, bool need_ptrs) {
 // Pool layout of a record.
 struct Layout {
   size_t counters, save_times, steps, n_trial, first_page, last_page, status,
-      save_idx, save_dt, y_final, links, pages;
+      save_idx, save_dt, y_final, save_base, links, pages;
   size_t fixed;  // bytes before the links array
   size_t page_bytes;
 };
@@ -187,6 +187,7 @@ Layout layout(int64_t n, int n_save_eff, int d, int dtype, int ckpt_every) {
   L.save_idx = take((size_t)n_save_eff * n * 4);
   L.save_dt = take((size_t)n_save_eff * n * 8);
   L.y_final = take((size_t)d * n * elem_size(dtype));
+  L.save_base = take((size_t)n_save_eff * d * n * elem_size(dtype));
   L.fixed = off;
   L.links = off;
   L.page_bytes = ckpt_every > 0
@@ -252,6 +253,7 @@ void fill_record(ens_record* r, const ens_problem* p, const ens_ivp* v,
   r->save_idx = (int32_t*)(base + L.save_idx);
   r->save_dt = (double*)(base + L.save_dt);
   r->y_final = base + L.y_final;
+  r->save_base = base + L.save_base;
   r->links = (int32_t*)(base + L.links);
   r->pages = base + align256(L.links + (size_t)ps.n_over * 8);
 }
@@ -274,6 +276,7 @@ RecView view_of(const ens_record* r) {
   v.save_dt = r->save_dt;
   v.save_times = r->save_times;
   v.y_final = r->y_final;
+  v.save_base = r->save_base;
   v.links = r->links;
   v.counters = r->counters;
   v.pages = (char*)r->pages;
@@ -636,13 +639,20 @@ int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,
   return e == hipSuccess ? ENS_OK : hip_fail(e, "export launch");
 }
 
+// Sweep prologue output: each save's cotangent carried back to its base
+// state, [n_save][dim][n].
+size_t contrib_bytes(const ens_record* r) {
+  return align256((size_t)r->n_save * r->dim * r->n * elem_size(r->dtype));
+}
+
 int ensemble_adjoint_workspace_bytes(const ens_record* r, size_t* bytes) {
   if (!r || !bytes) return fail(ENS_EINVAL, "bad arguments");
   SysInfo si;
   if (!sys_info(r->system, &si)) return fail(ENS_EINVAL, "record of unknown system");
   size_t b = 0;
   if (r->params_shared) b = partials_bytes(r->system, r->n, si.np, r->dtype);
-  if (r->ckpt_every > 0) b += (size_t)r->n * r->page_steps * rec_bytes(r->dtype, r->dim);
+  if (r->ckpt_every > 0) b += align256((size_t)r->n * r->page_steps * rec_bytes(r->dtype, r->dim));
+  if (r->system != ENS_SYS_LV_UDE) b += contrib_bytes(r);
   *bytes = b;
   return ENS_OK;
 }
@@ -681,9 +691,13 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
   aa.workspace = workspace;
   const bool shared = p->params_shared != 0;
   const bool ckpt = r->ckpt_every > 0;
-  aa.scratch = ckpt ? (char*)workspace +
-                          (shared ? partials_bytes(p->system, v->n, si.np, p->dtype) : 0)
-                    : nullptr;
+  {
+    char* w = (char*)workspace;
+    if (shared) w += partials_bytes(p->system, v->n, si.np, p->dtype);
+    aa.scratch = ckpt ? w : nullptr;
+    if (ckpt) w += align256((size_t)r->n * r->page_steps * rec_bytes(r->dtype, r->dim));
+    aa.contrib = p->system != ENS_SYS_LV_UDE ? w : nullptr;
+  }
   hipStream_t st = (hipStream_t)stream;
   if (p->system == ENS_SYS_LV_UDE) {
     const dim3 g(grid_of(v->n)), b(64 * UDE_ADJ_WAVES);

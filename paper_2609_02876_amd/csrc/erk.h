@@ -72,6 +72,7 @@ struct AdjArgs {
   double* loss_out;       // [n] or null
   void* workspace;        // shared parameters: [n_blocks][NP] partials
   void* scratch;          // checkpointed tape: [n][page_steps] step records
+  void* contrib;          // [n_save][D][n]: each save's cotangent carried to its base state
 };
 
 // ------------------------------------------------------------ one step --
@@ -585,6 +586,14 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   int next_save = 0;
   // running pointers to this lane's next save-state slots
   T* ys_out = ysv + tr;
+  // the base state of the save at ys_out, into the record's save_base
+  auto put_base = [&](const T* yb, bool valid) {
+    if constexpr (MODE != MODE_SOLVE) {
+      T* sb = (T*)R.save_base + (ys_out - ysv);
+#pragma unroll
+      for (int c = 0; c < D; ++c) sb[c * n] = valid ? yb[c] : T(NAN);
+    }
+  };
   int32_t* sidx_out = R.save_idx + tr;
   double* sdt_out = R.save_dt + tr;
   const int64_t ys_stride = (int64_t)D * n;
@@ -689,6 +698,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
     if (side) {
 #pragma unroll
       for (int c = 0; c < D; ++c) ys_out[c * n] = ynew[c];
+      put_base(y, true);
       ys_out += ys_stride;
       if constexpr (MODE != MODE_SOLVE) {
         *sidx_out = S - 1;
@@ -780,6 +790,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
           *sdt_out = ts - t;
           sidx_out += n;
           sdt_out += n;
+          put_base(y, true);
           ys_out += ys_stride;
           ++next_save;
           ts = s_times[next_save];
@@ -831,6 +842,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   for (; next_save < ns; ++next_save) {
 #pragma unroll
     for (int c = 0; c < D; ++c) ys_out[c * n] = ok ? y[c] : T(NAN);
+    put_base(y, ok);
     ys_out += ys_stride;
     if constexpr (MODE != MODE_SOLVE) {
       *sidx_out = ok ? S : -1;
@@ -877,6 +889,121 @@ __device__ __forceinline__ void save_cotangent(const AdjArgs& a, int s,
   } else {
 #pragma unroll
     for (int c = 0; c < D; ++c) w[c] = data[((int64_t)s * D + c) * n + tr];
+  }
+}
+
+// Reverse of one explicit step from stage states Y (recomputed by
+// step_push) with output cotangent w: lin = d(y_new)/dy^T w and
+// g += d(y_new)/dp^T w, stage by stage from the last:
+//   kbar_j = h (b_j w + sum_{l>j} a_lj Ybar_l),  Ybar_j = f_y(Y_j)^T kbar_j,
+//   g += f_p(Y_j)^T kbar_j,  lin = w + sum_j Ybar_j.
+template <class Sys, class Tab, class T>
+__device__ __forceinline__ void erk_step_vjp(const T (&Y)[Tab::SU][Sys::D], const T* p,
+                                             double hh, const T* w, T* lin, T* g) {
+  constexpr int D = Sys::D, SU = Tab::SU;
+  T Yb[SU][D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) lin[c] = w[c];
+#pragma unroll
+  for (int j = SU - 1; j >= 0; --j) {
+    T kb[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T acc = T(0);
+      bool first = true;
+      if (Tab::B[j] != 0.0) {
+        acc = T(Tab::B[j]) * w[c];
+        first = false;
+      }
+#pragma unroll
+      for (int l = j + 1; l < SU; ++l) {
+        if (Tab::A[l][j] != 0.0) {
+          if (first) {
+            acc = T(Tab::A[l][j]) * Yb[l][c];
+            first = false;
+          } else {
+            acc = fmaT(T(Tab::A[l][j]), Yb[l][c], acc);
+          }
+        }
+      }
+      kb[c] = T(hh) * acc;
+    }
+    Sys::vjp(Y[j], p, kb, Yb[j], g);
+#pragma unroll
+    for (int c = 0; c < D; ++c) lin[c] = lin[c] + Yb[j][c];
+  }
+}
+
+// A save step of size hh != 0 from its base state yb: recompute it, form
+// the save's cotangent from the state it reaches (cot(ys, w)), and reverse
+// it: lin = d(ys)/dyb^T w, g += d(ys)/dp^T w.  Rosenbrock factors of d >= 6
+// go through the lane's LDS slots sW, as in the sweep's loop.
+template <class Sys, class Tab, class T, bool W_LDS, class Cot>
+__device__ __forceinline__ void save_step_reverse(const T* yb, const T* p, double hh, T* sW,
+                                                  Cot&& cot, T* lin, T* g) {
+  constexpr int D = Sys::D;
+  T ys[D], w[D];
+  if constexpr (Tab::ROS) {
+    T u[Tab::S][D];
+    int piv[D];
+    if constexpr (W_LDS) {
+      ros_step_lds<Sys, Tab, T, Tab::SU>(yb, p, T(hh), LdsMat<T>{sW}, piv, u, ys);
+    } else {
+      T W[D * D];
+      ros_step<Sys, Tab, T, Tab::SU>(yb, p, T(hh), W, piv, u, ys);
+      cot(ys, w);
+      ros_step_vjp<Sys, Tab, T, T[D * D]>(yb, p, T(hh), W, piv, u, w, lin, g);
+      return;
+    }
+    cot(ys, w);
+    T ybo[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      ybo[c] = yb[c];
+      opaque(ybo[c]);
+#pragma unroll
+      for (int q = 0; q < Tab::SU; ++q) opaque(u[q][c]);
+    }
+    ros_step_vjp<Sys, Tab, T, LdsMat<T>>(ybo, p, T(hh), LdsMat<T>{sW}, piv, u, w, lin, g);
+  } else {
+    T k0[D], Y[Tab::SU][D], ylast[D], klast[D];
+    Sys::rhs(yb, p, k0);
+    step_push<Sys, Tab, T, Tab::SU, true, true, false>(yb, k0, p, T(hh), Y, ylast, klast, ys,
+                                                       nullptr);
+    cot(ys, w);
+    erk_step_vjp<Sys, Tab, T>(Y, p, hh, w, lin, g);
+  }
+}
+
+// The save steps of one trajectory's reverse sweep, from the last save to
+// the first: each save's cotangent (from the state its side step reaches, or
+// from its base state for a save on a mesh point), its loss term and the
+// reverse of its side step from the recorded base state, with the parameter
+// terms added into g.  The cotangent each save gives its base state goes to
+// a.contrib.
+template <class Sys, class Tab, class T, bool W_LDS>
+__device__ __forceinline__ void save_steps_reverse(const AdjArgs& a, int64_t tr, const T* p,
+                                                   T two_scale, T* sW, T* g, double& loss) {
+  constexpr int D = Sys::D;
+  const RecView& R = a.rec;
+  const int64_t n = a.ivp.n;
+  T* cb = (T*)a.contrib;
+  const T* sbase = (const T*)R.save_base;
+  for (int ss = R.n_save - 1; ss >= 0; --ss) {
+    const double dt = R.save_dt[(int64_t)ss * n + tr];
+    T yb[D], cs[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) yb[c] = sbase[((int64_t)ss * D + c) * n + tr];
+    if (dt == 0.0) {
+      save_cotangent<T, D>(a, ss, tr, yb, two_scale, cs, loss);
+    } else {
+      auto cot = [&](const T* ys, T* w) {
+        save_cotangent<T, D>(a, ss, tr, ys, two_scale, w, loss);
+      };
+      save_step_reverse<Sys, Tab, T, W_LDS>(yb, p, dt, sW, cot, cs, g);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) cb[((int64_t)ss * D + c) * n + tr] = cs[c];
   }
 }
 
@@ -950,10 +1077,11 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   load_params<T, NP>(a.ivp, tr, p);
   const int32_t S = R.steps[tr];
   int32_t page = R.last_page[tr];
-  T ycur[D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) ycur[c] = ((const T*)R.y_final)[c * n + tr];
   const T two_scale = T(2.0 * a.scale);
+
+  // The save steps first (save_steps_reverse); the cotangent each save
+  // gives its base state is added when the loop below reaches that point.
+  save_steps_reverse<Sys, Tab, T, W_LDS>(a, tr, p, two_scale, s_W, gp, loss);
 
   // Save bookkeeping, walked from the last save to the first.
   int s = R.n_save - 1;
@@ -996,24 +1124,20 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   if (CKPT && S > 0) start_segment(slot + 1);
 
   while (true) {
-    // save states that coincide with the current mesh point
-    while (!rebuild && s >= 0 && sidx == i && sdt == 0.0) {
-      T w[D];
-      save_cotangent<T, D>(a, s, tr, ycur, two_scale, w, loss);
+    if (!rebuild) {
+      // the saves based at this mesh point, from the last
+      const T* cb = (const T*)a.contrib;
+      while (s >= 0 && sidx == i) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) lam[c] = lam[c] + w[c];
-      next_save();
+        for (int c = 0; c < D; ++c) lam[c] = lam[c] + cb[((int64_t)s * D + c) * n + tr];
+        next_save();
+      }
+      if (i == 0) break;
     }
-    const bool side = !rebuild && (s >= 0 && sidx == i);
-    if (!rebuild && !side && i == 0) break;
 
     T yb[D];
     double hh;
-    if (side) {
-      hh = sdt;
-#pragma unroll
-      for (int c = 0; c < D; ++c) yb[c] = ycur[c];
-    } else {
+    {
       if (CKPT && rebuild) {
         hh = ((const double*)(R.pages + (int64_t)page * R.page_bytes + YB))[j_rb];
 #pragma unroll
@@ -1066,15 +1190,11 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
       continue;
     }
     T w[D];
-    if (side) {
-      save_cotangent<T, D>(a, s, tr, ys, two_scale, w, loss);
-    } else {
 #pragma unroll
-      for (int c = 0; c < D; ++c) w[c] = lam[c];
-    }
+    for (int c = 0; c < D; ++c) w[c] = lam[c];
 
     // reverse through the stages: kbar_j = h (b_j w + sum_{l>j} a_lj Ybar_l)
-    T Yb[NY][D], lin[D];
+    T lin[D];
     if constexpr (W_LDS) {
       const LdsMat<T> Wl{s_W};
       // the reverse recomputes the stage states and Jacobian terms from
@@ -1089,55 +1209,17 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
     } else if constexpr (Tab::ROS) {
       ros_step_vjp<Sys, Tab, T, T[NW]>(yb, p, T(hh), W, piv, u, w, lin, gp);
     } else {
-#pragma unroll
-    for (int c = 0; c < D; ++c) lin[c] = w[c];
-#pragma unroll
-    for (int j = SU - 1; j >= 0; --j) {
-      T kb[D];
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        T acc = T(0);
-        bool first = true;
-        if (Tab::B[j] != 0.0) {
-          acc = T(Tab::B[j]) * w[c];
-          first = false;
-        }
-#pragma unroll
-        for (int l = j + 1; l < SU; ++l) {
-          if (Tab::A[l][j] != 0.0) {
-            if (first) {
-              acc = T(Tab::A[l][j]) * Yb[l][c];
-              first = false;
-            } else {
-              acc = fmaT(T(Tab::A[l][j]), Yb[l][c], acc);
-            }
-          }
-        }
-        kb[c] = T(hh) * acc;
-      }
-      Sys::vjp(Y[j], p, kb, Yb[j], gp);
-#pragma unroll
-      for (int c = 0; c < D; ++c) lin[c] = lin[c] + Yb[j][c];
-    }
+      erk_step_vjp<Sys, Tab, T>(Y, p, hh, w, lin, gp);
     }
 
-    if (side) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) lam[c] = lam[c] + lin[c];
-      next_save();
-    } else {
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        lam[c] = lin[c];
-        ycur[c] = yb[c];
-      }
-      --i;
-      if (--slot < 0 && i > 0) {
-        page = prev_page(R, page);
-        slot = K - 1;
-        grp = -1;
-        if (CKPT) start_segment(K);
-      }
+    for (int c = 0; c < D; ++c) lam[c] = lin[c];
+    --i;
+    if (--slot < 0 && i > 0) {
+      page = prev_page(R, page);
+      slot = K - 1;
+      grp = -1;
+      if (CKPT) start_segment(K);
     }
   }
 
@@ -1210,43 +1292,30 @@ __global__ void __launch_bounds__(256, (DeferBlocks<Sys, Tab, T>::value))
 
 // Save states of a deferred record: for each trajectory and each save time
 // noted inside an accepted step (base index i < S), the step map from the
-// taped state y_i over the noted offset, Phi(y_i; t_s - t_i) -- the side
+// recorded base state over the noted offset, Phi(y_i; t_s - t_i) -- the side
 // step of the paper's extra-step save (Section 3.4), formed as the reverse
 // sweep forms it.  Saves at or after the last mesh point were written by
 // the record itself.
 template <class Sys, class Tab, class T>
 __global__ void __launch_bounds__(256) erk_saves_kernel(const FwdArgs a) {
   constexpr int D = Sys::D, NP = Sys::NP, SU = Tab::SU;
-  constexpr int RB = TapeRec<T, D>::BYTES;
   static_assert(!Tab::ROS, "explicit pairs only");
   const int64_t n = a.ivp.n;
   const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tr >= n) return;
   const RecView& R = a.rec;
   const int32_t S = R.steps[tr];
-  const int K = R.page_steps;
   T p[NP];
   load_params<T, NP>(a.ivp, tr, p);
   T* ysv = (T*)a.y_save;
-  int32_t page = -1, pidx = -1;  // the page last walked to and its index
+  const T* sbase = (const T*)R.save_base;
   for (int s = 0; s < a.ivp.n_save; ++s) {
     const int32_t i = R.save_idx[(int64_t)s * n + tr];
     if (i < 0 || i >= S) continue;
     const double dt = R.save_dt[(int64_t)s * n + tr];
-    const int32_t pi = i / K;
-    if (pi < R.static_pages) {
-      page = (int32_t)(tr * R.static_pages + pi);
-      pidx = pi;
-    } else {
-      if (pidx < R.static_pages || pidx > pi) {
-        page = R.first_page[tr];
-        pidx = R.static_pages;
-      }
-      for (; pidx < pi; ++pidx) page = next_page(R, tr, page);
-    }
     T y[D], k0[D], Yd[SU][D], ylast[D], klast[D], ys[D];
-    double hdummy;
-    load_rec<T, D>(R.pages + (int64_t)page * R.page_bytes + (i % K) * RB, hdummy, y);
+#pragma unroll
+    for (int c = 0; c < D; ++c) y[c] = sbase[((int64_t)s * D + c) * n + tr];
     Sys::rhs(y, p, k0);
     step_push<Sys, Tab, T, SU, true, true, false>(y, k0, p, T(dt), Yd, ylast, klast, ys,
                                                   nullptr);
@@ -1256,8 +1325,9 @@ __global__ void __launch_bounds__(256) erk_saves_kernel(const FwdArgs a) {
 }
 
 // Blocks per CU the compiler is asked to fit in the reverse sweep: 3 for the
-// FP64 Lorenz / Tsit5 sweep (3 waves per SIMD), which otherwise lands a few
-// registers above that occupancy; no request for the others.
+// FP64 Lorenz / Tsit5 sweep, which then lands at 128 registers with no
+// spill (4 waves per SIMD); asking for 4 gives the same occupancy with a
+// spill.  No request for the others.
 template <class Sys, class Tab, class T>
 struct AdjBlocks {
   static constexpr int value =

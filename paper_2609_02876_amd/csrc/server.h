@@ -138,6 +138,15 @@ struct ens_server {
 
 namespace {
 
+// The reverse sweep's per-save cotangents, [n_save][dim][n], at the end of
+// the job's allocation.
+size_t job_contrib_bytes(const SrvJob& J) {
+  SysInfo si;
+  sys_info(J.desc.prob.system, &si);
+  const int nse = J.desc.ivp.n_save > 0 ? J.desc.ivp.n_save : 1;
+  return align256((size_t)nse * si.d * J.desc.ivp.n * elem_size(J.desc.prob.dtype));
+}
+
 size_t job_record_bytes(const SrvJob& J, int64_t hint) {
   SysInfo si;
   sys_info(J.desc.prob.system, &si);
@@ -146,7 +155,8 @@ size_t job_record_bytes(const SrvJob& J, int64_t hint) {
   const int64_t pages_per = (hint + PAGE_STEPS - 1) / PAGE_STEPS;
   const int64_t n_static = pages_per * J.desc.ivp.n;
   const int64_t n_over = n_static / 8 + 64;
-  return L.fixed + 512 + (size_t)n_static * L.page_bytes + (size_t)n_over * (L.page_bytes + 8);
+  return L.fixed + 512 + (size_t)n_static * L.page_bytes + (size_t)n_over * (L.page_bytes + 8) +
+         job_contrib_bytes(J);
 }
 
 void free_job_memory(ens_server* s, SrvJob& J) {
@@ -203,8 +213,9 @@ int launch_slot(ens_server* s, Slot& sl, const std::vector<int64_t>& ids) {
     SrvJob& J = s->jobs[ids[k]];
     ens_job& d = J.desc;
     ens_tape_cfg tc{};
+    const size_t cb = job_contrib_bytes(J);
     tc.pool = s->arena_base + J.off;
-    tc.pool_bytes = J.bytes;
+    tc.pool_bytes = J.bytes - cb;
     tc.ckpt_every = 0;
     tc.steps_per_traj = (int32_t)J.hint;
     SysInfo si;
@@ -212,7 +223,7 @@ int launch_slot(ens_server* s, Slot& sl, const std::vector<int64_t>& ids) {
     const int nse = d.ivp.n_save > 0 ? d.ivp.n_save : 1;
     Layout L = layout(d.ivp.n, nse, si.d, d.prob.dtype, 0);
     PageSplit ps;
-    if (!split_pages(L, d.ivp.n, J.bytes, (int32_t)J.hint, PAGE_STEPS, &ps))
+    if (!split_pages(L, d.ivp.n, tc.pool_bytes, (int32_t)J.hint, PAGE_STEPS, &ps))
       return fail(ENS_ENOSPACE, "serve: record plan does not fit its allocation");
     ens_ivp v = d.ivp;
     v.save_times = J.save_times.empty() ? nullptr : J.save_times.data();
@@ -231,6 +242,7 @@ int launch_slot(ens_server* s, Slot& sl, const std::vector<int64_t>& ids) {
     H.adj.grad_p = d.grad_params;
     H.adj.grad_y0 = d.grad_y0;
     H.adj.loss_out = d.loss_out;
+    H.adj.contrib = s->arena_base + J.off + tc.pool_bytes;
     H.tile_begin = tiles;
     H.n_tiles = grid_of(d.ivp.n);
     tiles += H.n_tiles;
