@@ -109,21 +109,31 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
             raise SystemExit(f"the largest copy in {d} counts {max(copies):.0f} KiB, not near "
                              f"{mib << 10} KiB: no calibration copy of {mib} MiB in this run")
         out = {}
-        for part, key in (("record", "_forward_kernel<"), ("adjoint", "_adjoint_kernel<"),
-                          ("jvp", "jvp_kernel<")):
-            ks = [r for r in rows if key in r["Kernel_Name"]]
+        # a part's kernels: the explicit pairs' full-tape record is two
+        # launches (the loop, then the save states), each counted once
+        for part, keys in (("record", ("_forward_kernel<", "erk_record_deferred_kernel<",
+                                       "erk_saves_kernel<")),
+                           ("adjoint", ("_adjoint_kernel<",)), ("jvp", ("jvp_kernel<",))):
+            ks = [r for r in rows if any(k in r["Kernel_Name"] for k in keys)]
             if not ks:
                 if part == "record":
                     raise SystemExit(f"no record kernel rows under {d}")
                 continue
             g = max(int(r["Grid_Size"]) for r in ks)
-            ks = [r for r in ks if int(r["Grid_Size"]) == g]
-            # the instantiation dispatched most often: the timed launches (a
-            # forward-only solve of the same size, e.g. for targets, runs once)
-            names = [r["Kernel_Name"] for r in ks]
-            top = max(set(names), key=names.count)
-            vals = [float(r["Counter_Value"]) for r in ks if r["Kernel_Name"] == top]
-            out[part] = {"kib": sum(vals) / len(vals), "dispatches": len(vals), "grid": g}
+            kib, disp, names_used = 0.0, None, []
+            for key in keys:
+                kk = [r for r in ks if key in r["Kernel_Name"] and int(r["Grid_Size"]) == g]
+                if not kk:
+                    continue
+                # the instantiation dispatched most often: the timed launches (a
+                # forward-only solve of the same size, e.g. for targets, runs once)
+                names = [r["Kernel_Name"] for r in kk]
+                top = max(set(names), key=names.count)
+                vals = [float(r["Counter_Value"]) for r in kk if r["Kernel_Name"] == top]
+                kib += sum(vals) / len(vals)
+                disp = len(vals) if disp is None else min(disp, len(vals))
+                names_used.append(top.split("(")[0])
+            out[part] = {"kib": kib, "dispatches": disp, "grid": g, "kernels": names_used}
         return out, factor
 
     fe, ff = read(fetch_dir, "FETCH_SIZE")
@@ -137,7 +147,8 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
                                 "fetch_kib_counted": fe[part]["kib"],
                                 "write_kib_counted": wr[part]["kib"],
                                 "dispatches": fe[part]["dispatches"],
-                                "grid_threads": fe[part]["grid"]}
+                                "grid_threads": fe[part]["grid"],
+                                "kernels": fe[part]["kernels"]}
     if path is None:
         path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
@@ -310,8 +321,12 @@ def main():
         kname = f"ude_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel (f32)"
     else:
         bound, peak = "alu", (PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS)
-        kname = (f"erk_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel "
-                 f"({cfg['system']}, {cfg['method']}, {'f32' if f32 else 'f64'})")
+        deferred = cfg["method"] in ("tsit5", "vern7") and not ckpt and not args.registered
+        kname = ("erk_adjoint_kernel" if dominant == "adjoint" else
+                 # explicit pairs' full-tape record: the loop, then the save states
+                 "erk_record_deferred_kernel + erk_saves_kernel" if deferred else
+                 "erk_forward_kernel")
+        kname += f" ({cfg['system']}, {cfg['method']}, {'f32' if f32 else 'f64'})"
     out = {
         "metric": METRIC if args.workload == "lorenz_2p20_t10" else "trajectory-gradients/s (fwd+adjoint)",
         "value": value,

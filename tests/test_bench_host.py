@@ -48,6 +48,32 @@ def test_write_traffic_calibrates_and_picks_the_timed_launches(tmp_path, capsys)
     assert json.load(open(out))["source_hash"] == bench.kernel_source_hash()
 
 
+DEF = "void ens::erk_record_deferred_kernel<ens::Lorenz, ens::Tsit5, double>(ens::FwdArgs)"
+SAV = "void ens::erk_saves_kernel<ens::Lorenz, ens::Tsit5, double>(ens::FwdArgs)"
+
+
+def test_write_traffic_adds_the_two_launches_of_a_deferred_record(tmp_path, capsys):
+    # the record loop and the save-state kernel are one record; the pilot of
+    # the pool plan (a smaller grid of the one-launch record) is left out
+    fetch = [(131072, "__amd_rocclr_copyBuffer", 1048576.0),
+             (8192, FWD, 999.0),
+             (1048576, DEF, 100.0), (1048576, SAV, 40.0), (1048576, DEF, 120.0),
+             (1048576, SAV, 60.0), (1048576, ADJ, 4000.0)]
+    write = [(131072, "__amd_rocclr_copyBuffer", 1048576.0),
+             (8192, FWD, 5.0),
+             (1048576, DEF, 3000.0), (1048576, SAV, 10.0), (1048576, DEF, 3200.0),
+             (1048576, SAV, 30.0), (1048576, ADJ, 50.0)]
+    _write(tmp_path / "f", "FETCH_SIZE", fetch)
+    _write(tmp_path / "w", "WRITE_SIZE", write)
+    tr = bench.write_traffic(str(tmp_path / "f"), str(tmp_path / "w"), "lorenz_2p20_t10", 1 << 20,
+                             1024, path=str(tmp_path / "t.json"))
+    capsys.readouterr()
+    assert tr["record"] == (110.0 + 50.0 + 3100.0 + 20.0) * 1024
+    assert tr["record_detail"]["dispatches"] == 2
+    assert [k.split("<")[0] for k in tr["record_detail"]["kernels"]] == [
+        "void ens::erk_record_deferred_kernel", "void ens::erk_saves_kernel"]
+
+
 def test_traffic_is_used_only_for_the_sources_it_was_measured_on(tmp_path):
     good = {"n": 8, "source_hash": bench.kernel_source_hash(), "record": 1.0, "adjoint": 2.0}
     stale = dict(good, source_hash="0" * 16)
