@@ -385,8 +385,68 @@ int launch_forward_ude(int mode, bool ckpt, const FwdArgs& fa, hipStream_t st) {
   return e == hipSuccess ? ENS_OK : hip_fail(e, "forward launch");
 }
 
+// Base states of the saves of a full-tape record made on a given mesh
+// (MODE_FROZEN, MODE_REFRESH), which those loops do not store: the state in
+// the record of step i + 1 for a save based at mesh point i < S, the final
+// state for i = S.  Element size es (4 or 8), dimension d.
+__global__ void __launch_bounds__(256) save_bases_kernel(const RecView R, int64_t n, int d,
+                                                         int es) {
+  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tr >= n || R.status[tr] != LANE_OK) return;
+  const int32_t S = R.steps[tr];
+  const int rb = (8 + d * es + 15) / 16 * 16;
+  int32_t page = -1, pidx = -1;  // the page last walked to and its index
+  for (int s = 0; s < R.n_save; ++s) {
+    const int32_t i = R.save_idx[(int64_t)s * n + tr];
+    const char* src;
+    int64_t sstride;  // bytes between components
+    if (i >= S) {
+      src = (const char*)R.y_final + tr * es;
+      sstride = n * es;
+    } else {
+      const int32_t q = i / PAGE_STEPS;
+      if (q < R.static_pages) {
+        page = (int32_t)(tr * R.static_pages + q);
+        pidx = q;
+      } else {
+        if (pidx < R.static_pages || pidx > q) {
+          page = R.first_page[tr];
+          pidx = R.static_pages;
+        }
+        for (; pidx < q; ++pidx) page = next_page(R, tr, page);
+      }
+      src = R.pages + (int64_t)page * R.page_bytes + (i % PAGE_STEPS) * rb + 8;
+      sstride = es;
+    }
+    char* dst = (char*)R.save_base + ((int64_t)s * d * n + tr) * es;
+    for (int c = 0; c < d; ++c) {
+      if (es == 8)
+        *(double*)(dst + (int64_t)c * n * es) = *(const double*)(src + c * sstride);
+      else
+        *(float*)(dst + (int64_t)c * n * es) = *(const float*)(src + c * sstride);
+    }
+  }
+}
+
+int launch_forward_body(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
+                        hipStream_t st);
+
 int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
                    hipStream_t st) {
+  int rc = launch_forward_body(p, mode, ckpt, fa, st);
+  if (rc != ENS_OK || ckpt || (mode != MODE_FROZEN && mode != MODE_REFRESH) ||
+      p->system == ENS_SYS_LV_UDE)
+    return rc;
+  SysInfo si;
+  sys_info(p->system, &si);
+  hipLaunchKernelGGL(save_bases_kernel, dim3(grid_of(fa.ivp.n)), dim3(BLOCK), 0, st, fa.rec,
+                     fa.ivp.n, si.d, (int)elem_size(p->dtype));
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ENS_OK : hip_fail(e, "save-base launch");
+}
+
+int launch_forward_body(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
+                        hipStream_t st) {
   if (p->system == ENS_SYS_LV_UDE) return launch_forward_ude(mode, ckpt, fa, st);
   if (is_rtc(p->system))
     return rtc_launch(p->system, p->method, p->dtype, fwd_expr(p->method, p->dtype, mode, ckpt),
@@ -639,8 +699,7 @@ int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,
   return e == hipSuccess ? ENS_OK : hip_fail(e, "export launch");
 }
 
-// Sweep prologue output: each save's cotangent carried back to its base
-// state, [n_save][dim][n].
+// The sweep's per-save cotangents for their base states, [n_save][dim][n].
 size_t contrib_bytes(const ens_record* r) {
   return align256((size_t)r->n_save * r->dim * r->n * elem_size(r->dtype));
 }

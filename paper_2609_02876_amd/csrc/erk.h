@@ -72,7 +72,7 @@ struct AdjArgs {
   double* loss_out;       // [n] or null
   void* workspace;        // shared parameters: [n_blocks][NP] partials
   void* scratch;          // checkpointed tape: [n][page_steps] step records
-  void* contrib;          // [n_save][D][n]: each save's cotangent carried to its base state
+  void* contrib;          // [n_save][D][n]: each save's cotangent for its base state
 };
 
 // ------------------------------------------------------------ one step --
@@ -586,9 +586,12 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   int next_save = 0;
   // running pointers to this lane's next save-state slots
   T* ys_out = ysv + tr;
-  // the base state of the save at ys_out, into the record's save_base
+  // the base state of the save at ys_out, into the record's save_base.  The
+  // given-mesh modes on a full tape leave it to a kernel that copies the
+  // states from the tape afterwards: their loops load a step size per step,
+  // and those loads would wait behind these stores.
   auto put_base = [&](const T* yb, bool valid) {
-    if constexpr (MODE != MODE_SOLVE) {
+    if constexpr (MODE == MODE_RECORD || (CKPT && MODE != MODE_SOLVE)) {
       T* sb = (T*)R.save_base + (ys_out - ysv);
 #pragma unroll
       for (int c = 0; c < D; ++c) sb[c * n] = valid ? yb[c] : T(NAN);
@@ -1083,20 +1086,17 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   // gives its base state is added when the loop below reaches that point.
   save_steps_reverse<Sys, Tab, T, W_LDS>(a, tr, p, two_scale, s_W, gp, loss);
 
-  // Save bookkeeping, walked from the last save to the first.
+  // Save bookkeeping, walked from the last save to the first: the save's
+  // base index and its cotangent in a.contrib.
   int s = R.n_save - 1;
   const int32_t* sidx_p = R.save_idx + (int64_t)s * n + tr;
-  const double* sdt_p = R.save_dt + (int64_t)s * n + tr;
+  const T* cb_p = (const T*)a.contrib + (int64_t)s * D * n + tr;
   int32_t sidx = *sidx_p;
-  double sdt = *sdt_p;
   auto next_save = [&]() {
     --s;
     sidx_p -= n;
-    sdt_p -= n;
-    if (s >= 0) {
-      sidx = *sidx_p;
-      sdt = *sdt_p;
-    }
+    cb_p -= D * n;
+    if (s >= 0) sidx = *sidx_p;
   };
 
   // Tape position of the step record of mesh step i (h_i, y_{i-1}).
@@ -1126,10 +1126,9 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   while (true) {
     if (!rebuild) {
       // the saves based at this mesh point, from the last
-      const T* cb = (const T*)a.contrib;
       while (s >= 0 && sidx == i) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) lam[c] = lam[c] + cb[((int64_t)s * D + c) * n + tr];
+        for (int c = 0; c < D; ++c) lam[c] = lam[c] + cb_p[c * n];
         next_save();
       }
       if (i == 0) break;
@@ -1325,7 +1324,7 @@ __global__ void __launch_bounds__(256) erk_saves_kernel(const FwdArgs a) {
 }
 
 // Blocks per CU the compiler is asked to fit in the reverse sweep: 3 for the
-// FP64 Lorenz / Tsit5 sweep, which then lands at 128 registers with no
+// FP64 Lorenz / Tsit5 sweep, which then lands at 124 registers with no
 // spill (4 waves per SIMD); asking for 4 gives the same occupancy with a
 // spill.  No request for the others.
 template <class Sys, class Tab, class T>
