@@ -1123,14 +1123,29 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   };
   if (CKPT && S > 0) start_segment(slot + 1);
 
-  while (true) {
-    if (!rebuild) {
-      // the saves based at this mesh point, from the last
-      while (s >= 0 && sidx == i) {
+  // the saves based at mesh point i, from the last: their cotangents into lam
+  auto take_saves = [&]() {
+    while (s >= 0 && sidx == i) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) lam[c] = lam[c] + cb_p[c * n];
-        next_save();
+      for (int c = 0; c < D; ++c) lam[c] = lam[c] + cb_p[c * n];
+      next_save();
+    }
+  };
+  // Where the loop takes them: on reaching a point (explicit pairs), or at
+  // the end of the reverse step that reaches it (Rosenbrock).  The same
+  // additions in the same order; the register allocation differs (on the
+  // FP64 Lorenz / Tsit5 sweep 124 against 146 VGPRs; the HIRES Rodas4 sweep
+  // spills 92 B a lane against none).
+  constexpr bool AT_END = Tab::ROS;
+  if constexpr (AT_END) take_saves();
+
+  while (true) {
+    if constexpr (!AT_END) {
+      if (!rebuild) {
+        take_saves();
+        if (i == 0) break;
       }
+    } else {
       if (i == 0) break;
     }
 
@@ -1214,6 +1229,7 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
 #pragma unroll
     for (int c = 0; c < D; ++c) lam[c] = lin[c];
     --i;
+    if constexpr (AT_END) take_saves();
     if (--slot < 0 && i > 0) {
       page = prev_page(R, page);
       slot = K - 1;
