@@ -1131,12 +1131,14 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
       next_save();
     }
   };
-  // Where the loop takes them: on reaching a point (explicit pairs), or at
-  // the end of the reverse step that reaches it (Rosenbrock).  The same
-  // additions in the same order; the register allocation differs (on the
-  // FP64 Lorenz / Tsit5 sweep 124 against 146 VGPRs; the HIRES Rodas4 sweep
-  // spills 92 B a lane against none).
-  constexpr bool AT_END = Tab::ROS;
+  // Where the loop takes them: on reaching a point, or at the end of the
+  // reverse step that reaches it (the six-stage Rodas4).  The same additions
+  // in the same order; only the register allocation differs, and measured
+  // in opposite directions: at the end, the HIRES Rodas4 sweep spills
+  // nothing instead of 92 B a lane and runs 4 % faster, while the FP64
+  // Lorenz / Tsit5 sweep needs 146 VGPRs instead of 124 and the HIRES
+  // Rosenbrock23 sweep runs 17 % slower.
+  constexpr bool AT_END = Tab::ROS && Tab::SU >= 6;
   if constexpr (AT_END) take_saves();
 
   while (true) {
