@@ -125,18 +125,25 @@ def test_null_pointers_rejected_before_launch():
 
 
 def test_adjoint_workspace_plan():
+    """The sweep's workspace: each save's cotangent for its base state
+    ([n_save][dim][n]), plus the shared-parameter partials and the segment
+    replay records of a checkpointed tape, each 256-byte aligned."""
     lib = _lib()
     out = C.c_size_t()
     rec = A.Record(n=1024, system=A.SYS_LORENZ, method=A.TSIT5, dtype=A.F64, dim=3, nparams=3,
-                   params_shared=0, page_steps=16, ckpt_every=0)
+                   params_shared=0, n_save=20, page_steps=16, ckpt_every=0)
+    cot = 20 * 3 * 1024 * 8
     assert lib.ensemble_adjoint_workspace_bytes(C.byref(rec), C.byref(out)) == 0
-    assert out.value == 0
+    assert out.value == cot
     rec.params_shared = 1   # 4 blocks x 3 params x 8 bytes, 256-aligned
     assert lib.ensemble_adjoint_workspace_bytes(C.byref(rec), C.byref(out)) == 0
-    assert out.value == 256
+    assert out.value == 256 + cot
     rec.params_shared, rec.ckpt_every, rec.page_steps = 0, 64, 64   # one 64-step segment each
     assert lib.ensemble_adjoint_workspace_bytes(C.byref(rec), C.byref(out)) == 0
-    assert out.value == 1024 * 64 * 32
+    assert out.value == 1024 * 64 * 32 + cot
+    rec.n, rec.n_save, rec.ckpt_every, rec.page_steps = 1000, 1, 0, 16   # ragged: aligned up
+    assert lib.ensemble_adjoint_workspace_bytes(C.byref(rec), C.byref(out)) == 0
+    assert out.value == (3 * 1000 * 8 + 255) // 256 * 256
 
 
 def test_checkpoint_plan_is_smaller():
