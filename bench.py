@@ -508,8 +508,11 @@ def refresh_bench(args):
                    "atol": cfg["atol"], "n_save": cfg["n_save"],
                    "parameter_step": args.refresh_step, "slack": 1.0},
         "roofline": {"bound": "alu",
-                     "kernel": f"erk_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel "
-                               f"({cfg['system']}, {cfg['method']}, f64"
+                     # the refresh phase: the record kernel, then the copy of the
+                     # save base states from the tape
+                     "kernel": ("erk_adjoint_kernel" if dominant == "adjoint" else
+                                "erk_forward_kernel + save_bases_kernel")
+                               + f" ({cfg['system']}, {cfg['method']}, f64"
                                f"{', refresh' if dominant == 'refresh' else ''})",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
