@@ -11,7 +11,9 @@ already resident in device memory.  Prints one JSON line.
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -159,10 +161,48 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
     return tr
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_ORACLE_BUILD = None
+
+
+def load_oracle():
+    """The oracle, built with -O3 -march=native for this host when g++ can
+    (the build takes seconds), else the in-tree portable build."""
+    global _ORACLE_BUILD
+    import oracle as O
+    from oracle import build as OB
+    if _ORACLE_BUILD is None:
+        out = os.path.join(tempfile.mkdtemp(prefix="ens_oracle_"), "liboracle_native.so")
+        try:
+            OB.build_native(out)
+            O.use_library(out)
+            _ORACLE_BUILD = OB.flags(native=True)
+        except (OSError, subprocess.CalledProcessError, RuntimeError):
+            _ORACLE_BUILD = OB.flags(native=False)
+    return O
+
+
+def cpu_info():
+    return {"cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "cpu": cpu_model(), "build": _ORACLE_BUILD}
+
+
 def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
     """The FP64 CPU oracle (record + adjoint) on a bounded sample of the workload."""
     import numpy as np
-    import oracle as O
+    O = load_oracle()
     so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON, "hires": O.HIRES,
           "linear": O.LINEAR, "ude": O.LV_UDE}[cfg["system"]]
     mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}[cfg["method"]]
@@ -191,8 +231,7 @@ def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
         m2 = int(min(len(y0), m2 * target_s / max(dt2, 1e-3)))
         m2 = max(64, (m2 // 64) * 64)
         dt2 = run(m2)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": m2 / dt2, "unit": "trajectory-gradients/s", "cores": cores, "kind": "oracle",
+    return {"value": m2 / dt2, "unit": "trajectory-gradients/s", **cpu_info(), "kind": "oracle",
             "sample": f"first {m2} trajectories of the workload, record + adjoint, {dt2:.1f} s"}
 
 
@@ -535,7 +574,6 @@ def forward_bench(args):
     import numpy as np
     import torch
 
-    import oracle as O
     from paper_2609_02876_amd import binding as B
     from paper_2609_02876_amd import flops
     from paper_2609_02876_amd import workloads as W
@@ -639,6 +677,7 @@ def forward_bench(args):
                              "total_tflops": (f_rec + npar * f_pass) / (ms_per_step * 1e-3) / 1e12},
     }
     if not args.no_cpu_baseline:
+        O = load_oracle()
         so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON,
               "linear": O.LINEAR}[cfg["system"]]
         mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}[cfg["method"]]
@@ -663,8 +702,7 @@ def forward_bench(args):
             m2 = max(64, (m2 // 64) * 64)
             dt2 = run(m2)
         out["cpu_baseline"] = {
-            "value": m2 / dt2, "unit": "trajectory-gradients/s",
-            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "value": m2 / dt2, "unit": "trajectory-gradients/s", **cpu_info(),
             "kind": "oracle",
             "sample": f"first {m2} trajectories, record + {npar} dual-number replays, {dt2:.1f} s"}
     print(json.dumps(out), flush=True)

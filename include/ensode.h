@@ -322,7 +322,9 @@ int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* 
  * build never fuses a product and a sum by itself, so the written operations
  * fix the rounding), constants, and T(c).  It must be straight-line: no
  * branches, loops, '?', '&&', '||', preprocessor directives, inline
- * assembly, shared memory, synchronisation or atomics -- data-dependent
+ * assembly, compiler intrinsics (identifiers that begin with two
+ * underscores, other than __device__ and __forceinline__), shared memory,
+ * synchronisation, atomics or thread and block indices -- data-dependent
  * control flow is refused (ENS_EINVAL, as is a source that does not
  * compile; ensemble_last_error gives the reason and the compiler's log).
  * dim in [1, ENS_USER_MAX_DIM], nparams in [1, ENS_USER_MAX_PARAMS].  On

@@ -35,6 +35,15 @@ _i32 = C.POINTER(C.c_int32)
 _i64 = C.POINTER(C.c_int64)
 
 
+def use_library(path):
+    """Load the oracle from another build of the same source (the benchmark's
+    CPU baseline uses one tuned for its host); must precede the first call."""
+    global _lib, LIB_PATH
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    LIB_PATH = path
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -65,7 +74,9 @@ def _load():
                                               I, _i32, _d, _d, _d]
         lib.oracle_adjoint.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d,
                                        I, _d, D, _d, _d, _d]
-        for f in ("oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp", "oracle_jac",
+        lib.oracle_count_ops.argtypes = [I, I, _i64]
+        lib.oracle_count_system.argtypes = [I, _i64]
+        for f in ("oracle_count_ops", "oracle_count_system", "oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp", "oracle_jac",
                   "oracle_jac_vjp", "oracle_ros_tableau",
                   "oracle_record", "oracle_replay", "oracle_replay_dual",
                   "oracle_replay_complex", "oracle_adjoint"):
@@ -97,6 +108,28 @@ def erk_tableau(method):
         raise ValueError(f"no explicit tableau for method {method}")
     return dict(s=s, c=c[:s].copy(), A=a[: s * s].reshape(s, s).copy(), b=b[:s].copy(),
                 ew=ew[:s].copy(), order=o.value, q_emb=q.value)
+
+
+COUNT_UNITS = ("trial", "accept", "side_fwd", "adj_step", "adj_side", "adj_zero")
+
+
+def count_ops(method, system):
+    """Floating-point operations of one unit of work, counted by running the
+    oracle's own step routines on an operation-counting scalar (fma 2; +, -,
+    *, /, min, max, sqrt, tanh and the controller's root 1; negation, abs and
+    comparisons 0).  Returns a dict over COUNT_UNITS."""
+    out = np.zeros(6, np.int64)
+    if _load().oracle_count_ops(method, system, _p(out, _i64)) != 0:
+        raise ValueError(f"no counts for method {method} on system {system}")
+    return dict(zip(COUNT_UNITS, (int(v) for v in out)))
+
+
+def count_system(system):
+    """(f, VJP, Jacobian, Jacobian-VJP) operation counts of one evaluation."""
+    out = np.zeros(4, np.int64)
+    if _load().oracle_count_system(system, _p(out, _i64)) != 0:
+        raise ValueError(f"unknown system {system}")
+    return tuple(int(v) for v in out)
 
 
 def root_inv(x, k):

@@ -70,6 +70,39 @@ inline double value_of(double x) { return x; }
 inline double value_of(Dual x) { return x.v; }
 inline double value_of(Cplx x) { return x.real(); }
 
+// Operation counter: a double that counts the floating-point operations done
+// on it, by the counting rules of the algorithmic work (fma 2; +, -, *, /,
+// min, max 1; sqrt, tanh and the controller's root 1; negation, abs and
+// comparisons 0).  Instantiating the step routines below on it counts the
+// work of one trial step, one reverse step, ... as this file performs it.
+thread_local int64_t g_ops = 0;
+struct OpCount {
+  double v;
+  OpCount(double x = 0.0) : v(x) {}
+};
+inline OpCount operator+(OpCount a, OpCount b) { ++g_ops; return a.v + b.v; }
+inline OpCount operator-(OpCount a, OpCount b) { ++g_ops; return a.v - b.v; }
+inline OpCount operator*(OpCount a, OpCount b) { ++g_ops; return a.v * b.v; }
+inline OpCount operator/(OpCount a, OpCount b) { ++g_ops; return a.v / b.v; }
+inline OpCount operator-(OpCount a) { return -a.v; }
+inline OpCount& operator+=(OpCount& a, OpCount b) { a = a + b; return a; }
+inline bool operator==(OpCount a, OpCount b) { return a.v == b.v; }
+inline bool operator!=(OpCount a, OpCount b) { return a.v != b.v; }
+inline OpCount fma(OpCount a, OpCount b, OpCount c) { g_ops += 2; return std::fma(a.v, b.v, c.v); }
+inline OpCount tanh(OpCount a) { ++g_ops; return std::tanh(a.v); }
+inline double value_of(OpCount x) { return x.v; }
+
+// max, abs and sqrt in every scalar type of the norm and controller (double
+// and the counter; the others never reach them)
+inline double maxval(double a, double b) { return std::fmax(a, b); }
+inline double minval(double a, double b) { return std::fmin(a, b); }
+inline double absT(double a) { return std::fabs(a); }
+inline double sqrtT(double a) { return std::sqrt(a); }
+inline OpCount maxval(OpCount a, OpCount b) { ++g_ops; return std::fmax(a.v, b.v); }
+inline OpCount minval(OpCount a, OpCount b) { ++g_ops; return std::fmin(a.v, b.v); }
+inline OpCount absT(OpCount a) { return std::fabs(a.v); }
+inline OpCount sqrtT(OpCount a) { ++g_ops; return std::sqrt(a.v); }
+
 // --------------------------------------------------------------- tableaux --
 // Explicit Runge-Kutta pairs.  c, a (strictly lower), b and ew = b - bhat
 // (the weights of the embedded error estimate, up to a sign that the RMS
@@ -230,16 +263,16 @@ static void ude_forward(const T* y, const P* p, T* h1, T* h2, T* f) {
 
 // gy = (df/dy)^T w (overwritten), gp += (df/dp)^T w, by the chain rule
 // through the three layers (tanh' = 1 - tanh^2).
-static void ude_vjp(const double* y, const double* p, const double* w, double* gy,
-                    double* gp) {
-  double h1[UDE_H], h2[UDE_H], f[2], d2[UDE_H], d1[UDE_H];
+template <class T>
+static void ude_vjp(const T* y, const T* p, const T* w, T* gy, T* gp) {
+  T h1[UDE_H], h2[UDE_H], f[2], d2[UDE_H], d1[UDE_H];
   ude_forward(y, p, h1, h2, f);
   for (int o = 0; o < 2; ++o) {
     gp[UDE_B3 + o] += w[o];
     for (int j = 0; j < UDE_H; ++j) gp[UDE_W3 + UDE_H * o + j] += w[o] * h2[j];
   }
   for (int j = 0; j < UDE_H; ++j) {
-    double g = 0.0;
+    T g = T(0.0);
     for (int o = 0; o < 2; ++o) g += p[UDE_W3 + UDE_H * o + j] * w[o];
     d2[j] = g * (1.0 - h2[j] * h2[j]);
   }
@@ -248,7 +281,7 @@ static void ude_vjp(const double* y, const double* p, const double* w, double* g
     for (int j = 0; j < UDE_H; ++j) gp[UDE_W2 + UDE_H * i + j] += d2[i] * h1[j];
   }
   for (int j = 0; j < UDE_H; ++j) {
-    double g = 0.0;
+    T g = T(0.0);
     for (int i = 0; i < UDE_H; ++i) g += p[UDE_W2 + UDE_H * i + j] * d2[i];
     d1[j] = g * (1.0 - h1[j] * h1[j]);
   }
@@ -257,7 +290,7 @@ static void ude_vjp(const double* y, const double* p, const double* w, double* g
     for (int k = 0; k < 2; ++k) gp[UDE_W1 + 2 * i + k] += d1[i] * y[k];
   }
   for (int k = 0; k < 2; ++k) {
-    double g = 0.0;
+    T g = T(0.0);
     for (int i = 0; i < UDE_H; ++i) g += p[UDE_W1 + 2 * i + k] * d1[i];
     gy[k] = g;
   }
@@ -373,16 +406,16 @@ static void jac(int sys, const T* y, const P* p, T* J) {
 }
 
 // d/d(y, p) of G = u^T J(y, p) v, accumulated into gy and gp.
-static void jac_vjp(int sys, const double* y, const double* p, const double* u,
-                    const double* v, double* gy, double* gp) {
+template <class T>
+static void jac_vjp(int sys, const T* y, const T* p, const T* u, const T* v, T* gy, T* gp) {
   switch (sys) {
     case SYS_LINEAR: {
       gp[0] = gp[0] - fma(u[0], v[0], u[1] * v[1]);
       gp[1] = gp[1] + fma(u[1], v[0], -(u[0] * v[1]));
     } break;
     case SYS_ROBERTSON: {
-      double du = u[0] - u[1];
-      double t = (p[1] + p[1]) * (v[1] * (u[2] - u[1]));
+      T du = u[0] - u[1];
+      T t = (p[1] + p[1]) * (v[1] * (u[2] - u[1]));
       gy[1] = gy[1] + fma(p[2] * v[2], du, t);
       gy[2] = gy[2] + (p[2] * v[1]) * du;
       gp[0] = gp[0] + v[0] * (u[1] - u[0]);
@@ -390,7 +423,7 @@ static void jac_vjp(int sys, const double* y, const double* p, const double* u,
       gp[2] = gp[2] + du * fma(y[2], v[1], y[1] * v[2]);
     } break;
     case SYS_HIRES: {
-      double du = (u[6] - u[5]) - u[7];
+      T du = (u[6] - u[5]) - u[7];
       gy[5] = gy[5] + (p[9] * v[7]) * du;
       gy[7] = gy[7] + (p[9] * v[5]) * du;
       gp[0] = gp[0] + fma(u[5], v[4], fma(u[3], v[2], v[0] * (u[1] - u[0])));
@@ -421,8 +454,8 @@ static void jac_vjp(int sys, const double* y, const double* p, const double* u,
 //  Linear:
 //    gy0 = fma(w, w1, -(a*w0));  gy1 = -fma(w, w0, a*w1)
 //    gp0 = gp0 - fma(y0, w0, y1*w1);  gp1 = gp1 + fma(y0, w1, -(y1*w0))
-static void vjp(int sys, const double* y, const double* p, const double* w,
-                double* gy, double* gp) {
+template <class T>
+static void vjp(int sys, const T* y, const T* p, const T* w, T* gy, T* gp) {
   switch (sys) {
     case SYS_LORENZ: {
       gy[0] = fma(y[1], w[2], fma(p[1] - y[2], w[1], -(p[0] * w[0])));
@@ -433,9 +466,9 @@ static void vjp(int sys, const double* y, const double* p, const double* w,
       gp[2] = fma(-y[2], w[2], gp[2]);
     } break;
     case SYS_VDP: {
-      double u = p[0] * w[1];
-      double q = fma(-y[0], y[0], 1.0);
-      gy[0] = u * fma(-2.0 * y[0], y[1], -1.0);
+      T u = p[0] * w[1];
+      T q = fma(-y[0], y[0], T(1.0));
+      gy[0] = u * fma(T(-2.0) * y[0], y[1], T(-1.0));
       gy[1] = fma(u, q, w[0]);
       gp[0] = fma(w[1], fma(q, y[1], -y[0]), gp[0]);
     } break;
@@ -446,7 +479,7 @@ static void vjp(int sys, const double* y, const double* p, const double* w,
       gp[1] = gp[1] + fma(y[0], w[1], -(y[1] * w[0]));
     } break;
     case SYS_ROBERTSON: {
-      double s2 = p[2] * y[2], s1 = p[2] * y[1], q = p[1] * y[1];
+      T s2 = p[2] * y[2], s1 = p[2] * y[1], q = p[1] * y[1];
       gy[0] = p[0] * (w[1] - w[0]);
       gy[1] = fma(s2, w[0] - w[1], (q + q) * (w[2] - w[1]));
       gy[2] = s1 * (w[0] - w[1]);
@@ -456,7 +489,7 @@ static void vjp(int sys, const double* y, const double* p, const double* w,
     } break;
     case SYS_LV_UDE: ude_vjp(y, p, w, gy, gp); break;
     case SYS_HIRES: {
-      double a = p[9] * y[7], b = p[9] * y[5];
+      T a = p[9] * y[7], b = p[9] * y[5];
       gy[0] = p[0] * (w[1] - w[0]);
       gy[1] = fma(p[2], w[3], fma(p[1], w[0], -(p[4] * w[1])));
       gy[2] = fma(p[0], w[3], fma(p[2], w[0], -(p[5] * w[2])));
@@ -621,14 +654,55 @@ struct RecordArgs {
 
 // Scaled RMS norm of v against the scales sc (paper, Section 2.1):
 // sqrt(mean_c (v_c / sc_c)^2), the squares summed with fma in index order.
-static double rms_norm(int d, const double* v, const double* sc) {
-  double r = v[0] / sc[0];
-  double ss = r * r;
+template <class T>
+static T rms_norm(int d, const T* v, const T* sc) {
+  T r = v[0] / sc[0];
+  T ss = r * r;
   for (int c = 1; c < d; ++c) {
     r = v[c] / sc[c];
     ss = fma(r, r, ss);
   }
-  return std::sqrt(ss * (1.0 / (double)d));
+  return sqrtT(ss * T(1.0 / (double)d));
+}
+
+// The controller's power: x^(-1/k) by root_inv in double; the counter counts
+// it as one operation (a pow).
+static double root_pow(double x, int k) { return root_inv(x, k); }
+static OpCount root_pow(OpCount x, int k) {
+  ++g_ops;
+  return root_inv(x.v, k);
+}
+
+// Error estimate e = h * sum_j ew_j k_j of an explicit pair (index order, fma)
+// and its scaled RMS norm against atol + rtol max(|y|, |y_new|) (Section 2.1).
+template <class T>
+static T erk_err(const ERK& m, int d, T h, const T* y, const T* ynew, T k[SMAX][DMAX],
+                 double rtol, double atol) {
+  T e[DMAX], sc[DMAX];
+  for (int c = 0; c < d; ++c) {
+    T acc = T(0.0);
+    bool first = true;
+    for (int j = 0; j < m.s; ++j) {
+      if (m.ew[j] == 0.0) continue;
+      if (first) { acc = T(m.ew[j]) * k[j][c]; first = false; }
+      else acc = fma(T(m.ew[j]), k[j][c], acc);
+    }
+    e[c] = h * acc;
+    sc[c] = fma(T(rtol), maxval(absT(y[c]), absT(ynew[c])), T(atol));
+  }
+  return rms_norm(d, e, sc);
+}
+
+// Controller (integral, Section 2.1): the proposed factor 0.9 err^(-1/k),
+// then the next step after a rejection (factor at least 0.2) or an
+// acceptance (factor in [0.2, 10], at most 1 right after a rejection).
+template <class T>
+static T ctrl_fac0(T err, int k) { return T(0.9) * root_pow(err, k); }
+template <class T>
+static T ctrl_reject(T h, T fac0) { return h * maxval(T(0.2), fac0); }
+template <class T>
+static T ctrl_accept(T h, T fac0, bool prev_rejected) {
+  return h * maxval(T(0.2), minval(T(prev_rejected ? 1.0 : 10.0), fac0));
 }
 
 // Starting step: Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4, with
@@ -709,26 +783,14 @@ static void record_lane(const RecordArgs& A, int lane) {
       erk_update(m, d, y, h, k, ynew);
     }
     // error estimate e = h * sum_j ew_j k_j and its scaled RMS norm
-    double e[DMAX], sc[DMAX];
-    for (int c = 0; c < d; ++c) {
-      double acc = 0.0;
-      bool first = true;
-      for (int j = 0; j < m.s; ++j) {
-        if (m.ew[j] == 0.0) continue;
-        if (first) { acc = m.ew[j] * k[j][c]; first = false; }
-        else acc = fma(m.ew[j], k[j][c], acc);
-      }
-      e[c] = h * acc;
-      sc[c] = fma(A.rtol, std::fmax(std::fabs(y[c]), std::fabs(ynew[c])), A.atol);
-    }
-    double err = rms_norm(d, e, sc);
+    const double err = erk_err(m, d, h, y, ynew, k, A.rtol, A.atol);
     // proposed factor 0.9 err^(-1/(q_emb+1)), bounded below by 0.2 and above
     // by 10 (1 right after a rejection); err = 0 gives the upper bound
-    const double fac0 = 0.9 * root_inv(err, kroot);
+    const double fac0 = ctrl_fac0(err, kroot);
     if (following && !(err <= A.slack)) {  // the old mesh ends here: a rejected trial
       following = false;
       kept = S;
-      h = h * std::fmax(0.2, fac0);
+      h = ctrl_reject(h, fac0);
       prev_rejected = true;
       continue;
     }
@@ -759,11 +821,10 @@ static void record_lane(const RecordArgs& A, int lane) {
       } else {
         rhs(sys, y, p, k1);
       }
-      const double fac = std::fmax(0.2, std::fmin(prev_rejected ? 1.0 : 10.0, fac0));
-      h = h * fac;
+      h = ctrl_accept(h, fac0, prev_rejected);
       prev_rejected = false;
     } else {
-      h = h * std::fmax(0.2, fac0);
+      h = ctrl_reject(h, fac0);
       prev_rejected = true;
     }
   }
@@ -832,25 +893,25 @@ enum { LOSS_SUMSQ = 0, LOSS_MSE_TARGET = 1, LOSS_COTANGENT = 2 };
 // Returns the input cotangent lam + sum_j Ybar_j (accumulated in descending
 // j) and accumulates gp += sum_j (df/dp)^T kbar_j, where for j = s'..1
 //   kbar_j = h * (b_j lam + sum_{l>j} a_lj Ybar_l),  Ybar_j = (df/dy)^T kbar_j.
-static void erk_step_vjp(const ERK& m, int sys, int d, const double* y,
-                         const double* p, double h, const double* lam,
-                         double* lam_in, double* gp) {
-  double k[SMAX][DMAX], Y[SMAX][DMAX];
+template <class T>
+static void erk_step_vjp(const ERK& m, int sys, int d, const T* y, const T* p, T h,
+                         const T* lam, T* lam_in, T* gp) {
+  T k[SMAX][DMAX], Y[SMAX][DMAX];
   rhs(sys, y, p, k[0]);
   const int su = m.s_used;
   erk_stages(m, sys, d, y, p, h, su, k, Y);
-  double Yb[SMAX][DMAX];
+  T Yb[SMAX][DMAX];
   for (int c = 0; c < d; ++c) lam_in[c] = lam[c];
   for (int j = su - 1; j >= 0; --j) {
-    double kb[DMAX];
+    T kb[DMAX];
     for (int c = 0; c < d; ++c) {
-      double acc = 0.0;
+      T acc = T(0.0);
       bool first = true;
-      if (m.b[j] != 0.0) { acc = m.b[j] * lam[c]; first = false; }
+      if (m.b[j] != 0.0) { acc = T(m.b[j]) * lam[c]; first = false; }
       for (int l = j + 1; l < su; ++l) {
         if (m.a[l][j] == 0.0) continue;
-        if (first) { acc = m.a[l][j] * Yb[l][c]; first = false; }
-        else acc = fma(m.a[l][j], Yb[l][c], acc);
+        if (first) { acc = T(m.a[l][j]) * Yb[l][c]; first = false; }
+        else acc = fma(T(m.a[l][j]), Yb[l][c], acc);
       }
       kb[c] = h * acc;
     }
@@ -865,11 +926,30 @@ struct LossArgs {
   double scale;
 };
 
+// One component's loss cotangent w at a save state's value v and its loss
+// term (added into loss): sum of squares v^2 (w = 2 scale v), squared
+// difference to a target (v - x)^2 (w = 2 scale (v - x)), or a given
+// cotangent x (no loss term).
+template <class T>
+static void loss_cot(int kind, T v, double x, T two_scale, T& loss, T& w) {
+  if (kind == LOSS_SUMSQ) {
+    loss = fma(v, v, loss);
+    w = two_scale * v;
+  } else if (kind == LOSS_MSE_TARGET) {
+    T r = v - T(x);
+    loss = fma(r, r, loss);
+    w = two_scale * r;
+  } else {
+    w = T(x);
+  }
+}
+
 // Discrete adjoint of one lane: gradient of the lane's loss with respect to
 // its parameters (gp, accumulated) and its initial state (gy0).  Returns the
 // lane's loss.
-static void step_vjp_any(int method, int sys, int d, const double* y, const double* p,
-                         double h, const double* lam, double* lam_in, double* gp);
+template <class T>
+static void step_vjp_any(int method, int sys, int d, const T* y, const T* p, T h,
+                         const T* lam, T* lam_in, T* gp);
 
 static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
                            const double* y0, const double* p, double* gp,
@@ -896,21 +976,10 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
   double loss = 0.0;
   std::vector<double> wbar((size_t)M.n_save * d);
   const double two_scale = 2.0 * L.scale;
-  for (int s = 0; s < M.n_save; ++s) {
-    for (int c = 0; c < d; ++c) {
-      double v = ysave[s * d + c];
-      if (L.kind == LOSS_SUMSQ) {
-        loss = fma(v, v, loss);
-        wbar[s * d + c] = two_scale * v;
-      } else if (L.kind == LOSS_MSE_TARGET) {
-        double r = v - ldat[s * d + c];
-        loss = fma(r, r, loss);
-        wbar[s * d + c] = two_scale * r;
-      } else {
-        wbar[s * d + c] = ldat[s * d + c];
-      }
-    }
-  }
+  for (int s = 0; s < M.n_save; ++s)
+    for (int c = 0; c < d; ++c)
+      loss_cot(L.kind, ysave[s * d + c], ldat ? ldat[s * d + c] : 0.0, two_scale, loss,
+               wbar[s * d + c]);
   loss = L.scale * loss;
 
   // The save steps first, from the last save to the first: each one's
@@ -1033,6 +1102,7 @@ static bool is_ros(int method) { return ros_of(method) != nullptr; }
 inline double absval(double x) { return std::fabs(x); }
 inline double absval(Dual x) { return std::fabs(x.v); }
 inline double absval(Cplx x) { return std::fabs(x.real()); }
+inline double absval(OpCount x) { return std::fabs(x.v); }
 
 // LU factorisation with partial pivoting, in place (row-major d x d).  The
 // pivot of column k is the first row i >= k with the largest |W_ik| (ties go
@@ -1080,15 +1150,16 @@ static void lu_solve(int d, const T* LU, const int* perm, const T* b, T* x) {
 }
 
 // Solve W^T z = b with the factors: U^T v = b, L^T w = v, z[perm[i]] = w[i].
-static void lu_solve_t(int d, const double* LU, const int* perm, const double* b, double* z) {
-  double v[DMAX];
+template <class T>
+static void lu_solve_t(int d, const T* LU, const int* perm, const T* b, T* z) {
+  T v[DMAX];
   for (int i = 0; i < d; ++i) {
-    double acc = b[i];
+    T acc = b[i];
     for (int j = 0; j < i; ++j) acc = fma(-LU[j * d + i], v[j], acc);
     v[i] = acc * LU[i * d + i];
   }
   for (int i = d - 1; i >= 0; --i) {
-    double acc = v[i];
+    T acc = v[i];
     for (int j = i + 1; j < d; ++j) acc = fma(-LU[j * d + i], v[j], acc);
     v[i] = acc;
   }
@@ -1097,18 +1168,21 @@ static void lu_solve_t(int d, const double* LU, const int* perm, const double* b
 
 // One Rosenbrock step of method m from y with step h; stage inputs Y,
 // increments u and the factors are returned for the reverse sweep.
-// y_new = Y_s + u_s (Rodas4) or Y_s (Rosenbrock23).
+// y_new = Y_s + u_s (Rodas4) or Y_s (Rosenbrock23).  The first n_st stages
+// are formed: a trial step needs all s; a replay step and its reverse only
+// the su that enter y_new (for Rosenbrock23, y_new is then formed as the
+// third stage's input without that stage's solve).
 template <class T, class P>
-static void ros_step(const ROS& m, int sys, int d, const T* y, const P* p, T h, T* ynew,
-                     T Y[6][DMAX], T u[6][DMAX], T* LU, int* perm) {
+static void ros_step(const ROS& m, int sys, int d, const T* y, const P* p, T h, int n_st,
+                     T* ynew, T Y[6][DMAX], T u[6][DMAX], T* LU, int* perm) {
   jac(sys, y, p, LU);
   const T dg = T(1.0) / (T(m.gamma) * h);
   for (int i = 0; i < d * d; ++i) LU[i] = -LU[i];
   for (int i = 0; i < d; ++i) LU[i * d + i] = LU[i * d + i] + dg;
   lu_factor(d, LU, perm);
   const T hinv = T(1.0) / h;
-  for (int i = 0; i < m.s; ++i) {
-    T F[DMAX], r[DMAX];
+  // stage input Y_i = y + sum_{j<i} a_ij u_j
+  auto stage_input = [&](int i) {
     for (int c = 0; c < d; ++c) {
       T acc = T(0.0);
       bool first = true;
@@ -1119,6 +1193,10 @@ static void ros_step(const ROS& m, int sys, int d, const T* y, const P* p, T h, 
       }
       Y[i][c] = first ? y[c] : y[c] + acc;
     }
+  };
+  for (int i = 0; i < n_st; ++i) {
+    T F[DMAX], r[DMAX];
+    stage_input(i);
     rhs(sys, Y[i], p, F);
     for (int c = 0; c < d; ++c) {
       T acc = T(0.0);
@@ -1132,22 +1210,35 @@ static void ros_step(const ROS& m, int sys, int d, const T* y, const P* p, T h, 
     }
     lu_solve(d, LU, perm, r, u[i]);
   }
+  if (!ynew) return;  // the reverse needs only the stages
+  if (m.new_at_input && n_st < m.s) stage_input(m.s - 1);
   for (int c = 0; c < d; ++c)
     ynew[c] = m.new_at_input ? Y[m.s - 1][c] : Y[m.s - 1][c] + u[m.s - 1][c];
 }
 
 // Error estimate e = sum_j e_j u_j (Rodas4: u_6 itself).
-static void ros_errvec(const ROS& m, int d, const double u[6][DMAX], double* e) {
+template <class T>
+static void ros_errvec(const ROS& m, int d, const T u[6][DMAX], T* e) {
   for (int c = 0; c < d; ++c) {
-    double acc = 0.0;
+    T acc = T(0.0);
     bool first = true;
     for (int j = 0; j < m.s; ++j) {
       if (m.e[j] == 0.0) continue;
-      if (first) { acc = m.e[j] * u[j][c]; first = false; }
-      else acc = fma(m.e[j], u[j][c], acc);
+      if (first) { acc = T(m.e[j]) * u[j][c]; first = false; }
+      else acc = fma(T(m.e[j]), u[j][c], acc);
     }
     e[c] = acc;
   }
+}
+
+// The error estimate's scaled RMS norm (as for the explicit pairs).
+template <class T>
+static T ros_err(const ROS& m, int d, const T* y, const T* ynew, const T u[6][DMAX],
+                 double rtol, double atol) {
+  T sc[DMAX] = {}, e[DMAX] = {};
+  for (int c = 0; c < d; ++c) sc[c] = fma(T(rtol), maxval(absT(y[c]), absT(ynew[c])), T(atol));
+  ros_errvec(m, d, u, e);
+  return rms_norm(d, e, sc);
 }
 
 template <class T, class P>
@@ -1158,7 +1249,7 @@ static void ros_phi(const ROS& m, int sys, int d, const T* y, const P* p, T h, T
   }
   T Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
   int perm[DMAX];
-  ros_step(m, sys, d, y, p, h, ynew, Y, u, LU, perm);
+  ros_step(m, sys, d, y, p, h, m.su, ynew, Y, u, LU, perm);
 }
 
 static void ros_record_lane(const RecordArgs& A, int lane) {
@@ -1209,17 +1300,13 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
     ++trials;
     double ynew[DMAX], Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
     int perm[DMAX];
-    ros_step(m, sys, d, y, p, h, ynew, Y, u, LU, perm);
-    double sc[DMAX], e[DMAX];
-    for (int c = 0; c < d; ++c)
-      sc[c] = fma(A.rtol, std::fmax(std::fabs(y[c]), std::fabs(ynew[c])), A.atol);
-    ros_errvec(m, d, u, e);
-    const double err = rms_norm(d, e, sc);
-    const double fac0 = 0.9 * root_inv(err, kroot);
+    ros_step(m, sys, d, y, p, h, m.s, ynew, Y, u, LU, perm);
+    const double err = ros_err(m, d, y, ynew, u, A.rtol, A.atol);
+    const double fac0 = ctrl_fac0(err, kroot);
     if (following && !(err <= A.slack)) {  // the old mesh ends here: a rejected trial
       following = false;
       kept = S;
-      h = h * std::fmax(0.2, fac0);
+      h = ctrl_reject(h, fac0);
       prev_rejected = true;
       continue;
     }
@@ -1239,10 +1326,10 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
       ++S;
       t = tnew;
       for (int c = 0; c < d; ++c) y[c] = ynew[c];
-      h = h * std::fmax(0.2, std::fmin(prev_rejected ? 1.0 : 10.0, fac0));
+      h = ctrl_accept(h, fac0, prev_rejected);
       prev_rejected = false;
     } else {
-      h = h * std::fmax(0.2, fac0);
+      h = ctrl_reject(h, fac0);
       prev_rejected = true;
     }
   }
@@ -1271,35 +1358,36 @@ static void ros_record_lane(const RecordArgs& A, int lane) {
 // each stage adds its f_p term, then its J_p term, to p_bar.  Only the su
 // stages that enter y_new are reversed: a later stage (Rosenbrock23's third,
 // which serves the error estimate alone) has a zero cotangent.
-static void ros_step_vjp(const ROS& m, int sys, int d, const double* y, const double* p,
-                         double h, const double* lam, double* lam_in, double* gp) {
-  if (h == 0.0) {
+template <class T>
+static void ros_step_vjp(const ROS& m, int sys, int d, const T* y, const T* p, T h,
+                         const T* lam, T* lam_in, T* gp) {
+  if (value_of(h) == 0.0) {
     for (int c = 0; c < d; ++c) lam_in[c] = lam[c];
     return;
   }
-  double ynew[DMAX], Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
+  T Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
   int perm[DMAX];
-  ros_step(m, sys, d, y, p, h, ynew, Y, u, LU, perm);
-  const double hinv = 1.0 / h;
-  double Yb[6][DMAX], rb[6][DMAX], tb[6][DMAX], gJ[DMAX];
+  ros_step(m, sys, d, y, p, h, m.su, (T*)nullptr, Y, u, LU, perm);
+  const T hinv = T(1.0) / h;
+  T Yb[6][DMAX], rb[6][DMAX], tb[6][DMAX], gJ[DMAX];
   for (int c = 0; c < d; ++c) {
     lam_in[c] = lam[c];
-    gJ[c] = 0.0;
+    gJ[c] = T(0.0);
   }
   for (int i = m.su - 1; i >= 0; --i) {
-    double ub[DMAX];
+    T ub[DMAX];
     for (int c = 0; c < d; ++c) {
-      double acc = 0.0;
+      T acc = T(0.0);
       bool first = true;
-      if (m.m[i] != 0.0) { acc = m.m[i] * lam[c]; first = false; }
+      if (m.m[i] != 0.0) { acc = T(m.m[i]) * lam[c]; first = false; }
       for (int l = m.su - 1; l > i; --l) {  // in the order the sweep forms them
         if (m.a[l][i] != 0.0) {
-          if (first) { acc = m.a[l][i] * Yb[l][c]; first = false; }
-          else acc = fma(m.a[l][i], Yb[l][c], acc);
+          if (first) { acc = T(m.a[l][i]) * Yb[l][c]; first = false; }
+          else acc = fma(T(m.a[l][i]), Yb[l][c], acc);
         }
         if (m.c[l][i] != 0.0) {
-          if (first) { acc = m.c[l][i] * tb[l][c]; first = false; }
-          else acc = fma(m.c[l][i], tb[l][c], acc);
+          if (first) { acc = T(m.c[l][i]) * tb[l][c]; first = false; }
+          else acc = fma(T(m.c[l][i]), tb[l][c], acc);
         }
       }
       ub[c] = acc;
@@ -1320,8 +1408,9 @@ static void phi_any(int method, int sys, int d, const T* y, const P* p, T h, T* 
   else erk_phi(*erk_of(method), sys, d, y, p, h, ynew);
 }
 
-static void step_vjp_any(int method, int sys, int d, const double* y, const double* p,
-                         double h, const double* lam, double* lam_in, double* gp) {
+template <class T>
+static void step_vjp_any(int method, int sys, int d, const T* y, const T* p, T h,
+                         const T* lam, T* lam_in, T* gp) {
   if (is_ros(method)) ros_step_vjp(*ros_of(method), sys, d, y, p, h, lam, lam_in, gp);
   else erk_step_vjp(*erk_of(method), sys, d, y, p, h, lam, lam_in, gp);
 }
@@ -1409,7 +1498,7 @@ int oracle_ros_trial(int method, int sys, const double* y, const double* p, doub
     return -1;
   double Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
   int perm[DMAX];
-  ros_step(*rp, sys, d, y, p, h, ynew, Y, u, LU, perm);
+  ros_step(*rp, sys, d, y, p, h, rp->s, ynew, Y, u, LU, perm);
   ros_errvec(*rp, d, u, err);
   return 0;
 }
@@ -1571,6 +1660,131 @@ int oracle_adjoint(int sys, int method, int n, int params_shared,
     for (int c = 0; c < np; ++c) gp[c] = 0.0;
     loss_lane[l] = adjoint_lane(M, L, l, y0 + (int64_t)l * d, pl, gp,
                                 grad_y0 + (int64_t)l * d);
+  }
+  return 0;
+}
+
+// ------------------------------------------------------- operation counts --
+// Floating-point operations of one unit of work, counted by running this
+// file's own step routines on the OpCount scalar (the values are irrelevant:
+// no routine branches on them except the pivot search, which counts the same
+// either way).  out[6] for (method, system):
+//   0 trial     one trial step of the record: the stages, y_new, the error
+//               estimate and its norm, the controller's proposed factor and
+//               the next step size as after a rejection
+//   1 accept    what an accepted trial adds: the acceptance bound of the
+//               controller, and f(y_new) for a pair without first-same-as-last
+//   2 side_fwd  a save-time side step of the record (stages that enter
+//               y_new, y_new; the slope at the base point is known)
+//   3 adj_step  one mesh step of the reverse sweep (recomputed stages and
+//               their vector-Jacobian products)
+//   4 adj_side  a save-time side step of the sweep: the step's reverse, its
+//               y_new formed from the recomputed stages, the sum-of-squares
+//               cotangent and loss term, and the cotangent's addition into
+//               the base point's
+//   5 adj_zero  a save on a mesh point in the sweep (cotangent, loss term,
+//               addition)
+// Time bookkeeping (t + h, the end-of-span clip, the underflow test) is not
+// counted.  Returns 0, or -1 for an unknown pair.
+int oracle_count_ops(int method, int sys, int64_t* out) {
+  const int d = sys_dim(sys), np = sys_np(sys);
+  if (d < 0 || !(erk_of(method) || is_ros(method))) return -1;
+  std::vector<OpCount> p(np);
+  for (int c = 0; c < np; ++c) p[c] = OpCount(0.5 + 0.01 * c);
+  OpCount y[DMAX], ynew[DMAX], lam[DMAX], lin[DMAX], w[DMAX];
+  std::vector<OpCount> gp(np);
+  for (int c = 0; c < d; ++c) {
+    y[c] = OpCount(0.3 + 0.1 * c);
+    lam[c] = OpCount(1.0);
+  }
+  const OpCount h(1e-3);
+  const int kroot = is_ros(method) ? ros_of(method)->q_emb + 1 : erk_of(method)->q_emb + 1;
+  auto count = [&](auto&& fn) {
+    g_ops = 0;
+    fn();
+    return g_ops;
+  };
+  int64_t update = 0;  // y_new from the stages of a replay step
+  if (is_ros(method)) {
+    const ROS& m = *ros_of(method);
+    OpCount Y[6][DMAX], u[6][DMAX], LU[DMAX * DMAX];
+    int perm[DMAX];
+    out[0] = count([&] {
+      ros_step(m, sys, d, y, p.data(), h, m.s, ynew, Y, u, LU, perm);
+      OpCount fac0 = ctrl_fac0(ros_err(m, d, y, ynew, u, 1e-6, 1e-8), kroot);
+      ctrl_reject(h, fac0);
+    });
+    out[1] = count([&] { ctrl_accept(h, OpCount(1.0), false); }) -
+             count([&] { ctrl_reject(h, OpCount(1.0)); });
+    out[2] = count([&] { ros_step(m, sys, d, y, p.data(), h, m.su, ynew, Y, u, LU, perm); });
+    update = out[2] - count([&] {
+      ros_step(m, sys, d, y, p.data(), h, m.su, (OpCount*)nullptr, Y, u, LU, perm);
+    });
+  } else {
+    const ERK& m = *erk_of(method);
+    OpCount k[SMAX][DMAX], Y[SMAX][DMAX];
+    g_ops = 0;
+    rhs(sys, y, p.data(), k[0]);  // the slope at the base point is known
+    out[0] = count([&] {
+      erk_stages(m, sys, d, y, p.data(), h, m.s, k, Y);
+      if (m.fsal) {
+        for (int c = 0; c < d; ++c) ynew[c] = Y[m.s - 1][c];
+      } else {
+        erk_update(m, d, y, h, k, ynew);
+      }
+      OpCount fac0 = ctrl_fac0(erk_err(m, d, h, y, ynew, k, 1e-6, 1e-8), kroot);
+      ctrl_reject(h, fac0);
+    });
+    out[1] = count([&] { ctrl_accept(h, OpCount(1.0), false); }) -
+             count([&] { ctrl_reject(h, OpCount(1.0)); }) +
+             (m.fsal ? 0 : count([&] { rhs(sys, ynew, p.data(), k[0]); }));
+    out[2] = count([&] {
+      erk_stages(m, sys, d, y, p.data(), h, m.s_used, k, Y);
+      erk_update(m, d, y, h, k, ynew);
+    });
+    update = count([&] { erk_update(m, d, y, h, k, ynew); });
+  }
+  out[3] = count([&] { step_vjp_any(method, sys, d, y, p.data(), h, lam, lin, gp.data()); });
+  const int64_t cot = count([&] {
+    OpCount loss(0.0);
+    for (int c = 0; c < d; ++c) loss_cot(LOSS_SUMSQ, y[c], 0.0, OpCount(2.0), loss, w[c]);
+  });
+  const int64_t add = count([&] {
+    for (int c = 0; c < d; ++c) lam[c] = lam[c] + lin[c];
+  });
+  out[4] = out[3] + update + cot + add;
+  out[5] = cot + add;
+  return 0;
+}
+
+// Operations of one evaluation of a system's f, its VJP ((df/dy)^T w with
+// the parameter terms), its Jacobian and d/d(y, p) of u^T J v (the last two
+// for the stiff systems only, else 0): out[4].
+int oracle_count_system(int sys, int64_t* out) {
+  const int d = sys_dim(sys), np = sys_np(sys);
+  if (d < 0) return -1;
+  std::vector<OpCount> p(np), gp(np);
+  for (int c = 0; c < np; ++c) p[c] = OpCount(0.5 + 0.01 * c);
+  OpCount y[DMAX], f[DMAX], w[DMAX], gy[DMAX], J[DMAX * DMAX];
+  for (int c = 0; c < d; ++c) {
+    y[c] = OpCount(0.3 + 0.1 * c);
+    w[c] = OpCount(1.0);
+  }
+  const bool stiff = sys == SYS_ROBERTSON || sys == SYS_HIRES || sys == SYS_LINEAR;
+  g_ops = 0;
+  rhs(sys, y, p.data(), f);
+  out[0] = g_ops;
+  g_ops = 0;
+  vjp(sys, y, p.data(), w, gy, gp.data());
+  out[1] = g_ops;
+  out[2] = out[3] = 0;
+  if (stiff) {
+    g_ops = 0;
+    jac(sys, y, p.data(), J);
+    out[2] = g_ops;
+    g_ops = 0;
+    jac_vjp(sys, y, p.data(), w, f, gy, gp.data());
+    out[3] = g_ops;
   }
   return 0;
 }

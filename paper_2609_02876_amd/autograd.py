@@ -48,6 +48,10 @@ class _Cfg:
 class _EnsembleODE(torch.autograd.Function):
     @staticmethod
     def forward(ctx, y0, params, cfg: _Cfg):
+        # the record reads y0 and params through their storage (the sweep
+        # reuses them); saving the inputs lets torch's version counters
+        # refuse a backward after either was changed in place
+        ctx.save_for_backward(y0, params)
         y0 = y0.detach().contiguous()
         params = params.detach().contiguous()
         if cfg.mesh is None:
@@ -67,6 +71,7 @@ class _EnsembleODE(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g, _gs):
+        ctx.saved_tensors  # raises if y0 or params changed in place since forward
         rec = ctx.rec
         if g is None:
             return None, None, None

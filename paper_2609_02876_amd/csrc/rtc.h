@@ -42,14 +42,18 @@ bool rtc_info(int sys, int* d, int* np, bool* jac) {
 }
 
 // The first construct of the source that is not plain arithmetic on the
-// arguments (control flow, preprocessor, inline assembly, shared memory,
-// synchronisation or atomics), or "" if there is none.  Comments and
-// literals are skipped.
+// arguments (control flow, preprocessor, inline assembly, compiler
+// intrinsics, shared memory, synchronisation, atomics, thread or block
+// indices), or "" if there is none.  Comments and literals are skipped.
+// Identifiers beginning with two underscores are reserved to the compiler
+// (its intrinsics among them) and refused, except the two qualifiers a
+// device function declaration needs.
 std::string refused_construct(const std::string& s) {
   static const char* const kWords[] = {
       "if", "else", "for", "while", "do", "switch", "case", "goto", "break", "continue",
-      "asm", "__asm", "__asm__", "__shared__", "__syncthreads", "volatile", "atomicAdd",
-      "atomicCAS", "atomicExch", "__builtin_amdgcn_s_barrier", "extern", "__global__"};
+      "asm", "volatile", "extern", "threadIdx", "blockIdx", "blockDim", "gridDim",
+      "warpSize"};
+  static const char* const kAllowed[] = {"__device__", "__forceinline__"};
   const size_t n = s.size();
   size_t i = 0;
   bool line_start = true;
@@ -89,6 +93,11 @@ std::string refused_construct(const std::string& s) {
       const std::string w = s.substr(i, j - i);
       for (const char* k : kWords)
         if (w == k) return "'" + w + "'";
+      if (w.compare(0, 2, "__") == 0 || w.compare(0, 6, "atomic") == 0) {
+        bool ok = false;
+        for (const char* k : kAllowed) ok = ok || w == k;
+        if (!ok) return "'" + w + "'";
+      }
       i = j;
       continue;
     }

@@ -84,3 +84,16 @@ def test_record_reuse_while_parameters_move():
     ref = O.record(O.LORENZ, O.TSIT5, y0, p, 0.0, 1.0, 1e-6, 1e-8, save_t=st)
     gp_o, _, _ = O.adjoint(O.LORENZ, O.TSIT5, y0, p2, ref)
     assert np.array_equal(P2.grad.cpu().numpy(), gp_o.T)
+
+
+def test_inplace_change_of_inputs_is_refused():
+    """The sweep reads y0 and params through their storage: a change in
+    place between forward and backward must fail (torch's version check),
+    not give a gradient at mixed inputs."""
+    y0, p = W.lorenz(64, seed=15)
+    Y0, P = _dev(y0.T), _dev(p.T, grad=True)
+    ys = AG.odeint("lorenz", "tsit5", Y0, P, 0.0, 0.5, save_times=[0.5])
+    with torch.no_grad():
+        P.mul_(1.01)
+    with pytest.raises(RuntimeError, match="modified by an inplace operation"):
+        (ys ** 2).sum().backward()

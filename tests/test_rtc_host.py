@@ -23,6 +23,11 @@ def test_register_compiles_and_names_the_system():
     ("while (false) {}", "'while'"),
     ("f[0] = T(y[0] > 0 && y[1] > 0);", "&&"),
     ("asm volatile(\"\");", "'asm'"),
+    ("f[0] = __builtin_amdgcn_readfirstlane(y[0]);", "'__builtin_amdgcn_readfirstlane'"),
+    ("f[0] = __shfl_xor(y[0], 1);", "'__shfl_xor'"),
+    ("f[0] = y[threadIdx.x % 3];", "'threadIdx'"),
+    ("atomicAdd(f, y[0]);", "'atomicAdd'"),
+    ("__syncthreads();", "'__syncthreads'"),
 ])
 def test_control_flow_is_refused(snippet, what):
     src = ("struct System { template <class T> __device__ static void rhs(const T* y, "
