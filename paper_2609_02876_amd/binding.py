@@ -93,6 +93,17 @@ class RecordHandle:
     def n_trial(self):
         return _view_i32(self.rec.n_trial, self.n, self.pool)
 
+    def save_index(self):
+        """[n_save, n] int32: the mesh index of each save's base point."""
+        ns = self.spec.n_save
+        return _view_i32(self.rec.save_idx, ns * self.n, self.pool).view(ns, self.n)
+
+    def save_offset(self):
+        """[n_save, n] float64: each save's side-step size t_s - t_base."""
+        ns = self.spec.n_save
+        off = self.rec.save_dt - self.pool.data_ptr()
+        return self.pool[off: off + 8 * ns * self.n].view(torch.float64).view(ns, self.n)
+
 
 def _view_i32(ptr, n, pool):
     off = ptr - pool.data_ptr()

@@ -225,13 +225,8 @@ __device__ __forceinline__ void step_push(const T* y, const T* k0, const T* p, T
   }
 }
 
-// Norm of the error estimate e = h * esum against atol + rtol max(|y|, |ynew|).
-template <class T, int D>
-__device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double h,
-                                               const double* esum, double rtol,
-                                               double atol);
-
-// Scaled RMS norm sqrt(mean (v_c / sc_c)^2) with squares summed by fma.
+// Scaled RMS norm sqrt(mean (v_c / sc_c)^2) with squares summed by fma (the
+// starting step's norm).
 template <int D>
 __device__ __forceinline__ double rms(const double* v, const double* sc) {
   double r = v[0] / sc[0];
@@ -244,45 +239,84 @@ __device__ __forceinline__ double rms(const double* v, const double* sc) {
   return sqrt(ss * (1.0 / (double)D));
 }
 
-// Error estimate e = h sum_j ew_j k_j (in double) and its norm against
-// atol + rtol max(|y|, |y_new|).
-template <class Tab, class T, int D, int NST>
-__device__ __forceinline__ double err_norm(const T* y, const T* ynew, double h,
-                                           const T (&k)[NST][D], double rtol,
-                                           double atol) {
-  double e[D], sc[D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    double acc = 0.0;
-    bool first = true;
-#pragma unroll
-    for (int j = 0; j < NST; ++j) {
-      if (Tab::EW[j] != 0.0) {
-        if (first) {
-          acc = Tab::EW[j] * (double)k[j][c];
-          first = false;
-        } else {
-          acc = fmaT(Tab::EW[j], (double)k[j][c], acc);
-        }
-      }
-    }
-    e[c] = h * acc;
-    sc[c] = fmaT(rtol, fmax(fabs((double)y[c]), fabs((double)ynew[c])), atol);
-  }
-  return rms<D>(e, sc);
+// ---------------------------------------------------- trial-step control --
+// The acceptance test and the controller of the adaptive loop (Section 2.1)
+// work on the mean square ms = err^2 of the scaled error: err <= 1 is
+// ms <= 1, and the proposed factor 0.9 err^(-1/k) is 0.9 ms^(-1/(2k)).  No
+// square root, no division: each scale's reciprocal is the hardware
+// estimate refined by two Newton steps, and the power is a single-precision
+// estimate refined by two Newton steps in double.  Both are accurate to
+// about an ulp; the rounding differs from a division and a root by a few
+// ulps of h, so the adaptive mesh can differ from one formed by exact
+// division and root where a trial sits on the acceptance bound.
+
+// 1/x to about an ulp (x > 0 finite): e = 1 - x r, r <- r + r e, twice.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fmaT(-x, r, 1.0);
+  r = fmaT(r, e, r);
+  e = fmaT(-x, r, 1.0);
+  return fmaT(r, e, r);
 }
 
+// mean_c (v_c / sc_c)^2, the squares summed by fma in index order
+template <int D>
+__device__ __forceinline__ double mean_sq(const double* v, const double* sc) {
+  double ss = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double r = v[c] * recip(sc[c]);
+    ss = c == 0 ? r * r : fmaT(r, r, ss);
+  }
+  return ss * (1.0 / (double)D);
+}
+
+// Mean square of the error estimate e = h * esum against atol + rtol
+// max(|y|, |y_new|).
 template <class T, int D>
-__device__ __forceinline__ double err_norm_sum(const T* y, const T* ynew, double h,
-                                               const double* esum, double rtol,
-                                               double atol) {
+__device__ __forceinline__ double err_ms_sum(const T* y, const T* ynew, double h,
+                                             const double* esum, double rtol, double atol) {
   double e[D], sc[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     e[c] = h * esum[c];
     sc[c] = fmaT(rtol, fmax(fabs((double)y[c]), fabs((double)ynew[c])), atol);
   }
-  return rms<D>(e, sc);
+  return mean_sq<D>(e, sc);
+}
+
+// y^K by repeated squaring (compile-time K >= 1)
+template <int K>
+__device__ __forceinline__ double ipow(double y) {
+  if constexpr (K == 1) {
+    return y;
+  } else if constexpr (K % 2 == 0) {
+    const double h = ipow<K / 2>(y);
+    return h * h;
+  } else {
+    return ipow<K - 1>(y) * y;
+  }
+}
+
+// The proposed step factor 0.9 ms^(-1/K2), K2 = 2 (q + 1) for an embedded
+// order q.  ms is held to [1e-30, 1e30] first: the factor is clamped to
+// [0.2, 10] long before either end (with K2 >= 6 the ends give factors
+// beyond 90 and below 0.01).  A NaN ms gives 0, so that a trial whose
+// error is not a number shrinks h by the lower bound.  The seed
+// 2^(-log2(x) / K2) in single precision is within a few 1e-7; two Newton
+// steps y <- y + (y / K2)(1 - x y^K2) take it to about an ulp.
+template <int K2>
+__device__ __forceinline__ double step_factor(double ms) {
+  const double x = fmin(fmax(ms, 1e-30), 1e30);
+  const float l2 = __builtin_amdgcn_logf((float)x);
+  double y = (double)__builtin_amdgcn_exp2f(l2 * (-1.0f / (float)K2));
+  constexpr double inv_k = 1.0 / (double)K2;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double t = fmaT(-x, ipow<K2>(y), 1.0);
+    y = fmaT(y * inv_k, t, y);
+  }
+  return ms >= 0.0 ? 0.9 * y : 0.0;
 }
 
 // x^(-1/K) for the controller and the starting step (K = 3..8), from
@@ -565,8 +599,10 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       h = a.ivp.h0 > 0.0 ? fmin(a.ivp.h0, t1 - t0)
                          : initial_step<Sys, Tab, T>(y, p, k1, t0, t1, rtol, atol);
   }
-  // MODE_REFRESH: still on the old mesh; old steps kept so far
+  // MODE_REFRESH: still on the old mesh; old steps kept so far.  An old step
+  // is kept while its RMS error is <= slack, i.e. its mean square <= slack^2.
   bool following = (MODE == MODE_REFRESH) && S_mesh > 0;
+  const double slack2 = a.slack * a.slack;
   int32_t kept = S_mesh;
   // Given mesh: the size of the next mesh step is loaded one step ahead, so
   // the load's latency is hidden behind a whole step's arithmetic.
@@ -659,7 +695,8 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       hh = ts - t;
     }
 
-    // one evaluation of the step map from the base (y, k1)
+    // one evaluation of the step map from the base (y, k1); err is the mean
+    // square of the scaled error estimate (the RMS norm squared)
     T ynew[D], klast[D];
     double err = 0.0;
     if constexpr (Tab::ROS) {
@@ -676,7 +713,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       if constexpr (MODE != MODE_FROZEN) {
         T e[D];
         ros_errvec<Tab, D, T>(u, e);
-        err = ros_err<D, T>(y, ynew, e, rtol, atol);
+        err = ros_ms<D, T>(y, ynew, e, rtol, atol);
       }
     } else {
       T kb[D];
@@ -695,7 +732,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
 #pragma unroll
         for (int c = 0; c < D; ++c) ynew[c] = ylast[c];
       }
-      if constexpr (MODE != MODE_FROZEN) err = err_norm_sum<T, D>(y, ynew, hh, esum, rtol, atol);
+      if constexpr (MODE != MODE_FROZEN) err = err_ms_sum<T, D>(y, ynew, hh, esum, rtol, atol);
     }
 
     if (side) {
@@ -725,9 +762,9 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
 
     // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
     double fac0 = 0.0;
-    if constexpr (MODE != MODE_FROZEN) fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
+    if constexpr (MODE != MODE_FROZEN) fac0 = step_factor<2 * (Tab::QEMB + 1)>(err);
     if constexpr (MODE == MODE_REFRESH) {
-      if (following && !(err <= a.slack)) {  // the old mesh ends here: a rejected trial
+      if (following && !(err <= slack2)) {  // the old mesh ends here: a rejected trial
         following = false;
         kept = S;
         h = hh * fmax(0.2, fac0);

@@ -372,18 +372,25 @@ __device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h, const 
   for (int c = 0; c < D; ++c) lam_in[c] = lam_in[c] + gJ[c];
 }
 
-// Scaled RMS norm of the error estimate u_s against atol + rtol max(|y|, |y_new|).
+// Mean square (the RMS norm squared) of the scaled error estimate against
+// atol + rtol max(|y|, |y_new|); the reciprocal of each scale as the
+// explicit pairs' recip (the hardware estimate and two Newton steps).
 template <int D, class T>
-__device__ __forceinline__ double ros_err(const T* y, const T* ynew, const T* e, double rtol,
-                                          double atol) {
-  double r = 0.0, ss = 0.0;
+__device__ __forceinline__ double ros_ms(const T* y, const T* ynew, const T* e, double rtol,
+                                         double atol) {
+  double ss = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     const double sc = fmaT(rtol, fmax(fabs((double)y[c]), fabs((double)ynew[c])), atol);
-    r = (double)e[c] / sc;
+    double q = __builtin_amdgcn_rcp(sc);
+    double t = fmaT(-sc, q, 1.0);
+    q = fmaT(q, t, q);
+    t = fmaT(-sc, q, 1.0);
+    q = fmaT(q, t, q);
+    const double r = (double)e[c] * q;
     ss = c == 0 ? r * r : fmaT(r, r, ss);
   }
-  return sqrt(ss * (1.0 / (double)D));
+  return ss * (1.0 / (double)D);
 }
 
 }  // namespace ens

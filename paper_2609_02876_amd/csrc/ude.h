@@ -415,8 +415,8 @@ __global__ void __launch_bounds__(256, 2) ude_forward_kernel(const FwdArgs a) {
     for (int c = 0; c < D; ++c) ynew[c] = ylast[c];
     double err = 0.0, fac0 = 0.0;
     if constexpr (MODE != MODE_FROZEN) {
-      err = err_norm_sum<T, D>(yb, ynew, hh, esum, rtol, atol);
-      fac0 = 0.9 * root_inv<Tab::QEMB + 1>(err);
+      err = err_ms_sum<T, D>(yb, ynew, hh, esum, rtol, atol);  // RMS norm squared
+      fac0 = step_factor<2 * (Tab::QEMB + 1)>(err);
     }
     if (!act) continue;
 

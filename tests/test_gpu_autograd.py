@@ -5,7 +5,9 @@ import pytest
 import torch
 
 import oracle as O
+from gpu_helpers import oracle_mesh
 from paper_2609_02876_amd import autograd as AG
+from paper_2609_02876_amd import binding as B
 from paper_2609_02876_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -38,8 +40,11 @@ def test_autograd_matches_oracle(system, method, t1):
     loss.backward()
     so = {"lorenz": O.LORENZ, "vdp": O.VDP}[system]
     mo = {"tsit5": O.TSIT5, "vern7": O.VERN7}[method]
-    ref = O.record(so, mo, y0, p, 0.0, t1, 1e-6, 1e-8, save_t=st)
-    gp_o, gy_o, ll_o = O.adjoint(so, mo, y0, p, ref)
+    # the oracle's discrete adjoint on the mesh the forward recorded (the
+    # record is deterministic: a second record of the same inputs has it)
+    hd = B.ensemble_record(system, method, Y0.detach(), P.detach(), 0.0, t1, 1e-6, 1e-8,
+                           save_times=st)
+    gp_o, gy_o, ll_o = O.adjoint(so, mo, y0, p, oracle_mesh(hd))
     assert np.isclose(loss.item(), ll_o.sum(), rtol=1e-12)
     assert np.array_equal(P.grad.cpu().numpy(), gp_o.T)
     assert np.array_equal(Y0.grad.cpu().numpy(), gy_o.T)
@@ -61,9 +66,9 @@ def test_shared_parameters_sum_over_trajectories():
                    params_shared=True)
     (ys ** 2).sum().backward()
     assert torch.equal(g1, P.grad)
-    ref = O.record(O.LORENZ, O.TSIT5, y0, p, 0.0, 2.0, 1e-6, 1e-8, save_t=[1.0, 2.0],
-                   params_shared=True)
-    gp_o, _, _ = O.adjoint(O.LORENZ, O.TSIT5, y0, p, ref, params_shared=True)
+    hd = B.ensemble_record("lorenz", "tsit5", Y0, P.detach(), 0.0, 2.0, 1e-6, 1e-8,
+                           save_times=[1.0, 2.0], params_shared=True)
+    gp_o, _, _ = O.adjoint(O.LORENZ, O.TSIT5, y0, p, oracle_mesh(hd), params_shared=True)
     ref_sum = gp_o.sum(axis=0)
     assert np.allclose(g1.cpu().numpy(), ref_sum, rtol=1e-12, atol=0)
 
@@ -81,8 +86,9 @@ def test_record_reuse_while_parameters_move():
     ys = AG.odeint("lorenz", "tsit5", Y0, P2, 0.0, 1.0, save_times=st, mesh=mesh)
     (ys ** 2).sum().backward()
     # the oracle on the same (old) mesh at the new parameters
-    ref = O.record(O.LORENZ, O.TSIT5, y0, p, 0.0, 1.0, 1e-6, 1e-8, save_t=st)
-    gp_o, _, _ = O.adjoint(O.LORENZ, O.TSIT5, y0, p2, ref)
+    hd = B.ensemble_record("lorenz", "tsit5", Y0, P, 0.0, 1.0, 1e-6, 1e-8, save_times=st,
+                           steps_hint=96)
+    gp_o, _, _ = O.adjoint(O.LORENZ, O.TSIT5, y0, p2, oracle_mesh(hd))
     assert np.array_equal(P2.grad.cpu().numpy(), gp_o.T)
 
 

@@ -6,15 +6,19 @@ trajectories that the oracle computes one by one.
   per-trajectory reservation);
 * 2^20 Lorenz with Vern7 and 2^20 Van der Pol (FP64), and 2^20 Van der Pol
   (Vern7) in FP32 against the FP64 oracle on the GPU's own mesh;
-* 2^18 UDE trajectories (FP32): sampled states against the oracle's
-  adaptive solve, and sampled y0-gradients against the oracle's adjoint on
-  the mesh the GPU recorded for those trajectories.
+* 2^20 Lorenz on [0, 10] in FP32: the per-trajectory error against FP64 on
+  the shared mesh, reported and bounded;
+* 2^18 UDE trajectories (FP32): sampled states and y0-gradients, per
+  trajectory, against the oracle on the mesh the GPU recorded for them.
+FP64 adaptive meshes are compared with the oracle's by their statistics,
+and states and gradients against the oracle on the GPU's own mesh.
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
+from gpu_helpers import oracle_mesh, own_mesh_parity
 from paper_2609_02876_amd import binding as B
 from paper_2609_02876_amd import workloads as W
 
@@ -47,13 +51,18 @@ def _planned_record(system, method, y0_d, p_d, t1, rtol, atol, st, shared=False)
                              pool=pool, steps_per_traj=hint, params_shared=shared)
 
 
+def _per_lane_scaled(g32, g64):
+    """FP32 gradient error per lane against max(|g_lane|, RMS over lanes)
+    (a lane whose gradient nearly vanishes has no meaningful relative error)."""
+    gn = np.linalg.norm(g64, axis=0)
+    return np.linalg.norm(g32 - g64, axis=0) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))
+
+
 @pytest.mark.parametrize("system,method,t1,dtype", [
     ("lorenz", "tsit5", 10.0, torch.float64),    # the headline workload
     ("lorenz", "vern7", 10.0, torch.float64),
     ("vdp", "tsit5", 6.3, torch.float64),
-    ("vdp", "vern7", 6.3, torch.float32),   # FP32 (chaotic Lorenz on [0, 10] amplifies
-                                            # FP32 rounding far beyond 1e-4; its FP32
-                                            # parity runs on [0, 2] in test_gpu_parity)
+    ("vdp", "vern7", 6.3, torch.float32),
 ])
 def test_full_size_sampled(system, method, t1, dtype):
     n = 1 << 20
@@ -76,50 +85,54 @@ def test_full_size_sampled(system, method, t1, dtype):
     so, mo = SYS_O[system], MET_O[method]
     if dtype == torch.float64:
         ref = O.record(so, mo, y0[idx], p[idx], 0.0, t1, 1e-6, 1e-8, save_t=st)
-        tol = 1e-11
-    else:
-        # FP32: the oracle's FP64 solution on the GPU's own (FP32) mesh
-        cap = int(rec.steps().max().item())
-        h, s = B.ensemble_mesh_export(rec, cap)
-        h = h.cpu().numpy()[:, idx].T.copy()
-        s = s.cpu().numpy()[idx]
-        ref = O.record(so, mo, y0[idx], p[idx], 0.0, t1, 1e-6, 1e-8, save_t=st)
-        ref["h"], ref["S"] = h, s
-        ref["save_idx"] = rec_save_idx(rec, idx)
-        ref["save_dt"] = rec_save_dt(rec, idx)
-        tol = 1e-4
-    gp_o, gy_o, _ = O.adjoint(so, mo, y0[idx], p[idx], ref)
-    ys_o = O.replay(so, mo, y0[idx], p[idx], ref)
+        own_mesh_parity(rec, so, mo, y0, p, ref, 1e-11, lanes=idx, gp=gp, gy=gy,
+                        label="sampled ")
+        return
+    # FP32: the oracle's FP64 solution on the GPU's own (FP32) mesh
+    gm = oracle_mesh(rec, idx)
+    gp_o, gy_o, _ = O.adjoint(so, mo, y0[idx], p[idx], gm)
+    ys_o = O.replay(so, mo, y0[idx], p[idx], gm)
     ys = rec.y_save.cpu().numpy()[..., idx].astype(np.float64)
     e_s = _rel(ys, np.transpose(ys_o, (1, 2, 0))).max()
-    gp_n = gp.cpu().numpy()[:, idx].astype(np.float64)
-    gy_n = gy.cpu().numpy()[:, idx].astype(np.float64)
-    if dtype == torch.float64:
-        e_p, e_y = _rel(gp_n, gp_o.T).max(), _rel(gy_n, gy_o.T).max()
-    else:  # per-lane scale as in the FP32 parity test (R13)
-        sc = np.sqrt(np.mean(np.sum(gp_o ** 2, axis=1)))
-        e_p = (np.linalg.norm(gp_n - gp_o.T, axis=0) / np.maximum(np.linalg.norm(gp_o, axis=1), sc)).max()
-        scy = np.sqrt(np.mean(np.sum(gy_o ** 2, axis=1)))
-        e_y = (np.linalg.norm(gy_n - gy_o.T, axis=0) / np.maximum(np.linalg.norm(gy_o, axis=1), scy)).max()
+    e_p = _per_lane_scaled(gp.cpu().numpy()[:, idx].astype(np.float64), gp_o.T).max()
+    e_y = _per_lane_scaled(gy.cpu().numpy()[:, idx].astype(np.float64), gy_o.T).max()
     print(f"  sampled: states {e_s:.2e} grad_p {e_p:.2e} grad_y0 {e_y:.2e}")
-    assert e_s <= tol and e_p <= tol and e_y <= tol
+    assert e_s <= 1e-4 and e_p <= 1e-4 and e_y <= 1e-4
 
 
-def rec_save_idx(rec, idx):
-    """Save bookkeeping of a record for the sampled trajectories ([k][n_save])."""
-    ns = rec.rec.n_save
-    n = rec.n
-    off = rec.rec.save_idx - rec.pool.data_ptr()
-    a = rec.pool[off: off + 4 * ns * n].view(torch.int32).view(ns, n).cpu().numpy()
-    return np.ascontiguousarray(a[:, idx].T)
-
-
-def rec_save_dt(rec, idx):
-    ns = rec.rec.n_save
-    n = rec.n
-    off = rec.rec.save_dt - rec.pool.data_ptr()
-    a = rec.pool[off: off + 8 * ns * n].view(torch.float64).view(ns, n).cpu().numpy()
-    return np.ascontiguousarray(a[:, idx].T)
+def test_fp32_lorenz_headline_span_error():
+    """FP32 on the headline span: 2^20 Lorenz trajectories on [0, 10] in
+    single precision against the FP64 oracle on the same (the GPU's) mesh,
+    256 sampled trajectories.  The chaotic flow amplifies FP32 rounding by
+    about e^(0.9 t) ~ 8e3 over the span, so the 1e-4 bar of the shorter
+    FP32 cases does not hold for every trajectory here; the per-trajectory
+    errors are reported (median, p99, max) and bounded as stated: median
+    below 1e-3, p99 below 1e-1."""
+    n = 1 << 20
+    t1 = 10.0
+    print(f"case fp32 lorenz headline span n={n}", flush=True)
+    y0, p = W.lorenz(n, seed=0)
+    y0 = y0.astype(np.float32).astype(np.float64)
+    p = p.astype(np.float32).astype(np.float64)
+    st = list(W.save_times(0.0, t1, 20))
+    y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=torch.float32, device="cuda")
+    p_d = torch.tensor(np.ascontiguousarray(p.T), dtype=torch.float32, device="cuda")
+    rec = _planned_record("lorenz", "tsit5", y0_d, p_d, t1, 1e-6, 1e-8, st)
+    gp, gy, _ = B.ensemble_adjoint(rec)
+    torch.cuda.synchronize()
+    assert np.all(rec.status.cpu().numpy() == 0)
+    idx = np.sort(np.random.default_rng(3).choice(n, 256, replace=False))
+    gm = oracle_mesh(rec, idx)
+    gp_o, gy_o, _ = O.adjoint(O.LORENZ, O.TSIT5, y0[idx], p[idx], gm)
+    ys_o = np.transpose(O.replay(O.LORENZ, O.TSIT5, y0[idx], p[idx], gm), (1, 2, 0))
+    ys = rec.y_save.cpu().numpy()[..., idx].astype(np.float64)
+    e = {"states": _rel(ys, ys_o),
+         "grad_p": _rel(gp.cpu().numpy()[:, idx].astype(np.float64), gp_o.T),
+         "grad_y0": _rel(gy.cpu().numpy()[:, idx].astype(np.float64), gy_o.T)}
+    for k, v in e.items():
+        print(f"  {k}: per-trajectory relative error median {np.median(v):.2e} "
+              f"p99 {np.quantile(v, 0.99):.2e} max {v.max():.2e}", flush=True)
+        assert np.median(v) <= 1e-3 and np.quantile(v, 0.99) <= 1e-1
 
 
 def test_ude_max_size_sampled():
@@ -138,22 +151,15 @@ def test_ude_max_size_sampled():
     assert np.all(np.isfinite(gp.cpu().numpy()))
     idx = np.sort(np.random.default_rng(2).choice(n, 32, replace=False))
     idx[-1] = n - 1
-    # states against the oracle's own adaptive solve (both at tolerance 1e-6)
-    ref = O.record(O.LV_UDE, O.TSIT5, y0[idx], th, 0.0, 10.0, 1e-6, 1e-6, save_t=st,
-                   params_shared=True)
+    # per trajectory, normwise: the FP32 states and y0-gradients against the
+    # FP64 oracle on the mesh the GPU recorded for these trajectories
+    gm = oracle_mesh(rec, idx)
+    ys_o = np.transpose(O.replay(O.LV_UDE, O.TSIT5, y0[idx], th, gm, params_shared=True),
+                        (1, 2, 0))
+    _, gy_o, _ = O.adjoint(O.LV_UDE, O.TSIT5, y0[idx], th, gm, params_shared=True)
     ys = rec.y_save.cpu().numpy()[..., idx].astype(np.float64)
-    ys_o = np.transpose(ref["y_save"], (1, 2, 0))
-    e_s = np.abs(ys - ys_o).max() / np.abs(ys_o).max()
-    # y0-gradients against the oracle's adjoint on the GPU's mesh of these lanes
-    cap = int(rec.steps().max().item())
-    h, s = B.ensemble_mesh_export(rec, cap)
-    mesh = dict(ref)
-    mesh["h"] = h.cpu().numpy()[:, idx].T.copy()
-    mesh["S"] = s.cpu().numpy()[idx]
-    mesh["save_idx"] = rec_save_idx(rec, idx)
-    mesh["save_dt"] = rec_save_dt(rec, idx)
-    _, gy_o, _ = O.adjoint(O.LV_UDE, O.TSIT5, y0[idx], th, mesh, params_shared=True)
-    gy_n = gy.cpu().numpy()[:, idx].astype(np.float64)
-    e_y = np.abs(gy_n - gy_o.T).max() / np.abs(gy_o).max()
-    print(f"  sampled: states {e_s:.2e} grad_y0 {e_y:.2e}")
-    assert e_s <= 1e-4 and e_y <= 1e-4
+    e_s = _rel(ys, ys_o)
+    e_y = _rel(gy.cpu().numpy()[:, idx].astype(np.float64), gy_o.T)
+    print(f"  sampled per trajectory: states median {np.median(e_s):.2e} max {e_s.max():.2e}; "
+          f"grad_y0 median {np.median(e_y):.2e} max {e_y.max():.2e}")
+    assert e_s.max() <= 1e-4 and e_y.max() <= 1e-4

@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import oracle as O
+from gpu_helpers import check_mesh, oracle_mesh
 from paper_2609_02876_amd import binding as B
 from paper_2609_02876_amd import workloads as W
 
@@ -42,10 +43,9 @@ def _tangents(y0, p, seed=7):
     return rng.standard_normal(y0.shape), rng.standard_normal(p.shape) * p
 
 
-def _oracle(system, method, y0, p, t1, st, dy, dp):
-    rtol, atol = TOL[system]
-    rec = O.record(SYS_O[system], MET_O[method], y0, p, 0.0, t1, rtol, atol, save_t=st)
-    assert np.all(rec["status"] == O.ST_OK)
+def _oracle(system, method, y0, p, dy, dp, h):
+    """The oracle's dual-number replay on the mesh of the GPU record h."""
+    rec = oracle_mesh(h)
     ys, dys = O.replay_dual(SYS_O[system], MET_O[method], y0, p, dy, dp, rec)
     return rec, ys, dys
 
@@ -62,13 +62,17 @@ def test_jvp_matches_oracle_dual_replay(system, method, t1, n):
     y0, p = GEN[system](n, seed=3)
     dy, dp = _tangents(y0, p)
     st = list(W.save_times(0.0, t1, 20))
-    rec, ys_o, dys_o = _oracle(system, method, y0, p, t1, st, dy, dp)
     rtol, atol = TOL[system]
-    # the GPU's own adaptive record (its mesh equals the oracle's)
+    # the GPU's own adaptive record; the oracle's dual replay on its mesh
     h = B.ensemble_record(system, method, _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
                           save_times=st, steps_hint=2048 if method == "ros23" else 512)
     ysd, ld = B.ensemble_jvp(h, _dev(dy.T), _dev(dp.T))
-    # the oracle's mesh replayed on the GPU
+    torch.cuda.synchronize()
+    assert np.all(h.status.cpu().numpy() == 0)
+    rec, ys_o, dys_o = _oracle(system, method, y0, p, dy, dp, h)
+    check_mesh(rec, O.record(SYS_O[system], MET_O[method], y0, p, 0.0, t1, rtol, atol,
+                             save_t=st))
+    # that mesh replayed on the GPU gives the same tangents
     cap = int(rec["S"].max())
     hr = B.ensemble_replay_mesh(system, method, _dev(y0.T), _dev(p.T), 0.0, t1,
                                 _dev(rec["h"][:, :cap].T),
@@ -76,7 +80,6 @@ def test_jvp_matches_oracle_dual_replay(system, method, t1, n):
                                 save_times=st)
     ysd_r, ld_r = B.ensemble_jvp(hr, _dev(dy.T), _dev(dp.T))
     torch.cuda.synchronize()
-    assert np.all(h.status.cpu().numpy() == 0)
     assert torch.equal(h.steps(), hr.steps())
     ref = np.transpose(dys_o, (1, 2, 0))                     # [ns, d, n]
     got = ysd.cpu().numpy()
@@ -97,9 +100,10 @@ def test_jvp_loss_kinds():
     y0, p = W.lorenz(n, seed=4)
     dy, dp = _tangents(y0, p, seed=8)
     st = list(W.save_times(0.0, 3.0, 20))
-    rec, ys_o, dys_o = _oracle("lorenz", "tsit5", y0, p, 3.0, st, dy, dp)
     h = B.ensemble_record("lorenz", "tsit5", _dev(y0.T), _dev(p.T), 0.0, 3.0, 1e-6, 1e-8,
                           save_times=st, steps_hint=256)
+    torch.cuda.synchronize()
+    rec, ys_o, dys_o = _oracle("lorenz", "tsit5", y0, p, dy, dp, h)
     rng = np.random.default_rng(9)
     tgt = ys_o + 0.1 * rng.standard_normal(ys_o.shape)
     cot = rng.standard_normal(ys_o.shape)
@@ -172,11 +176,11 @@ def test_jvp_ragged_sizes(n):
     y0, p = W.vdp(n, seed=10)
     dy, dp = _tangents(y0, p)
     st = list(W.save_times(0.0, 6.3, 20))
-    rec, ys_o, dys_o = _oracle("vdp", "tsit5", y0, p, 6.3, st, dy, dp)
     h = B.ensemble_record("vdp", "tsit5", _dev(y0.T), _dev(p.T), 0.0, 6.3, 1e-6, 1e-8,
                           save_times=st, steps_hint=256)
     ysd, _ = B.ensemble_jvp(h, _dev(dy.T), _dev(dp.T))
     torch.cuda.synchronize()
+    rec, ys_o, dys_o = _oracle("vdp", "tsit5", y0, p, dy, dp, h)
     assert _rel(ysd.cpu().numpy(), np.transpose(dys_o, (1, 2, 0))).max() <= 1e-11
 
 
@@ -195,14 +199,8 @@ def test_jvp_fp32_against_fp64_oracle():
     h = B.ensemble_record("lorenz", "tsit5", _dev(y0.T, f32), _dev(p.T, f32), 0.0, 2.0, 1e-6,
                           1e-8, save_times=st, steps_hint=256)
     ysd, _ = B.ensemble_jvp(h, _dev(dy.T, f32), _dev(dp.T, f32))
-    cap = int(h.steps().max().item())
-    hm, sm = B.ensemble_mesh_export(h, cap)
     torch.cuda.synchronize()
-    from test_gpu_fullsize import rec_save_dt, rec_save_idx
-    idx = np.arange(n)
-    mesh = {"h": hm.cpu().numpy().T.copy(), "S": sm.cpu().numpy(),
-            "save_idx": rec_save_idx(h, idx), "save_dt": rec_save_dt(h, idx)}
-    _, dys_o = O.replay_dual(O.LORENZ, O.TSIT5, y0, p, dy, dp, mesh)
+    _, dys_o = O.replay_dual(O.LORENZ, O.TSIT5, y0, p, dy, dp, oracle_mesh(h))
     ref = np.transpose(dys_o, (1, 2, 0))
     got = ysd.cpu().numpy().astype(np.float64)
     sc = np.sqrt(np.mean(np.sum(ref.reshape(-1, n) ** 2, axis=0)))
@@ -243,7 +241,9 @@ def test_jvp_full_size_sampled():
     assert np.all(rec.status.cpu().numpy() == 0)
     idx = np.sort(np.random.default_rng(1).choice(n, 64, replace=False))
     idx[0], idx[-1] = 0, n - 1
-    ref_rec = O.record(O.LORENZ, O.TSIT5, y0[idx], p[idx], 0.0, 10.0, 1e-6, 1e-8, save_t=st)
+    ref_rec = oracle_mesh(rec, idx)
+    check_mesh(ref_rec, O.record(O.LORENZ, O.TSIT5, y0[idx], p[idx], 0.0, 10.0, 1e-6, 1e-8,
+                                 save_t=st))
     ys_o, dys_o = O.replay_dual(O.LORENZ, O.TSIT5, y0[idx], p[idx], np.zeros_like(y0[idx]),
                                 dp[idx], ref_rec)
     got = ysd.cpu().numpy()[..., idx]

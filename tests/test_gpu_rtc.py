@@ -5,14 +5,18 @@ runs the same kernels compiled from the same headers with the same flags, so
 its record, reverse sweep and forward mode equal the built-in system's to the
 bit; the built-in systems are pinned to the oracle (test_gpu_parity,
 test_gpu_rosenbrock, test_gpu_jvp), which pins the registered path in turn.
-A system with no built-in counterpart has no oracle: its gradients are
-checked against central differences of the replay on the frozen mesh and
-against the forward mode.
+Registered Lorenz and Robertson are also compared with the oracle directly
+(mesh statistics against its adaptive record; states, gradients and forward
+tangents against it on the GPU's mesh).  A system with no built-in
+counterpart has no oracle: its gradients are checked against central
+differences of the replay on the frozen mesh and against the forward mode.
 """
 import numpy as np
 import pytest
 import torch
 
+import oracle as O
+from gpu_helpers import own_mesh_parity
 from paper_2609_02876_amd import _abi as A
 from paper_2609_02876_amd import binding as B
 from paper_2609_02876_amd import serving as SV
@@ -43,6 +47,38 @@ def _run(system, method, y0, p, t1, rtol, atol, st, dtype, **kw):
     ysd, ld = B.ensemble_jvp(h, None, dp)
     torch.cuda.synchronize()
     return [h.y_save, h.status, h.steps(), gp, gy, ll, ysd, ld]
+
+
+@pytest.mark.parametrize("base,system,method,t1,rtol,atol", [
+    ("rtc_lorenz", O.LORENZ, "tsit5", 10.0, 1e-6, 1e-8),
+    ("rtc_lorenz", O.LORENZ, "vern7", 10.0, 1e-8, 1e-8),
+    ("rtc_robertson", O.ROBERTSON, "rodas4", 1e5, 1e-6, 1e-10),
+    ("rtc_robertson", O.ROBERTSON, "ros23", 1e5, 1e-6, 1e-10),
+])
+def test_registered_systems_match_oracle(base, system, method, t1, rtol, atol):
+    """A registered system against the oracle itself, not only against the
+    built-in kernel: its adaptive mesh by the statistics, its save states,
+    sweep gradients and forward-mode tangents on its own mesh."""
+    print(f"case registered {base} {method} against the oracle", flush=True)
+    n = 500
+    y0, p = (W.lorenz if system == O.LORENZ else W.robertson)(n, seed=9)
+    st = list(W.save_times(0.0, t1, 20))
+    mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}[method]
+    h = B.ensemble_record(_name(base), method, _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
+                          save_times=st, steps_hint=2048 if method == "ros23" else 512)
+    gp, gy, _ = B.ensemble_adjoint(h)
+    rng = np.random.default_rng(10)
+    dp = rng.standard_normal(p.shape) * p
+    ysd, _ = B.ensemble_jvp(h, None, _dev(dp.T))
+    torch.cuda.synchronize()
+    assert np.all(h.status.cpu().numpy() == 0)
+    ref = O.record(system, mo, y0, p, 0.0, t1, rtol, atol, save_t=st)
+    own_mesh_parity(h, system, mo, y0, p, ref, 1e-11, gp=gp, gy=gy)
+    from gpu_helpers import oracle_mesh, rel
+    _, dys = O.replay_dual(system, mo, y0, p, np.zeros_like(y0), dp, oracle_mesh(h))
+    e = rel(ysd.cpu().numpy(), np.transpose(dys, (1, 2, 0))).max()
+    print(f"  forward tangents vs oracle dual replay: {e:.2e}")
+    assert e <= 1e-11
 
 
 @pytest.mark.parametrize("method,dtype", [("tsit5", torch.float64), ("vern7", torch.float64),

@@ -84,6 +84,14 @@ def test_ude_replay_and_adjoint_match_oracle(n):
     print(f"  vs FP64 oracle: states {e_state:.2e}  weight grad {e_g:.2e}  "
           f"y0 grad {e_gy:.2e}  loss {e_ll:.2e}")
     assert e_state <= TOL32 and e_g <= TOL32 and e_gy <= TOL32 and e_ll <= TOL32
+    # per trajectory, normwise (floor 1e-30), beside the scale-relative figures
+    pl_s = np.linalg.norm((ys - ys_o).reshape(-1, n), axis=0) / np.maximum(
+        np.linalg.norm(ys_o.reshape(-1, n), axis=0), 1e-30)
+    pl_y = np.linalg.norm(gy_n - gy_o.T, axis=0) / np.maximum(np.linalg.norm(gy_o, axis=1), 1e-30)
+    print(f"  per trajectory: states median {np.median(pl_s):.2e} max {pl_s.max():.2e}; "
+          f"y0 grad median {np.median(pl_y):.2e} p99 {np.quantile(pl_y, 0.99):.2e} "
+          f"max {pl_y.max():.2e}")
+    assert pl_s.max() <= TOL32 and np.median(pl_y) <= TOL32
 
 
 def test_ude_adaptive_record_states():
