@@ -336,6 +336,26 @@ int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* 
 int ensemble_system_register(const char* source, int dim, int nparams, int has_jacobian,
                              int* system);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc:
+ * ensemble_adjoint with its workspace taken from a library-owned device array
+ * of ENS_STATIC_WORKSPACE_BYTES on each GPU (a file-scope static; each GPU
+ * the library runs on holds one until the process ends) instead of a caller
+ * buffer.  Arguments and results as ensemble_adjoint; the caller still
+ * provides every input and output.  A record whose
+ * ensemble_adjoint_workspace_bytes exceeds ENS_STATIC_WORKSPACE_BYTES is
+ * refused (ENS_EINVAL, with the sizes in the message): at 20 save times that
+ * is about 2^17 FP64 Lorenz trajectories.  Calls no allocating routine.  The
+ * array is shared by every call on a GPU and keeps the last call's contents
+ * (nothing in it must start at zero): calls that overlap on one GPU -- on
+ * different streams, or from different host threads without ordering --
+ * race and give wrong results. */
+#define ENS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int ensemble_adjoint_static(const ens_problem* prob, const ens_ivp* ivp,
+                            const ens_record* rec, const ens_loss* loss,
+                            void* grad_params, void* grad_y0, double* loss_out,
+                            void* stream);
+
 /* Workspace ensemble_adjoint needs for this record: per-block partial sums
  * for shared parameters, one segment of step records per trajectory for a
  * checkpointed tape, and each save's cotangent for the state its side step

@@ -87,9 +87,11 @@ class ServerStats(C.Structure):
 
 JOB_WAITING, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, -1
 
+STATIC_WORKSPACE_BYTES = 64 << 20   # ENS_STATIC_WORKSPACE_BYTES
+
 EXPORTS = ("ensemble_solve", "ensemble_record_bytes", "ensemble_record",
            "ensemble_replay_mesh", "ensemble_refresh", "ensemble_mesh_export",
-           "ensemble_adjoint",
+           "ensemble_adjoint", "ensemble_adjoint_static",
            "ensemble_adjoint_workspace_bytes", "ensemble_jvp", "ensemble_system_register",
            "ensemble_record_stats",
            "ensemble_server_create", "ensemble_server_submit", "ensemble_server_progress",
@@ -122,6 +124,8 @@ def load(build_if_missing=True):
     lib.ensemble_mesh_export.argtypes = [C.POINTER(Record), Ptr, Ptr, C.c_int64, Ptr]
     lib.ensemble_adjoint.argtypes = [P, V, C.POINTER(Record), C.POINTER(Loss), Ptr, Ptr, Ptr,
                                      Ptr, C.c_size_t, Ptr]
+    lib.ensemble_adjoint_static.argtypes = [P, V, C.POINTER(Record), C.POINTER(Loss), Ptr, Ptr,
+                                            Ptr, Ptr]
     lib.ensemble_adjoint_workspace_bytes.argtypes = [C.POINTER(Record), C.POINTER(C.c_size_t)]
     lib.ensemble_jvp.argtypes = [P, V, C.POINTER(Record), Ptr, Ptr, C.POINTER(Loss), Ptr, Ptr,
                                  Ptr]

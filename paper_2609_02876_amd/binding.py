@@ -306,6 +306,36 @@ def ensemble_adjoint(handle, loss="sumsq", data=None, scale=1.0, want_y0=True,
     return gp, gy, ll
 
 
+def ensemble_adjoint_static(handle, loss="sumsq", data=None, scale=1.0, want_y0=True,
+                            want_loss=True, out=None):
+    """ensemble_adjoint with the library's static device workspace (no
+    workspace is allocated for it).  out = (grad_params, grad_y0, loss)
+    tensors to write into (any may be None); missing outputs are allocated
+    here, by torch, as ensemble_adjoint does."""
+    spec = handle.spec
+    if loss not in _LOSS:
+        raise ValueError(f"loss must be one of {sorted(_LOSS)}")
+    if data is not None:
+        _require_gpu(data)
+        if data.dtype != spec.dtype or tuple(data.shape) != (spec.n_save, spec.d, spec.n):
+            raise ValueError(f"loss data must be [{spec.n_save}, {spec.d}, {spec.n}] {spec.dtype}")
+    dev = spec.y0.device
+    shared = bool(spec.prob.params_shared)
+    gp, gy, ll = out if out is not None else (None, None, None)
+    if gp is None:
+        gp = torch.empty((spec.npar,) if shared else (spec.npar, spec.n), dtype=spec.dtype,
+                         device=dev)
+    if gy is None and want_y0:
+        gy = torch.empty((spec.d, spec.n), dtype=spec.dtype, device=dev)
+    if ll is None and want_loss:
+        ll = torch.empty(spec.n, dtype=torch.float64, device=dev)
+    lo = A.Loss(_LOSS[loss], data.data_ptr() if data is not None else None, float(scale))
+    A.check(A.load().ensemble_adjoint_static(C.byref(spec.prob), C.byref(spec.ivp),
+                                             C.byref(handle.rec), C.byref(lo), _ptr(gp),
+                                             _ptr(gy), _ptr(ll), _stream()))
+    return gp, gy, ll
+
+
 def ensemble_jvp(handle, dy0=None, dparams=None, loss="sumsq", data=None, scale=1.0,
                  want_states=True, want_loss=True):
     """Forward mode on the recorded mesh: (y_save_dot [n_save, d, n] or None,

@@ -716,10 +716,74 @@ int ensemble_adjoint_workspace_bytes(const ens_record* r, size_t* bytes) {
   return ENS_OK;
 }
 
+namespace {
+int adjoint_impl(const ens_problem* p, const ens_ivp* v, const ens_record* r,
+                 const ens_loss* loss, void* grad_params, void* grad_y0, double* loss_out,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+// The workspace of ensemble_adjoint_static: one copy of this array on each
+// GPU the library runs on.  In host code its name is only a stand-in, never a
+// device address; the address comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[ENS_STATIC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// This device's copy of the scratch array.
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(ENS_EUNSUPPORTED, "device %d: the static workspace serves devices 0..%d", dev,
+                kMaxDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || ((uintptr_t)ptr & 255) != 0)
+      return fail(ENS_EHIP, "the static workspace has no 256-byte aligned device address");
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return ENS_OK;
+}
+}  // namespace
+
 int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
                      const ens_record* r, const ens_loss* loss,
                      void* grad_params, void* grad_y0, double* loss_out,
                      void* workspace, size_t workspace_bytes, void* stream) {
+  return adjoint_impl(p, v, r, loss, grad_params, grad_y0, loss_out, workspace,
+                      workspace_bytes, stream);
+}
+
+int ensemble_adjoint_static(const ens_problem* p, const ens_ivp* v,
+                            const ens_record* r, const ens_loss* loss,
+                            void* grad_params, void* grad_y0, double* loss_out,
+                            void* stream) {
+  if (!r) return fail(ENS_EINVAL, "record is NULL");
+  size_t need = 0;
+  int rc = ensemble_adjoint_workspace_bytes(r, &need);
+  if (rc != ENS_OK) return rc;
+  if (need > ENS_STATIC_WORKSPACE_BYTES)
+    return fail(ENS_EINVAL,
+                "this adjoint needs %zu bytes of workspace; the static workspace holds %zu "
+                "(use ensemble_adjoint with a caller buffer)",
+                need, (size_t)ENS_STATIC_WORKSPACE_BYTES);
+  void* ws = nullptr;
+  if ((rc = scratch_of_current_device(&ws)) != ENS_OK) return rc;
+  return adjoint_impl(p, v, r, loss, grad_params, grad_y0, loss_out, ws,
+                      (size_t)ENS_STATIC_WORKSPACE_BYTES, stream);
+}
+
+namespace {
+int adjoint_impl(const ens_problem* p, const ens_ivp* v, const ens_record* r,
+                 const ens_loss* loss, void* grad_params, void* grad_y0, double* loss_out,
+                 void* workspace, size_t workspace_bytes, void* stream) {
   SysInfo si;
   int rc;
   if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
@@ -807,6 +871,7 @@ int ensemble_adjoint(const ens_problem* p, const ens_ivp* v,
     return e == hipSuccess ? ENS_OK : hip_fail(e, "adjoint launch");
   });
 }
+}  // namespace
 
 int ensemble_jvp(const ens_problem* p, const ens_ivp* v, const ens_record* r,
                  const void* dy0, const void* dparams, const ens_loss* loss,
