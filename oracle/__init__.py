@@ -67,13 +67,13 @@ def _load():
                                        D, L, _d, _i32, _i32, _i32, _d, _d, _i64, _i32]
         lib.oracle_record.argtypes = [I, I, I, I, _d, _d, D, D, D, D, D, L, I, _d, L,
                                       _d, _i32, _i32, _i32, _d, _d, _i64]
-        lib.oracle_replay.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d, _d]
+        lib.oracle_replay.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d, _d, I]
         lib.oracle_replay_dual.argtypes = [I, I, I, _d, _d, _d, _d, L, _d, _i32, I,
-                                           _i32, _d, _d, _d]
+                                           _i32, _d, _d, _d, I]
         lib.oracle_replay_complex.argtypes = [I, I, I, _d, _d, _d, _d, D, L, _d, _i32,
-                                              I, _i32, _d, _d, _d]
+                                              I, _i32, _d, _d, _d, I]
         lib.oracle_adjoint.argtypes = [I, I, I, I, _d, _d, L, _d, _i32, I, _i32, _d,
-                                       I, _d, D, _d, _d, _d]
+                                       I, _d, D, _d, _d, _d, I]
         lib.oracle_count_ops.argtypes = [I, I, _i64]
         lib.oracle_count_system.argtypes = [I, _i64]
         for f in ("oracle_count_ops", "oracle_count_system", "oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp", "oracle_jac",
@@ -248,29 +248,32 @@ def _mesh(mesh):
             np.ascontiguousarray(mesh["save_idx"], np.int32), _f64(mesh["save_dt"]))
 
 
-def replay(system, method, y0, p, mesh, params_shared=False):
+def replay(system, method, y0, p, mesh, params_shared=False, dense=False):
+    """Save states on a frozen mesh: by one extra step from each save's base
+    point, or (dense) by the continuous extension of the step holding it."""
     y0, p = _f64(y0), _f64(p)
     h, cap, S, sidx, sdt = _mesh(mesh)
     n, d = y0.shape
     ns = sidx.shape[1]
     ys = np.zeros((n, ns, d))
     _load().oracle_replay(system, method, n, int(params_shared), _p(y0), _p(p), cap, _p(h),
-                          _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(ys))
+                          _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(ys), int(dense))
     return ys
 
 
-def replay_dual(system, method, y0, p, dy0, dp, mesh):
+def replay_dual(system, method, y0, p, dy0, dp, mesh, dense=False):
     y0, p, dy0, dp = _f64(y0), _f64(p), _f64(dy0), _f64(dp)
     h, cap, S, sidx, sdt = _mesh(mesh)
     n, d = y0.shape
     ns = sidx.shape[1]
     ys = np.zeros((n, ns, d)); dys = np.zeros((n, ns, d))
     _load().oracle_replay_dual(system, method, n, _p(y0), _p(p), _p(dy0), _p(dp), cap, _p(h),
-                               _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(ys), _p(dys))
+                               _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(ys), _p(dys),
+                               int(dense))
     return ys, dys
 
 
-def replay_complex(system, method, y0, p, dy0, dp, eps, mesh):
+def replay_complex(system, method, y0, p, dy0, dp, eps, mesh, dense=False):
     y0, p, dy0, dp = _f64(y0), _f64(p), _f64(dy0), _f64(dp)
     h, cap, S, sidx, sdt = _mesh(mesh)
     n, d = y0.shape
@@ -278,13 +281,14 @@ def replay_complex(system, method, y0, p, dy0, dp, eps, mesh):
     re = np.zeros((n, ns, d)); im = np.zeros((n, ns, d))
     _load().oracle_replay_complex(system, method, n, _p(y0), _p(p), _p(dy0), _p(dp), eps, cap,
                                   _p(h), _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), _p(re),
-                                  _p(im))
+                                  _p(im), int(dense))
     return re, im
 
 
 def adjoint(system, method, y0, p, mesh, loss_kind=LOSS_SUMSQ, loss_data=None, scale=1.0,
-            params_shared=False):
-    """Discrete adjoint on a frozen mesh: (grad_p [n][P], grad_y0 [n][d], loss [n])."""
+            params_shared=False, dense=False):
+    """Discrete adjoint on a frozen mesh: (grad_p [n][P], grad_y0 [n][d], loss [n]);
+    dense: the save states from the continuous extension."""
     y0, p = _f64(y0), _f64(p)
     h, cap, S, sidx, sdt = _mesh(mesh)
     n, d = y0.shape
@@ -294,5 +298,6 @@ def adjoint(system, method, y0, p, mesh, loss_kind=LOSS_SUMSQ, loss_data=None, s
     ld = _f64(loss_data) if loss_data is not None else None
     _load().oracle_adjoint(system, method, n, int(params_shared), _p(y0), _p(p), cap, _p(h),
                            _p(S, _i32), ns, _p(sidx, _i32), _p(sdt), loss_kind,
-                           _p(ld) if ld is not None else None, scale, _p(gp), _p(gy), _p(ll))
+                           _p(ld) if ld is not None else None, scale, _p(gp), _p(gy), _p(ll),
+                           int(dense))
     return gp, gy, ll

@@ -855,7 +855,40 @@ struct MeshArgs {
   int n_save;
   const int32_t* save_idx;  // [n][n_save]
   const double* save_dt;    // [n][n_save]
+  int dense = 0;            // save states by the continuous extension (below)
 };
+
+// ------------------------------------------------------------ dense output --
+// Dense output (the continuous extension of an accepted step, Section 3.2):
+// the state at t_i + theta h inside the step from y_i to y_{i+1} is the cubic
+// Hermite interpolant of the two end states and their slopes f_i = f(y_i),
+// f_{i+1} = f(y_{i+1}) (Hairer, Norsett & Wanner I, Sec. II.6):
+//   y(theta) = a0 y_i + a1 y_{i+1} + h (c0 f_i + c1 f_{i+1}),
+//   a0 = (1 - theta)^2 (1 + 2 theta),  a1 = theta^2 (3 - 2 theta),
+//   c0 = theta (1 - theta)^2,          c1 = -theta^2 (1 - theta),
+// with theta = (t_s - t_i) / h.  It takes the step's end values exactly
+// (theta = 0 and 1), is exact for cubic solutions, and its local error is
+// O(h^4).  A save at or after the last mesh point is y_S.
+struct Hermite {
+  double a0, a1, c0, c1;
+};
+static Hermite hermite(double theta) {
+  const double u = 1.0 - theta;
+  return Hermite{u * u * (1.0 + 2.0 * theta), theta * theta * (3.0 - 2.0 * theta),
+                 theta * u * u, -(theta * theta) * u};
+}
+
+// The dense state from (y_i, y_{i+1}) over a step of size h at offset dt.
+template <class T, class P>
+static void dense_state(int sys, int d, const T* y0, const T* y1, const P* p, double h,
+                        double dt, T* out) {
+  const Hermite H = hermite(dt / h);
+  T f0[DMAX], f1[DMAX];
+  rhs(sys, y0, p, f0);
+  rhs(sys, y1, p, f1);
+  for (int c = 0; c < d; ++c)
+    out[c] = T(H.a0) * y0[c] + T(H.a1) * y1[c] + T(h) * (T(H.c0) * f0[c] + T(H.c1) * f1[c]);
+}
 
 // Replay one lane in scalar type T; writes the save-time states.
 // One replay step Phi(y; h) of the chosen method.
@@ -874,6 +907,20 @@ static void replay_lane(const MeshArgs& M, int lane, const T* y0, const T* p,
   for (int c = 0; c < d; ++c) y[c] = y0[c];
   int s = 0;
   for (int i = 0; i <= S; ++i) {
+    if (M.dense) {
+      if (i == S) {  // saves at the last mesh point: the state itself
+        for (; s < M.n_save; ++s)
+          for (int c = 0; c < d; ++c) ysave[s * d + c] = y[c];
+        break;
+      }
+      T yn[DMAX];
+      phi_any(M.method, M.sys, d, y, p, T(hrow[i]), yn);
+      // saves inside this step: the continuous extension
+      for (; s < M.n_save && sidx[s] == i; ++s)
+        dense_state(M.sys, d, y, yn, p, hrow[i], sdt[s], ysave + s * d);
+      for (int c = 0; c < d; ++c) y[c] = yn[c];
+      continue;
+    }
     // saves whose base is y_i
     while (s < M.n_save && sidx[s] == i) {
       phi_any(M.method, M.sys, d, y, p, T(sdt[s]), ysave + s * d);
@@ -967,10 +1014,19 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
   for (int i = 0; i < S; ++i)
     phi_any(M.method, M.sys, d, &ys[(size_t)i * d], p, hrow[i], &ys[(size_t)(i + 1) * d]);
 
-  // save-time states (one extra step from the base mesh point)
+  // save-time states (one extra step from the base mesh point, or the
+  // continuous extension of the step that holds the save time)
   std::vector<double> ysave((size_t)M.n_save * d);
-  for (int s = 0; s < M.n_save; ++s)
-    phi_any(M.method, M.sys, d, &ys[(size_t)sidx[s] * d], p, sdt[s], &ysave[(size_t)s * d]);
+  for (int s = 0; s < M.n_save; ++s) {
+    if (!M.dense) {
+      phi_any(M.method, M.sys, d, &ys[(size_t)sidx[s] * d], p, sdt[s], &ysave[(size_t)s * d]);
+    } else if (sidx[s] == S) {
+      for (int c = 0; c < d; ++c) ysave[(size_t)s * d + c] = ys[(size_t)S * d + c];
+    } else {
+      dense_state(M.sys, d, &ys[(size_t)sidx[s] * d], &ys[(size_t)(sidx[s] + 1) * d], p,
+                  hrow[sidx[s]], sdt[s], &ysave[(size_t)s * d]);
+    }
+  }
 
   // loss and save-time cotangents
   double loss = 0.0;
@@ -989,14 +1045,44 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
   // steps in gp is not fixed by the method; this one every sweep layout on
   // the device reproduces).
   std::vector<double> lsave((size_t)M.n_save * d);
-  for (int s2 = M.n_save - 1; s2 >= 0; --s2)
-    step_vjp_any(M.method, M.sys, d, &ys[(size_t)sidx[s2] * d], p, sdt[s2], &wbar[s2 * d],
-                 &lsave[(size_t)s2 * d], gp);
+  // dense output: each save's cotangent reaches both end states of its step;
+  // collected per mesh point first, added as the sweep reaches the point
+  std::vector<double> lpt(M.dense ? (size_t)(S + 1) * d : 0, 0.0);
+  if (M.dense) {
+    for (int s2 = M.n_save - 1; s2 >= 0; --s2) {
+      const int i = sidx[s2];
+      const double* w = &wbar[(size_t)s2 * d];
+      if (i == S) {
+        for (int c = 0; c < d; ++c) lpt[(size_t)S * d + c] += w[c];
+        continue;
+      }
+      const double h = hrow[i];
+      const Hermite H = hermite(sdt[s2] / h);
+      // y(theta) = a0 y_i + a1 y_{i+1} + h (c0 f(y_i) + c1 f(y_{i+1}))
+      double v0[DMAX], v1[DMAX], g0[DMAX], g1[DMAX];
+      for (int c = 0; c < d; ++c) {
+        v0[c] = h * H.c0 * w[c];
+        v1[c] = h * H.c1 * w[c];
+      }
+      vjp(M.sys, &ys[(size_t)i * d], p, v0, g0, gp);
+      vjp(M.sys, &ys[(size_t)(i + 1) * d], p, v1, g1, gp);
+      for (int c = 0; c < d; ++c) {
+        lpt[(size_t)i * d + c] += H.a0 * w[c] + g0[c];
+        lpt[(size_t)(i + 1) * d + c] += H.a1 * w[c] + g1[c];
+      }
+    }
+  } else {
+    for (int s2 = M.n_save - 1; s2 >= 0; --s2)
+      step_vjp_any(M.method, M.sys, d, &ys[(size_t)sidx[s2] * d], p, sdt[s2], &wbar[s2 * d],
+                   &lsave[(size_t)s2 * d], gp);
+  }
   double lam[DMAX];
   for (int c = 0; c < d; ++c) lam[c] = 0.0;
   int s = M.n_save - 1;
   for (int i = S; i >= 0; --i) {
-    while (s >= 0 && sidx[s] == i) {
+    if (M.dense)
+      for (int c = 0; c < d; ++c) lam[c] = lam[c] + lpt[(size_t)i * d + c];
+    while (!M.dense && s >= 0 && sidx[s] == i) {
       for (int c = 0; c < d; ++c) lam[c] = lam[c] + lsave[(size_t)s * d + c];
       --s;
     }
@@ -1570,10 +1656,11 @@ int oracle_replay(int sys, int method, int n, int params_shared,
                   const double* y0, const double* p, int64_t cap,
                   const double* h, const int32_t* S, int n_save,
                   const int32_t* save_idx, const double* save_dt,
-                  double* y_save) {
+                  double* y_save, int dense) {
   if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, params_shared, cap, h, S, n_save,
                          save_idx, save_dt);
+  M.dense = dense;
   const int d = M.d, np = M.np;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int l = 0; l < n; ++l) {
@@ -1590,9 +1677,10 @@ int oracle_replay_dual(int sys, int method, int n, const double* y0,
                        const double* p, const double* dy0, const double* dp,
                        int64_t cap, const double* h, const int32_t* S,
                        int n_save, const int32_t* save_idx,
-                       const double* save_dt, double* y_save, double* dy_save) {
+                       const double* save_dt, double* y_save, double* dy_save, int dense) {
   if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, 0, cap, h, S, n_save, save_idx, save_dt);
+  M.dense = dense;
   const int d = M.d, np = M.np;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int l = 0; l < n; ++l) {
@@ -1617,9 +1705,10 @@ int oracle_replay_complex(int sys, int method, int n, const double* y0,
                           const double* p, const double* dy0, const double* dp,
                           double eps, int64_t cap, const double* h,
                           const int32_t* S, int n_save, const int32_t* save_idx,
-                          const double* save_dt, double* re, double* im) {
+                          const double* save_dt, double* re, double* im, int dense) {
   if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, 0, cap, h, S, n_save, save_idx, save_dt);
+  M.dense = dense;
   const int d = M.d, np = M.np;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int l = 0; l < n; ++l) {
@@ -1647,10 +1736,11 @@ int oracle_adjoint(int sys, int method, int n, int params_shared,
                    const int32_t* save_idx, const double* save_dt,
                    int loss_kind, const double* loss_data,
                    double loss_scale, double* grad_p, double* grad_y0,
-                   double* loss_lane) {
+                   double* loss_lane, int dense) {
   if (sys_dim(sys) < 0 || !(erk_of(method) || is_ros(method))) return -1;
   MeshArgs M = mesh_args(sys, method, n, params_shared, cap, h, S, n_save,
                          save_idx, save_dt);
+  M.dense = dense;
   LossArgs L{loss_kind, loss_data, loss_scale};
   const int d = M.d, np = M.np;
 #pragma omp parallel for schedule(dynamic, 64)
