@@ -130,6 +130,16 @@ typedef struct {
   int64_t max_steps;        /* trial budget per trajectory; 0 = 100000 */
   int32_t n_save;           /* 0: the only save time is t1 */
   const double* save_times; /* host [n_save], nondecreasing, each in [t0, t1] */
+  int32_t dense;            /* 0: each save state by one extra step from the last
+                               mesh point before it (Section 3.4); 1: by the
+                               continuous extension of the accepted step that
+                               holds it (dense output, Section 3.2): the cubic
+                               Hermite interpolant of the step's end states and
+                               slopes, no extra step.  Explicit pairs and
+                               Rosenbrock methods on the built-in systems except
+                               the UDE, in ensemble_solve, ensemble_record,
+                               ensemble_replay_mesh and ensemble_adjoint;
+                               elsewhere ENS_EUNSUPPORTED */
 } ens_ivp;
 
 /* ---- records ------------------------------------------------------------ */
@@ -182,6 +192,11 @@ typedef struct {
   void* pages;          /* [n_pages][page_bytes] */
   void* save_base;      /* [n_save][dim][n] state each save's side step starts from
                            (the record writes it; the reverse sweep reads it) */
+  int32_t dense;        /* the save states are the dense output (ens_ivp.dense) */
+  void* save_base_hi;   /* dense: [n_save][dim][n] end state of the step holding
+                           each save; NULL otherwise */
+  double* save_h;       /* dense: [n_save][n] size of that step (0 for a save at
+                           the last mesh point); NULL otherwise */
 } ens_record;
 
 typedef struct {
@@ -359,7 +374,8 @@ int ensemble_adjoint_static(const ens_problem* prob, const ens_ivp* ivp,
 /* Workspace ensemble_adjoint needs for this record: per-block partial sums
  * for shared parameters, one segment of step records per trajectory for a
  * checkpointed tape, and each save's cotangent for the state its side step
- * starts from ([n_save][dim][n] elements; not for the UDE). */
+ * starts from ([n_save][dim][n] elements, twice that for dense output,
+ * whose saves reach both end states of their step; not for the UDE). */
 int ensemble_adjoint_workspace_bytes(const ens_record* rec, size_t* bytes);
 
 /* Totals of a finished record (synchronizes the stream). */

@@ -36,7 +36,8 @@ class Ivp(C.Structure):
     _fields_ = [("n", C.c_int64), ("y0", C.c_void_p), ("params", C.c_void_p),
                 ("t0", C.c_double), ("t1", C.c_double), ("rtol", C.c_double),
                 ("atol", C.c_double), ("h0", C.c_double), ("max_steps", C.c_int64),
-                ("n_save", C.c_int32), ("save_times", C.POINTER(C.c_double))]
+                ("n_save", C.c_int32), ("save_times", C.POINTER(C.c_double)),
+                ("dense", C.c_int32)]
 
 
 class TapeCfg(C.Structure):
@@ -57,7 +58,8 @@ class Record(C.Structure):
                 ("last_page", C.c_void_p), ("status", C.c_void_p), ("save_idx", C.c_void_p),
                 ("save_dt", C.c_void_p), ("save_times", C.c_void_p), ("y_final", C.c_void_p),
                 ("links", C.c_void_p), ("counters", C.c_void_p), ("pages", C.c_void_p),
-                ("save_base", C.c_void_p)]
+                ("save_base", C.c_void_p), ("dense", C.c_int32), ("save_base_hi", C.c_void_p),
+                ("save_h", C.c_void_p)]
 
 
 class Stats(C.Structure):

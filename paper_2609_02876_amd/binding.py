@@ -46,7 +46,7 @@ class _Spec:
     """Problem + ivp structs with the host arrays they point to kept alive."""
 
     def __init__(self, system, method, y0, params, t0, t1, rtol, atol, save_times,
-                 h0, max_steps, params_shared):
+                 h0, max_steps, params_shared, dense=False):
         sid, d, npar = _sysinfo(system)
         if method not in A.METHODS:
             raise ValueError(f"unknown method {method!r}")
@@ -71,9 +71,10 @@ class _Spec:
         self._st = (C.c_double * max(1, len(st)))(*st) if st else None
         self.n_save = max(1, len(st))
         self.save_times = st
+        self.dense = bool(dense)
         self.ivp = A.Ivp(n, y0.data_ptr(), params.data_ptr(), float(t0), float(t1), float(rtol),
                          float(atol), float(h0), int(max_steps), len(st),
-                         C.cast(self._st, C.POINTER(C.c_double)) if st else None)
+                         C.cast(self._st, C.POINTER(C.c_double)) if st else None, int(dense))
 
 
 class RecordHandle:
@@ -111,14 +112,14 @@ def _view_i32(ptr, n, pool):
 
 
 def ensemble_record_bytes(system, method, n, t0, t1, steps_hint, n_save=0,
-                          dtype=torch.float64, ckpt_every=0, params_shared=None):
+                          dtype=torch.float64, ckpt_every=0, params_shared=None, dense=False):
     sid, d, npar = _sysinfo(system)
     if params_shared is None:
         params_shared = system in SHARED_ONLY
     prob = A.Problem(sid, A.METHODS[method], _DT[dtype], d, npar, int(params_shared))
     st = (C.c_double * max(1, n_save))(*([t1] * max(1, n_save)))
     ivp = A.Ivp(n, None, None, float(t0), float(t1), 1e-6, 1e-6, 0.0, 0, int(n_save),
-                C.cast(st, C.POINTER(C.c_double)))
+                C.cast(st, C.POINTER(C.c_double)), int(dense))
     out = C.c_size_t()
     A.check(A.load().ensemble_record_bytes(C.byref(prob), C.byref(ivp), int(steps_hint),
                                            int(ckpt_every), C.byref(out)))
@@ -142,10 +143,11 @@ def plan_tape(system, method, n, t0, t1, steps_hint, n_save=0, dtype=torch.float
 
 
 def ensemble_solve(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
-                   max_steps=0, params_shared=False):
-    """Forward solve: (states at the save times [n_save, d, n], lane status [n])."""
+                   max_steps=0, params_shared=False, dense=False):
+    """Forward solve: (states at the save times [n_save, d, n], lane status [n]).
+    dense: save states from the continuous extension instead of extra steps."""
     spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
-                 params_shared)
+                 params_shared, dense)
     y_out = torch.empty((spec.n_save, spec.d, spec.n), dtype=spec.dtype, device=y0.device)
     status = torch.empty(spec.n, dtype=torch.int32, device=y0.device)
     A.check(A.load().ensemble_solve(C.byref(spec.prob), C.byref(spec.ivp), _ptr(y_out),
@@ -163,7 +165,7 @@ def _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every=0):
     else:
         nbytes = ensemble_record_bytes(spec.system, spec.method, spec.n, spec.ivp.t0,
                                        spec.ivp.t1, steps_hint, spec.ivp.n_save, spec.dtype,
-                                       ckpt_every, bool(spec.prob.params_shared))
+                                       ckpt_every, bool(spec.prob.params_shared), spec.dense)
         pool = torch.empty(nbytes, dtype=torch.uint8, device=spec.y0.device)
         spt = int(steps_hint)
     return pool, A.TapeCfg(pool.data_ptr(), pool.numel(), int(ckpt_every), spt)
@@ -171,16 +173,17 @@ def _pool_for(spec, steps_hint, pool, steps_per_traj, ckpt_every=0):
 
 def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=None, h0=0.0,
                     max_steps=0, params_shared=False, steps_hint=512, pool=None,
-                    steps_per_traj=None, ckpt_every=0, tape_budget_bytes=None):
+                    steps_per_traj=None, ckpt_every=0, tape_budget_bytes=None, dense=False):
     """Adaptive record.  Returns a RecordHandle (.y_save, .status, .pool).
 
     Without a pool, one is planned that reserves steps_hint taped steps per
     trajectory (plus overflow).  With a pool, steps_per_traj sets the
     per-trajectory reservation (None: 7/8 of the pool evenly).
     ckpt_every="auto" keeps the full tape unless its plan exceeds
-    tape_budget_bytes, then checkpoints every 64 steps (plan_tape)."""
+    tape_budget_bytes, then checkpoints every 64 steps (plan_tape).  dense: save
+    states from the continuous extension of the accepted step (no extra step)."""
     spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
-                 params_shared)
+                 params_shared, dense)
     if ckpt_every == "auto":
         ckpt_every = plan_tape(system, method, spec.n, t0, t1, steps_hint, spec.ivp.n_save,
                                spec.dtype, tape_budget_bytes, shared=bool(params_shared))
@@ -194,10 +197,11 @@ def ensemble_record(system, method, y0, params, t0, t1, rtol, atol, save_times=N
 
 
 def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_times=None,
-                         params_shared=False, pool=None, steps_per_traj=None, ckpt_every=0):
+                         params_shared=False, pool=None, steps_per_traj=None, ckpt_every=0,
+                         dense=False):
     """Record on a given mesh h [cap, n] (float64), steps [n] (int32)."""
     spec = _Spec(system, method, y0, params, t0, t1, 1e-6, 1e-6, save_times, 0.0, 0,
-                 params_shared)
+                 params_shared, dense)
     _require_gpu(h, steps)
     if h.dtype != torch.float64 or steps.dtype != torch.int32:
         raise ValueError("h must be float64 and steps int32")
@@ -216,13 +220,14 @@ def ensemble_replay_mesh(system, method, y0, params, t0, t1, h, steps, save_time
 
 def ensemble_refresh(system, method, y0, params, t0, t1, rtol, atol, h, steps, slack=1.0,
                      save_times=None, h0=0.0, max_steps=0, params_shared=False, steps_hint=None,
-                     pool=None, steps_per_traj=None, ckpt_every=0):
+                     pool=None, steps_per_traj=None, ckpt_every=0, dense=False):
     """Refresh an old mesh h [cap, n] (float64), steps [n] (int32) at new
     inputs: each trajectory keeps its old steps while their error estimates
     stay <= slack, then records adaptively (the mesh-drift policy).
-    Returns (RecordHandle, drift_at [n] int32: old steps kept)."""
+    Returns (RecordHandle, drift_at [n] int32: old steps kept).  (dense
+    output is refused by the library here.)"""
     spec = _Spec(system, method, y0, params, t0, t1, rtol, atol, save_times, h0, max_steps,
-                 params_shared)
+                 params_shared, dense)
     _require_gpu(h, steps)
     if h.dtype != torch.float64 or steps.dtype != torch.int32:
         raise ValueError("h must be float64 and steps int32")

@@ -113,6 +113,9 @@ struct RecView {
   const double* save_times;
   void* y_final;         // [D][n]
   void* save_base;       // [n_save][D][n] base state of each save's side step
+  // dense output: the end state of the step holding each save and its size
+  void* save_base_hi;    // [n_save][D][n] or null
+  double* save_h;        // [n_save][n] or null
   int32_t* links;        // [overflow pages][2]: previous, next page id
   unsigned long long* counters;
   char* pages;

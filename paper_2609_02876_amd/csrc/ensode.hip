@@ -138,6 +138,7 @@ int check_ivp(const ens_ivp* v, bool need_ptrs) {
     return fail(ENS_EINVAL, "max_steps out of range");
   if (v->n_save < 0 || v->n_save > ENS_MAX_SAVE)
     return fail(ENS_EINVAL, "n_save must be in [0, %d]", ENS_MAX_SAVE);
+  if (v->dense != 0 && v->dense != 1) return fail(ENS_EINVAL, "dense must be 0 or 1");
   if (v->n_save > 0) {
     if (!v->save_times) return fail(ENS_EINVAL, "save_times is NULL");
     for (int i = 0; i < v->n_save; ++i) {
@@ -154,7 +155,7 @@ int check_ivp(const ens_ivp* v, bool need_ptrs) {
 // Pool layout of a record.
 struct Layout {
   size_t counters, save_times, steps, n_trial, first_page, last_page, status,
-      save_idx, save_dt, y_final, save_base, links, pages;
+      save_idx, save_dt, y_final, save_base, save_base_hi, save_h, links, pages;
   size_t fixed;  // bytes before the links array
   size_t page_bytes;
 };
@@ -169,7 +170,7 @@ bool ckpt_ok(int ckpt_every) {
          ckpt_every == 128 || ckpt_every == 256;
 }
 
-Layout layout(int64_t n, int n_save_eff, int d, int dtype, int ckpt_every) {
+Layout layout(int64_t n, int n_save_eff, int d, int dtype, int ckpt_every, bool dense = false) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -188,6 +189,9 @@ Layout layout(int64_t n, int n_save_eff, int d, int dtype, int ckpt_every) {
   L.save_dt = take((size_t)n_save_eff * n * 8);
   L.y_final = take((size_t)d * n * elem_size(dtype));
   L.save_base = take((size_t)n_save_eff * d * n * elem_size(dtype));
+  // dense output: each save's step end state and step size
+  L.save_base_hi = dense ? take((size_t)n_save_eff * d * n * elem_size(dtype)) : 0;
+  L.save_h = dense ? take((size_t)n_save_eff * n * 8) : 0;
   L.fixed = off;
   L.links = off;
   L.page_bytes = ckpt_every > 0
@@ -254,6 +258,9 @@ void fill_record(ens_record* r, const ens_problem* p, const ens_ivp* v,
   r->save_dt = (double*)(base + L.save_dt);
   r->y_final = base + L.y_final;
   r->save_base = base + L.save_base;
+  r->dense = v->dense;
+  r->save_base_hi = v->dense ? base + L.save_base_hi : nullptr;
+  r->save_h = v->dense ? (double*)(base + L.save_h) : nullptr;
   r->links = (int32_t*)(base + L.links);
   r->pages = base + align256(L.links + (size_t)ps.n_over * 8);
 }
@@ -277,6 +284,8 @@ RecView view_of(const ens_record* r) {
   v.save_times = r->save_times;
   v.y_final = r->y_final;
   v.save_base = r->save_base;
+  v.save_base_hi = r->save_base_hi;
+  v.save_h = r->save_h;
   v.links = r->links;
   v.counters = r->counters;
   v.pages = (char*)r->pages;
@@ -429,12 +438,12 @@ __global__ void __launch_bounds__(256) save_bases_kernel(const RecView R, int64_
 }
 
 int launch_forward_body(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
-                        hipStream_t st);
+                        hipStream_t st, bool dense);
 
 int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
-                   hipStream_t st) {
-  int rc = launch_forward_body(p, mode, ckpt, fa, st);
-  if (rc != ENS_OK || ckpt || (mode != MODE_FROZEN && mode != MODE_REFRESH) ||
+                   hipStream_t st, bool dense = false) {
+  int rc = launch_forward_body(p, mode, ckpt, fa, st, dense);
+  if (rc != ENS_OK || ckpt || dense || (mode != MODE_FROZEN && mode != MODE_REFRESH) ||
       p->system == ENS_SYS_LV_UDE)
     return rc;
   SysInfo si;
@@ -446,8 +455,37 @@ int launch_forward(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
 }
 
 int launch_forward_body(const ens_problem* p, int mode, bool ckpt, const FwdArgs& fa,
-                        hipStream_t st) {
+                        hipStream_t st, bool dense) {
   if (p->system == ENS_SYS_LV_UDE) return launch_forward_ude(mode, ckpt, fa, st);
+  if (dense) {
+    // dense output: the save states from the continuous extension, formed in
+    // the loop (solve, record with either tape, replay of a given mesh)
+    return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
+      using Sys = decltype(s);
+      using Tab = decltype(m);
+      using T = decltype(t);
+      const dim3 g(grid_of(fa.ivp.n)), b(BLOCK);
+      if (mode == MODE_SOLVE)
+        hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_SOLVE, false, true>), g, b, 0,
+                           st, fa);
+      else if (mode == MODE_RECORD && !ckpt)
+        hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD, false, true>), g, b,
+                           0, st, fa);
+      else if (mode == MODE_RECORD)
+        hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_RECORD, true, true>), g, b, 0,
+                           st, fa);
+      else if (mode == MODE_FROZEN && !ckpt)
+        hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_FROZEN, false, true>), g, b,
+                           0, st, fa);
+      else if (mode == MODE_FROZEN)
+        hipLaunchKernelGGL((erk_forward_kernel<Sys, Tab, T, MODE_FROZEN, true, true>), g, b, 0,
+                           st, fa);
+      else
+        return fail(ENS_EUNSUPPORTED, "dense output is not built for this mode");
+      hipError_t e = hipGetLastError();
+      return e == hipSuccess ? ENS_OK : hip_fail(e, "dense forward launch");
+    });
+  }
   if (is_rtc(p->system))
     return rtc_launch(p->system, p->method, p->dtype, fwd_expr(p->method, p->dtype, mode, ckpt),
                       grid_of(fa.ivp.n), fa, st);
@@ -495,7 +533,21 @@ int check_record_matches(const ens_problem* p, const ens_ivp* v,
   if (r->n_save != (v->n_save > 0 ? v->n_save : 1))
     return fail(ENS_EINVAL, "record has %d save times, ivp %d", r->n_save,
                 v->n_save);
+  if (r->dense != v->dense)
+    return fail(ENS_EINVAL, "record and ivp differ in dense output");
   if (!r->pool || !r->pages) return fail(ENS_EINVAL, "record has no pool");
+  return ENS_OK;
+}
+
+// Dense output is built for the explicit pairs and the Rosenbrock methods on
+// the built-in systems other than the UDE, in the solve, the record and the
+// replay of a given mesh.
+int check_dense(const ens_problem* p, const ens_ivp* v, int mode) {
+  if (!v->dense) return ENS_OK;
+  if (p->system == ENS_SYS_LV_UDE || is_rtc(p->system))
+    return fail(ENS_EUNSUPPORTED, "dense output is not built for the UDE or registered systems");
+  if (mode == MODE_REFRESH)
+    return fail(ENS_EUNSUPPORTED, "dense output is not built for the mesh refresh");
   return ENS_OK;
 }
 
@@ -515,7 +567,8 @@ int record_common(const ens_problem* p, const ens_ivp* v,
     return fail(ENS_EINVAL, "ckpt_every must be 0, 16, 32, 64, 128 or 256");
   if (!out || !y_save) return fail(ENS_EINVAL, "out and y_save are required");
   const int nse = v->n_save > 0 ? v->n_save : 1;
-  Layout L = layout(v->n, nse, si.d, p->dtype, tc->ckpt_every);
+  if ((rc = check_dense(p, v, mode)) != ENS_OK) return rc;
+  Layout L = layout(v->n, nse, si.d, p->dtype, tc->ckpt_every, v->dense != 0);
   if (tc->steps_per_traj < 0) return fail(ENS_EINVAL, "steps_per_traj < 0");
   PageSplit ps;
   if (!split_pages(L, v->n, tc->pool_bytes, tc->steps_per_traj,
@@ -542,7 +595,7 @@ int record_common(const ens_problem* p, const ens_ivp* v,
   fa.cap = cap;
   fa.slack = slack;
   fa.drift_at = drift_at;
-  return launch_forward(p, mode, tc->ckpt_every > 0, fa, st);
+  return launch_forward(p, mode, tc->ckpt_every > 0, fa, st, v->dense != 0);
 }
 
 // Mesh export: walk each trajectory's pages forward.  The step sizes of
@@ -628,11 +681,12 @@ int ensemble_solve(const ens_problem* p, const ens_ivp* v, void* y_out,
   if ((rc = check_problem(p, &si)) != ENS_OK) return rc;
   if ((rc = check_ivp(v, true)) != ENS_OK) return rc;
   if (!y_out) return fail(ENS_EINVAL, "y_out is NULL");
+  if ((rc = check_dense(p, v, MODE_SOLVE)) != ENS_OK) return rc;
   FwdArgs fa{};
   fa.ivp = ivp_args(p, v);
   fa.y_save = y_out;
   fa.lane_status = lane_status;
-  return launch_forward(p, MODE_SOLVE, false, fa, (hipStream_t)stream);
+  return launch_forward(p, MODE_SOLVE, false, fa, (hipStream_t)stream, v->dense != 0);
 }
 
 int ensemble_record_bytes(const ens_problem* p, const ens_ivp* v,
@@ -647,7 +701,8 @@ int ensemble_record_bytes(const ens_problem* p, const ens_ivp* v,
     return fail(ENS_EINVAL, "ckpt_every must be 0, 16, 32, 64, 128 or 256");
   if (steps_hint < 1) return fail(ENS_EINVAL, "steps_hint must be >= 1");
   const int nse = v->n_save > 0 ? v->n_save : 1;
-  Layout L = layout(v->n, nse, si.d, p->dtype, ckpt_every);
+  if ((rc = check_dense(p, v, MODE_RECORD)) != ENS_OK) return rc;
+  Layout L = layout(v->n, nse, si.d, p->dtype, ckpt_every, v->dense != 0);
   const int ps = page_steps_of(ckpt_every);
   const int64_t pages_per = (steps_hint + ps - 1) / ps;
   const int64_t n_static = pages_per * v->n;
@@ -701,7 +756,7 @@ int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,
 
 // The sweep's per-save cotangents for their base states, [n_save][dim][n].
 size_t contrib_bytes(const ens_record* r) {
-  return align256((size_t)r->n_save * r->dim * r->n * elem_size(r->dtype));
+  return align256((size_t)(r->dense ? 2 : 1) * r->n_save * r->dim * r->n * elem_size(r->dtype));
 }
 
 int ensemble_adjoint_workspace_bytes(const ens_record* r, size_t* bytes) {
@@ -855,7 +910,19 @@ int adjoint_impl(const ens_problem* p, const ens_ivp* v, const ens_record* r,
     using Tab = decltype(m);
     using T = decltype(t);
     const dim3 g(grid_of(v->n)), b(BLOCK);
-    if (shared && ckpt)
+    if (r->dense) {
+      if (shared && ckpt)
+        hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true, true, true>), g, b, 0, st, aa);
+      else if (shared)
+        hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true, false, true>), g, b, 0, st,
+                           aa);
+      else if (ckpt)
+        hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, false, true, true>), g, b, 0, st,
+                           aa);
+      else
+        hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, false, false, true>), g, b, 0, st,
+                           aa);
+    } else if (shared && ckpt)
       hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true, true>), g, b, 0, st, aa);
     else if (shared)
       hipLaunchKernelGGL((erk_adjoint_kernel<Sys, Tab, T, true, false>), g, b, 0, st, aa);
@@ -883,6 +950,7 @@ int ensemble_jvp(const ens_problem* p, const ens_ivp* v, const ens_record* r,
   if ((rc = check_record_matches(p, v, r)) != ENS_OK) return rc;
   if (p->params_shared)
     return fail(ENS_EUNSUPPORTED, "forward mode takes per-trajectory parameters");
+  if (r->dense) return fail(ENS_EUNSUPPORTED, "forward mode is not built for dense output");
   if (p->system == ENS_SYS_LV_UDE || p->system == ENS_SYS_HIRES)
     return fail(ENS_EUNSUPPORTED,
                 "forward mode is built for the systems with few inputs per trajectory "

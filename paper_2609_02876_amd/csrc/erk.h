@@ -526,6 +526,33 @@ __device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
   for (int c = 0; c < D; ++c) y[c] = b.y[c];
 }
 
+// ------------------------------------------------------------ dense output --
+// The continuous extension of an accepted step (the dense output of Section
+// 3.2): the cubic Hermite interpolant of the step's end states y0, y1 and
+// slopes f0 = f(y0), f1 = f(y1), at offset theta = dt / h,
+//   y(theta) = a0 y0 + a1 y1 + h (c0 f0 + c1 f1),
+//   a0 = (1 - theta)^2 (1 + 2 theta), a1 = theta^2 (3 - 2 theta),
+//   c0 = theta (1 - theta)^2,         c1 = -theta^2 (1 - theta).
+struct HermiteW {
+  double a0, a1, c0, c1;
+};
+__device__ __forceinline__ HermiteW hermite_weights(double theta) {
+  const double u = 1.0 - theta;
+  return HermiteW{u * u * fmaT(2.0, theta, 1.0), theta * theta * fmaT(-2.0, theta, 3.0),
+                  theta * u * u, -(theta * theta) * u};
+}
+
+template <class T, int D>
+__device__ __forceinline__ void hermite_state(const T* y0, const T* y1, const T* f0,
+                                              const T* f1, double h, double dt, T* out) {
+  const HermiteW w = hermite_weights(dt / h);
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const T slope = fmaT(T(w.c1), f1[c], T(w.c0) * f0[c]);
+    out[c] = fmaT(T(h), slope, fmaT(T(w.a1), y1[c], T(w.a0) * y0[c]));
+  }
+}
+
 // ------------------------------------------------------- forward / record --
 // MODE_SOLVE: adaptive solve, no tape.  MODE_RECORD: adaptive solve writing
 // the tape.  MODE_FROZEN: steps taken from a given mesh, writing the tape.
@@ -542,10 +569,17 @@ __device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
 // save states from the taped base states, all (trajectory, save) pairs in
 // parallel with the same step map: the same values, and a loop with fewer
 // iterations and less state.
-template <class Sys, class Tab, class T, int MODE, bool CKPT, bool DEFER = false>
+//
+// DENSE (dense output): no side steps either; each save time inside an
+// accepted step takes the step's continuous extension at once, from the
+// step's end states and slopes.  The record keeps both end states of the
+// step (save_base and save_base_hi) and its size (save_h) for the sweep.
+template <class Sys, class Tab, class T, int MODE, bool CKPT, bool DEFER = false,
+          bool DENSE = false>
 __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block) {
   static_assert(!DEFER || (MODE == MODE_RECORD && !CKPT),
                 "save steps are deferred only from a full-tape record");
+  static_assert(!(DEFER && DENSE), "a dense record forms its save states in the loop");
   constexpr int D = Sys::D, NP = Sys::NP;
   constexpr int RB = TapeRec<T, D>::BYTES;
   constexpr int YB = StateBytes<T, D>::BYTES;
@@ -627,10 +661,20 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   // states from the tape afterwards: their loops load a step size per step,
   // and those loads would wait behind these stores.
   auto put_base = [&](const T* yb, bool valid) {
-    if constexpr (MODE == MODE_RECORD || (CKPT && MODE != MODE_SOLVE)) {
+    if constexpr (MODE == MODE_RECORD || (CKPT && MODE != MODE_SOLVE) ||
+                  (DENSE && MODE != MODE_SOLVE)) {
       T* sb = (T*)R.save_base + (ys_out - ysv);
 #pragma unroll
       for (int c = 0; c < D; ++c) sb[c * n] = valid ? yb[c] : T(NAN);
+    }
+  };
+  // dense output: the step's end state and its size, beside the base state
+  auto put_dense = [&](const T* y1, double hstep) {
+    if constexpr (DENSE && MODE != MODE_SOLVE) {
+      T* sb = (T*)R.save_base_hi + (ys_out - ysv);
+#pragma unroll
+      for (int c = 0; c < D; ++c) sb[c * n] = y1[c];
+      R.save_h[(int64_t)next_save * n + tr] = hstep;
     }
   };
   int32_t* sidx_out = R.save_idx + tr;
@@ -823,7 +867,44 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         h = hh * fmax(0.2, fmin(prev_rej ? 1.0 : 10.0, fac0));
         prev_rej = false;
       }
-      if constexpr (DEFER) {
+      if constexpr (DENSE) {
+        // saves inside this step: the step's continuous extension
+        if (ts < tnew) {
+          T f0[D], f1[D], yd[D];
+          if constexpr (Tab::FSAL) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              f0[c] = k1[c];
+              f1[c] = klast[c];
+            }
+          } else {
+            Sys::rhs(y, p, f0);
+            Sys::rhs(ynew, p, f1);
+          }
+          while (ts < tnew) {
+            hermite_state<T, D>(y, ynew, f0, f1, hh, ts - t, yd);
+#pragma unroll
+            for (int c = 0; c < D; ++c) ys_out[c * n] = yd[c];
+            if constexpr (MODE != MODE_SOLVE) {
+              *sidx_out = S - 1;
+              *sdt_out = ts - t;
+              sidx_out += n;
+              sdt_out += n;
+            }
+            put_base(y, true);
+            put_dense(ynew, hh);
+            ys_out += ys_stride;
+            ++next_save;
+            ts = s_times[next_save];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          y[c] = ynew[c];
+          if constexpr (Tab::FSAL) k1[c] = klast[c];
+        }
+        t = tnew;
+      } else if constexpr (DEFER) {
         // saves inside this step: base index S - 1 and offset from its start
         while (ts < tnew) {
           *sidx_out = S - 1;
@@ -883,6 +964,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
 #pragma unroll
     for (int c = 0; c < D; ++c) ys_out[c * n] = ok ? y[c] : T(NAN);
     put_base(y, ok);
+    put_dense(y, 0.0);
     ys_out += ys_stride;
     if constexpr (MODE != MODE_SOLVE) {
       *sidx_out = ok ? S : -1;
@@ -1047,6 +1129,65 @@ __device__ __forceinline__ void save_steps_reverse(const AdjArgs& a, int64_t tr,
   }
 }
 
+// The dense saves of one trajectory's reverse sweep, from the last save to
+// the first: each save's cotangent w (from its state, the continuous
+// extension recomputed from the step's end states), its loss term, and the
+// reverse of the extension.  With y(theta) = a0 y0 + a1 y1 + h (c0 f(y0) +
+// c1 f(y1)), the end states receive a0 w + f_y(y0)^T (h c0 w) and
+// a1 w + f_y(y1)^T (h c1 w), and g the parameter terms of both VJPs.  The
+// two cotangents go to a.contrib ([n_save][D][n], for y0) and to the half
+// after it (for y1); a save at the last mesh point gives w to y_S alone.
+template <class Sys, class T>
+__device__ __forceinline__ void dense_saves_reverse(const AdjArgs& a, int64_t tr, const T* p,
+                                                    T two_scale, T* g, double& loss) {
+  constexpr int D = Sys::D;
+  const RecView& R = a.rec;
+  const int64_t n = a.ivp.n;
+  T* cb = (T*)a.contrib;
+  T* cb_hi = cb + (int64_t)R.n_save * D * n;
+  const T* b0 = (const T*)R.save_base;
+  const T* b1 = (const T*)R.save_base_hi;
+  for (int ss = R.n_save - 1; ss >= 0; --ss) {
+    const double dt = R.save_dt[(int64_t)ss * n + tr];
+    const double hs = R.save_h[(int64_t)ss * n + tr];
+    T y0[D], y1[D], lo[D], hi[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      y0[c] = b0[((int64_t)ss * D + c) * n + tr];
+      y1[c] = b1[((int64_t)ss * D + c) * n + tr];
+    }
+    if (hs == 0.0) {  // at the last mesh point: the state itself
+      save_cotangent<T, D>(a, ss, tr, y0, two_scale, lo, loss);
+#pragma unroll
+      for (int c = 0; c < D; ++c) hi[c] = T(0);
+    } else {
+      T f0[D], f1[D], ys[D], w[D], v0[D], v1[D], g0[D], g1[D];
+      Sys::rhs(y0, p, f0);
+      Sys::rhs(y1, p, f1);
+      hermite_state<T, D>(y0, y1, f0, f1, hs, dt, ys);
+      save_cotangent<T, D>(a, ss, tr, ys, two_scale, w, loss);
+      const HermiteW hw = hermite_weights(dt / hs);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        v0[c] = T(hs * hw.c0) * w[c];
+        v1[c] = T(hs * hw.c1) * w[c];
+      }
+      Sys::vjp(y0, p, v0, g0, g);
+      Sys::vjp(y1, p, v1, g1, g);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        lo[c] = fmaT(T(hw.a0), w[c], g0[c]);
+        hi[c] = fmaT(T(hw.a1), w[c], g1[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      cb[((int64_t)ss * D + c) * n + tr] = lo[c];
+      cb_hi[((int64_t)ss * D + c) * n + tr] = hi[c];
+    }
+  }
+}
+
 // Slot (trajectory offset in the block) this lane sweeps.  The block's 256
 // lanes take its trajectories in increasing order of their step counts (ties
 // by index; failed and absent ones first), so each wavefront gets sweeps of
@@ -1080,7 +1221,13 @@ __device__ __forceinline__ int sweep_slot(const RecView& R, int64_t base, int64_
 // page (full step records, the same arithmetic as the record, so the same
 // bits), then walks it backward.  Replay steps and reverse steps share one
 // loop iteration so that lanes at different phases do not serialize.
-template <class Sys, class Tab, class T, bool SHARED, bool CKPT>
+//
+// DENSE: the saves come from the continuous extension of the step holding
+// each one (dense_saves_reverse); each save's cotangent reaches both end
+// states of its step, so the loop takes two streams of cotangents: at mesh
+// point i, those of the saves whose step ends at i, then of the saves whose
+// step starts at i (each from the last save to the first).
+template <class Sys, class Tab, class T, bool SHARED, bool CKPT, bool DENSE = false>
 __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block) {
   constexpr int D = Sys::D, NP = Sys::NP, SU = Tab::SU;
   constexpr int RB = TapeRec<T, D>::BYTES;
@@ -1121,7 +1268,10 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
 
   // The save steps first (save_steps_reverse); the cotangent each save
   // gives its base state is added when the loop below reaches that point.
-  save_steps_reverse<Sys, Tab, T, W_LDS>(a, tr, p, two_scale, s_W, gp, loss);
+  if constexpr (DENSE)
+    dense_saves_reverse<Sys, T>(a, tr, p, two_scale, gp, loss);
+  else
+    save_steps_reverse<Sys, Tab, T, W_LDS>(a, tr, p, two_scale, s_W, gp, loss);
 
   // Save bookkeeping, walked from the last save to the first: the save's
   // base index and its cotangent in a.contrib.
@@ -1160,8 +1310,24 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   };
   if (CKPT && S > 0) start_segment(slot + 1);
 
+  // dense output: the saves whose step ends at mesh point i (base index
+  // i - 1, and not at the last point), walked by a second cursor
+  int s_hi = R.n_save - 1;
+  int32_t sidx_hi = DENSE ? R.save_idx[(int64_t)s_hi * n + tr] : 0;
+  const T* cbh_p = (const T*)a.contrib + ((int64_t)R.n_save + s_hi) * D * n + tr;
   // the saves based at mesh point i, from the last: their cotangents into lam
   auto take_saves = [&]() {
+    if constexpr (DENSE) {
+      while (s_hi >= 0 && sidx_hi + 1 >= i) {
+        if (sidx_hi + 1 == i) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) lam[c] = lam[c] + cbh_p[c * n];
+        }
+        --s_hi;
+        cbh_p -= D * n;
+        if (s_hi >= 0) sidx_hi = R.save_idx[(int64_t)s_hi * n + tr];
+      }
+    }
     while (s >= 0 && sidx == i) {
 #pragma unroll
       for (int c = 0; c < D; ++c) lam[c] = lam[c] + cb_p[c * n];
@@ -1320,10 +1486,10 @@ struct FwdBlocks {
       (Sys::ID == 1 && Tab::ORDER == 5 && !Tab::ROS && sizeof(T) == 8) ? 4 : 1;
 };
 
-template <class Sys, class Tab, class T, int MODE, bool CKPT>
+template <class Sys, class Tab, class T, int MODE, bool CKPT, bool DENSE = false>
 __global__ void __launch_bounds__(256, (FwdBlocks<Sys, Tab, T>::value))
     erk_forward_kernel(const FwdArgs a) {
-  erk_forward_body<Sys, Tab, T, MODE, CKPT>(a, blockIdx.x);
+  erk_forward_body<Sys, Tab, T, MODE, CKPT, false, DENSE>(a, blockIdx.x);
 }
 
 // Full-tape record whose save states are formed afterwards by
@@ -1388,10 +1554,10 @@ struct AdjBlocks {
       (Sys::ID == 1 && Tab::ORDER == 5 && !Tab::ROS && sizeof(T) == 8) ? 3 : 1;
 };
 
-template <class Sys, class Tab, class T, bool SHARED, bool CKPT>
+template <class Sys, class Tab, class T, bool SHARED, bool CKPT, bool DENSE = false>
 __global__ void __launch_bounds__(256, (AdjBlocks<Sys, Tab, T>::value))
     erk_adjoint_kernel(const AdjArgs a) {
-  erk_adjoint_body<Sys, Tab, T, SHARED, CKPT>(a, blockIdx.x);
+  erk_adjoint_body<Sys, Tab, T, SHARED, CKPT, DENSE>(a, blockIdx.x);
 }
 
 // Sum of the per-block partials of shared-parameter gradients, in a fixed

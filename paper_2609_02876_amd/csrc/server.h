@@ -382,6 +382,7 @@ int ensemble_server_submit(ens_server* s, const ens_job* job, int64_t* id) {
   if (job->prob.system >= ENS_SYS_USER_BASE)
     return fail(ENS_EUNSUPPORTED, "registered systems are not served");
   if ((rc = check_ivp(&job->ivp, true)) != ENS_OK) return rc;
+  if (job->ivp.dense) return fail(ENS_EUNSUPPORTED, "served jobs save by the extra step (no dense output)");
   const ens_loss& L = job->loss;
   if (L.kind != ENS_LOSS_SUMSQ && L.kind != ENS_LOSS_MSE_TARGET && L.kind != ENS_LOSS_COTANGENT)
     return fail(ENS_EINVAL, "unknown loss kind %d", L.kind);
