@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--refresh-step", type=float, default=1e-3,
                     help="relative parameter change for --mode refresh (seeded normal)")
     ap.add_argument("--n", type=int, default=None, help="override the trajectory count")
+    ap.add_argument("--dense", action="store_true",
+                    help="save states from the continuous extension (dense output) instead "
+                         "of an extra step")
+    ap.add_argument("--grid", choices=("explicit", "stiff", "ude"), default=None,
+                    help="run a size / tolerance sweep of the benchmark configurations, one "
+                         "line per configuration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
@@ -199,7 +205,7 @@ def cpu_info():
             "cpu": cpu_model(), "build": _ORACLE_BUILD}
 
 
-def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
+def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0, dense=False):
     """The FP64 CPU oracle (record + adjoint) on a bounded sample of the workload."""
     import numpy as np
     O = load_oracle()
@@ -215,10 +221,10 @@ def cpu_baseline(cfg, y0, p, st, target_s, cap, loss_data=None, scale=1.0):
         rec = O.record(so, mo, y0[:m], pm, cfg["t0"], cfg["t1"], cfg["rtol"], cfg["atol"],
                        save_t=save, cap=cap, params_shared=shared)
         if loss_data is None:
-            O.adjoint(so, mo, y0[:m], pm, rec, params_shared=shared)
+            O.adjoint(so, mo, y0[:m], pm, rec, params_shared=shared, dense=dense)
         else:
             O.adjoint(so, mo, y0[:m], pm, rec, O.LOSS_MSE_TARGET, loss_data[:m], scale,
-                      params_shared=shared)
+                      params_shared=shared, dense=dense)
         return time.perf_counter() - t
 
     # grow the sample until it takes about target_s (small samples run below
@@ -247,13 +253,12 @@ def main():
               "shards by trajectory with no exchange, so more GPUs are not exercised here.",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    from paper_2609_02876_amd import binding as B
-    from paper_2609_02876_amd import flops
     from paper_2609_02876_amd import workloads as W
 
+    if args.grid:
+        return grid_bench(args)
     if args.workload == "serve_mix":
         return serve_bench(args)
     if args.mode == "forward":
@@ -261,17 +266,35 @@ def main():
     if args.mode == "refresh":
         return refresh_bench(args)
     cfg, y0, p, st = W.make(args.workload, n=args.n)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    out = reverse_bench(cfg, y0, p, st, args.steps, args.warmup, workload=args.workload,
+                        dense=args.dense, registered=args.registered,
+                        cpu_seconds=None if args.no_cpu_baseline else args.cpu_seconds,
+                        traffic_path=args.traffic, copy_mib=args.copy_calibration)
+    print(json.dumps(out), flush=True)
+
+
+def reverse_bench(cfg, y0, p, st, steps, warmup, workload, dense=False, registered=False,
+                  cpu_seconds=None, traffic_path=None, copy_mib=0):
+    """Time `steps` steps of record + reverse sweep of one ensemble (inputs
+    resident on the GPU) and return the benchmark line as a dict."""
+    import numpy as np
+    import torch
+
+    from paper_2609_02876_amd import binding as B
+    from paper_2609_02876_amd import flops
+    from paper_2609_02876_amd import workloads as W
+
     n = cfg["n"]
     save = list(st) if cfg["n_save"] else None
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     f32 = cfg.get("dtype", "f64") == "f32"
     tdt = torch.float32 if f32 else torch.float64
     shared = cfg.get("shared", False)
     ckpt = cfg.get("ckpt_every", 0)
     y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=tdt, device=dev)
     p_d = torch.tensor(np.ascontiguousarray(p if shared else p.T), dtype=tdt, device=dev)
-    gsys = registered_system(cfg["system"]) if args.registered else cfg["system"]
+    gsys = registered_system(cfg["system"]) if registered else cfg["system"]
     args_common = (gsys, cfg["method"], y0_d, p_d, cfg["t0"], cfg["t1"], cfg["rtol"],
                    cfg["atol"])
 
@@ -296,8 +319,9 @@ def main():
     hint = B.steps_hint_for(float(s_pilot.mean().item()), margin=1.12)
     del pilot
     nbytes = B.ensemble_record_bytes(gsys, cfg["method"], n, cfg["t0"], cfg["t1"], hint,
-                                     cfg["n_save"], tdt, ckpt)
+                                     cfg["n_save"], tdt, ckpt, dense=dense)
     pool = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    ws = None
 
     stream = torch.cuda.current_stream()
 
@@ -305,34 +329,37 @@ def main():
         if events:
             events[0].record(stream)
         rec = B.ensemble_record(*args_common, save_times=save, pool=pool, steps_per_traj=hint,
-                                params_shared=shared, ckpt_every=ckpt)
+                                params_shared=shared, ckpt_every=ckpt, dense=dense)
         if events:
             events[1].record(stream)
         gp, gy, ll = B.ensemble_adjoint(rec, loss_kind, loss_data, scale, want_y0=True,
-                                        want_loss=True)
+                                        want_loss=True, workspace=ws)
         if events:
             events[2].record(stream)
         return rec, gp, gy, ll
 
-    if args.copy_calibration:
-        calibration_copy(args.copy_calibration, dev)
-    for _ in range(args.warmup):
+    if copy_mib:
+        calibration_copy(copy_mib, dev)
+    for _ in range(warmup):
         rec, gp, gy, ll = step()
+        if ws is None:
+            wsb = B.ensemble_adjoint_workspace_bytes(rec)
+            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
-    if args.warmup:
+    if warmup:
         bad = int((rec.status != 0).sum().item())
         if bad:
             raise RuntimeError(f"{bad} trajectories did not finish (status != OK)")
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         rec, gp, gy, ll = step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rec_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    adj_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    rec_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
     step_ev = sorted(e[0].elapsed_time(e[2]) for e in evs)
 
     bad = int((rec.status != 0).sum().item())
@@ -342,17 +369,17 @@ def main():
     n_saves = n * (cfg["n_save"] or 1)
     zero_sides = n_saves - stats["side_steps"]
     f_rec = flops.record_flops(cfg["method"], cfg["system"], stats["trials"],
-                               stats["steps_accepted"], stats["side_steps"])
+                               stats["steps_accepted"], stats["side_steps"], dense)
     f_adj = flops.adjoint_flops(cfg["method"], cfg["system"], stats["steps_accepted"],
-                                stats["side_steps"], zero_sides)
-    ms_per_step = wall * 1e3 / args.steps
-    value = n * args.steps / wall
+                                stats["side_steps"], zero_sides, dense)
+    ms_per_step = wall * 1e3 / steps
+    value = n * steps / wall
 
     dominant = "adjoint" if adj_ms >= rec_ms else "record"
     f_dom, ms_dom = (f_adj, adj_ms) if dominant == "adjoint" else (f_rec, rec_ms)
     achieved = f_dom / (ms_dom * 1e-3) / 1e12
     traffic = None
-    tr = load_traffic(args.traffic, args.workload)
+    tr = load_traffic(traffic_path, workload)
     if tr is not None and tr.get("n") == n:
         traffic = tr.get(dominant)
     if cfg["system"] == "ude":
@@ -360,29 +387,34 @@ def main():
         kname = f"ude_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel (f32)"
     else:
         bound, peak = "alu", (PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS)
-        deferred = cfg["method"] in ("tsit5", "vern7") and not ckpt and not args.registered
+        deferred = (cfg["method"] in ("tsit5", "vern7") and not ckpt and not registered
+                    and not dense)
         kname = ("erk_adjoint_kernel" if dominant == "adjoint" else
                  # explicit pairs' full-tape record: the loop, then the save states
                  "erk_record_deferred_kernel + erk_saves_kernel" if deferred else
                  "erk_forward_kernel")
-        kname += f" ({cfg['system']}, {cfg['method']}, {'f32' if f32 else 'f64'})"
+        kname += f" ({cfg['system']}, {cfg['method']}, {'f32' if f32 else 'f64'}"
+        kname += ", dense output)" if dense else ")"
     out = {
-        "metric": METRIC if args.workload == "lorenz_2p20_t10" else "trajectory-gradients/s (fwd+adjoint)",
+        "metric": METRIC if workload == "lorenz_2p20_t10" and not dense
+        else "trajectory-gradients/s (fwd+adjoint)",
         "value": value,
         "unit": "trajectory-gradients/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if f32 else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "system": cfg["system"], "method": cfg["method"],
-                   "registered_at_run_time": bool(args.registered),
+        "config": {"workload": workload, "system": cfg["system"], "method": cfg["method"],
+                   "registered_at_run_time": bool(registered),
                    "n": n, "t_span": [cfg["t0"], cfg["t1"]], "rtol": cfg["rtol"],
                    "atol": cfg["atol"], "n_save": cfg["n_save"], "ckpt_every": ckpt,
+                   "save_states": ("dense output (continuous extension)" if dense
+                                   else "extra step from the last mesh point"),
                    "loss": ("MSE to teacher-network trajectories" if loss_kind == "mse"
                             else "sum of squared save states"),
                    "gradient": "shared weights" if shared else "per-trajectory params"},
@@ -401,10 +433,69 @@ def main():
                          "side_steps": stats["side_steps"], "overflow_pages_used": stats["overflow_pages_used"],
                          "pool_gb": nbytes / 1e9},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, args.cpu_seconds, cap_cpu, tgt_host,
-                                           scale)
-    print(json.dumps(out), flush=True)
+    if cpu_seconds:
+        out["cpu_baseline"] = cpu_baseline(cfg, y0, p, st, cpu_seconds, cap_cpu, tgt_host,
+                                           scale, dense)
+    return out
+
+
+# The size / tolerance sweeps of the benchmark configurations: explicit pairs
+# on Lorenz and Van der Pol (both methods, both precisions, two tolerances,
+# 2^12..2^20 trajectories, 20 save times), the stiff systems with both
+# Rosenbrock methods at 2^10..2^18, the UDE at 2^14..2^18 with the full and
+# the checkpointed tape.
+def grid_configs(which):
+    from paper_2609_02876_amd import workloads as W
+    out = []
+    if which == "explicit":
+        for system, t1 in (("lorenz", 10.0), ("vdp", 6.3)):
+            for method in ("tsit5", "vern7"):
+                for dtype in ("f64", "f32"):
+                    for rtol in (1e-6, 1e-8):
+                        for k in (12, 14, 16, 18, 20):
+                            out.append(dict(system=system, method=method, n=1 << k, t0=0.0,
+                                            t1=t1, rtol=rtol, atol=1e-8, n_save=20,
+                                            dtype=dtype))
+    elif which == "stiff":
+        for system, t1 in (("robertson", 1e5), ("hires", 321.8122)):
+            for method in ("rodas4", "ros23"):
+                for k in (10, 12, 14, 16, 18):
+                    out.append(dict(system=system, method=method, n=1 << k, t0=0.0, t1=t1,
+                                    rtol=1e-6, atol=1e-10, n_save=20))
+    elif which == "ude":
+        for k in (14, 15, 16, 17, 18):
+            for ck in (0, 64):
+                cfg = dict(W.WORKLOADS["ude_2p16"])
+                cfg.update(n=1 << k, ckpt_every=ck)
+                out.append(cfg)
+    else:
+        raise SystemExit(f"unknown grid {which!r}: explicit, stiff or ude")
+    return out
+
+
+def grid_bench(args):
+    """One JSON line per configuration of the chosen sweep (a few timed steps
+    each; the oracle on a small sample for the configurations at 2^12, 2^10
+    and 2^14 trajectories only)."""
+    import numpy as np
+    import torch
+
+    from paper_2609_02876_amd import workloads as W
+    torch.cuda.set_device(torch.device("cuda:0"))
+    for cfg in grid_configs(args.grid):
+        gen = W.GENERATORS[cfg["system"]]
+        y0, p = gen(cfg["n"], 0)
+        if cfg.get("dtype") == "f32":
+            y0 = y0.astype(np.float32).astype(np.float64)
+            p = p.astype(np.float32).astype(np.float64)
+        st = W.save_times(cfg["t0"], cfg["t1"], cfg["n_save"])
+        small = cfg["n"] == {"explicit": 1 << 12, "stiff": 1 << 10, "ude": 1 << 14}[args.grid]
+        name = (f"{cfg['system']}_{cfg['method']}_{cfg.get('dtype', 'f64')}_rtol{cfg['rtol']:g}"
+                f"_n{cfg['n']}" + (f"_ckpt{cfg['ckpt_every']}" if cfg.get("ckpt_every") else ""))
+        out = reverse_bench(cfg, y0, p, st, args.steps, args.warmup, workload=name,
+                            dense=args.dense,
+                            cpu_seconds=(3.0 if small and not args.no_cpu_baseline else None))
+        print(json.dumps(out), flush=True)
 
 
 def registered_system(system):

@@ -110,7 +110,8 @@ def erk_tableau(method):
                 ew=ew[:s].copy(), order=o.value, q_emb=q.value)
 
 
-COUNT_UNITS = ("trial", "accept", "side_fwd", "adj_step", "adj_side", "adj_zero")
+COUNT_UNITS = ("trial", "accept", "side_fwd", "adj_step", "adj_side", "adj_zero", "dense_fwd",
+               "dense_adj")
 
 
 def count_ops(method, system):
@@ -118,7 +119,7 @@ def count_ops(method, system):
     oracle's own step routines on an operation-counting scalar (fma 2; +, -,
     *, /, min, max, sqrt, tanh and the controller's root 1; negation, abs and
     comparisons 0).  Returns a dict over COUNT_UNITS."""
-    out = np.zeros(6, np.int64)
+    out = np.zeros(8, np.int64)
     if _load().oracle_count_ops(method, system, _p(out, _i64)) != 0:
         raise ValueError(f"no counts for method {method} on system {system}")
     return dict(zip(COUNT_UNITS, (int(v) for v in out)))

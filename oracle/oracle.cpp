@@ -973,6 +973,27 @@ struct LossArgs {
   double scale;
 };
 
+// The reverse of one dense save (the continuous extension of the step from
+// y0 to y1 of size h, at offset dt) with cotangent w: the cotangents of the
+// two end states, lo = a0 w + f_y(y0)^T (h c0 w) and hi = a1 w +
+// f_y(y1)^T (h c1 w), and the parameter terms of both VJPs into gp.
+template <class T>
+static void dense_save_vjp(int sys, int d, const T* y0, const T* y1, const T* p, double h,
+                           double dt, const T* w, T* lo, T* hi, T* gp) {
+  const Hermite H = hermite(dt / h);
+  T v0[DMAX], v1[DMAX], g0[DMAX], g1[DMAX];
+  for (int c = 0; c < d; ++c) {
+    v0[c] = T(h * H.c0) * w[c];
+    v1[c] = T(h * H.c1) * w[c];
+  }
+  vjp(sys, y0, p, v0, g0, gp);
+  vjp(sys, y1, p, v1, g1, gp);
+  for (int c = 0; c < d; ++c) {
+    lo[c] = T(H.a0) * w[c] + g0[c];
+    hi[c] = T(H.a1) * w[c] + g1[c];
+  }
+}
+
 // One component's loss cotangent w at a save state's value v and its loss
 // term (added into loss): sum of squares v^2 (w = 2 scale v), squared
 // difference to a target (v - x)^2 (w = 2 scale (v - x)), or a given
@@ -1056,19 +1077,13 @@ static double adjoint_lane(const MeshArgs& M, const LossArgs& L, int lane,
         for (int c = 0; c < d; ++c) lpt[(size_t)S * d + c] += w[c];
         continue;
       }
-      const double h = hrow[i];
-      const Hermite H = hermite(sdt[s2] / h);
       // y(theta) = a0 y_i + a1 y_{i+1} + h (c0 f(y_i) + c1 f(y_{i+1}))
-      double v0[DMAX], v1[DMAX], g0[DMAX], g1[DMAX];
+      double lo[DMAX], hi[DMAX];
+      dense_save_vjp(M.sys, d, &ys[(size_t)i * d], &ys[(size_t)(i + 1) * d], p, hrow[i],
+                     sdt[s2], w, lo, hi, gp);
       for (int c = 0; c < d; ++c) {
-        v0[c] = h * H.c0 * w[c];
-        v1[c] = h * H.c1 * w[c];
-      }
-      vjp(M.sys, &ys[(size_t)i * d], p, v0, g0, gp);
-      vjp(M.sys, &ys[(size_t)(i + 1) * d], p, v1, g1, gp);
-      for (int c = 0; c < d; ++c) {
-        lpt[(size_t)i * d + c] += H.a0 * w[c] + g0[c];
-        lpt[(size_t)(i + 1) * d + c] += H.a1 * w[c] + g1[c];
+        lpt[(size_t)i * d + c] += lo[c];
+        lpt[(size_t)(i + 1) * d + c] += hi[c];
       }
     }
   } else {
@@ -1774,6 +1789,11 @@ int oracle_adjoint(int sys, int method, int n, int params_shared,
 //               the base point's
 //   5 adj_zero  a save on a mesh point in the sweep (cotangent, loss term,
 //               addition)
+//   6 dense_fwd a dense save of the record: the continuous extension from
+//               the step's end states (both slopes counted, as evaluated here)
+//   7 dense_adj a dense save of the sweep: the extension recomputed, the
+//               sum-of-squares cotangent and loss term, its reverse (two
+//               VJPs), and both end states' additions
 // Time bookkeeping (t + h, the end-of-span clip, the underflow test) is not
 // counted.  Returns 0, or -1 for an unknown pair.
 int oracle_count_ops(int method, int sys, int64_t* out) {
@@ -1844,6 +1864,12 @@ int oracle_count_ops(int method, int sys, int64_t* out) {
   });
   out[4] = out[3] + update + cot + add;
   out[5] = cot + add;
+  OpCount y1[DMAX], lo[DMAX], hi[DMAX];
+  for (int c = 0; c < d; ++c) y1[c] = OpCount(0.35 + 0.1 * c);
+  out[6] = count([&] { dense_state(sys, d, y, y1, p.data(), 1e-3, 4e-4, w); });
+  out[7] = out[6] + cot +
+           count([&] { dense_save_vjp(sys, d, y, y1, p.data(), 1e-3, 4e-4, lam, lo, hi, gp.data()); }) +
+           2 * add;
   return 0;
 }
 

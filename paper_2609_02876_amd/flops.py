@@ -24,30 +24,36 @@ Per-unit figures, per (method, system):
              adj_step plus y_new from the recomputed stages, the loss
              cotangent and term, and the addition into the base cotangent
   adj_zero   one save time on a mesh point in the reverse sweep
+  dense_fwd  one dense save of the record (dense output): the continuous
+             extension from the step's end states and slopes
+  dense_adj  one dense save of the sweep: the extension recomputed, the loss
+             cotangent and term, its reverse (a VJP at each end state), and
+             the two additions into the end states' cotangents
 
 These are operation counts of the method's steps exactly as the plain CPU
 reference performs them, counted there by an operation-counting scalar; a
 CPU test keeps every entry equal to that count.
 """
 
-UNITS = ("trial", "accept", "side_fwd", "adj_step", "adj_side", "adj_zero")
+UNITS = ("trial", "accept", "side_fwd", "adj_step", "adj_side", "adj_zero", "dense_fwd",
+         "dense_adj")
 
 PER_UNIT = {
-    ("tsit5", "lorenz"): (257, 1, 184, 417, 468, 12),
-    ("vern7", "lorenz"): (431, 9, 313, 705, 762, 12),
-    ("tsit5", "vdp"): (171, 1, 121, 274, 308, 8),
-    ("vern7", "vdp"): (286, 6, 206, 464, 502, 8),
-    ("tsit5", "linear"): (177, 1, 126, 286, 320, 8),
-    ("vern7", "linear"): (295, 7, 214, 482, 520, 8),
+    ("tsit5", "lorenz"): (257, 1, 184, 417, 468, 12, 40, 113),
+    ("vern7", "lorenz"): (431, 9, 313, 705, 762, 12, 40, 113),
+    ("tsit5", "vdp"): (171, 1, 121, 274, 308, 8, 26, 74),
+    ("vern7", "vdp"): (286, 6, 206, 464, 502, 8, 26, 74),
+    ("tsit5", "linear"): (177, 1, 126, 286, 320, 8, 28, 78),
+    ("vern7", "linear"): (295, 7, 214, 482, 520, 8, 28, 78),
     # Lotka-Volterra + 2-32-32-2 tanh MLP: the field costs 2,377 and its
     # vector-Jacobian product 7,257 (it recomputes the hidden layers)
-    ("tsit5", "ude"): (14403, 1, 11981, 57970, 58004, 8),
-    ("rodas4", "robertson"): (390, 1, 364, 983, 998, 12),
-    ("rodas4", "hires"): (1855, 1, 1794, 3919, 3959, 32),
-    ("rodas4", "linear"): (233, 1, 214, 539, 549, 8),
-    ("ros23", "robertson"): (177, 1, 101, 251, 275, 12),
-    ("ros23", "hires"): (1003, 1, 714, 1271, 1335, 32),
-    ("ros23", "linear"): (101, 1, 52, 123, 139, 8),
+    ("tsit5", "ude"): (14403, 1, 11981, 57970, 58004, 8, 4770, 19306),
+    ("rodas4", "robertson"): (390, 1, 364, 983, 998, 12, 40, 121),
+    ("rodas4", "hires"): (1855, 1, 1794, 3919, 3959, 32, 136, 386),
+    ("rodas4", "linear"): (233, 1, 214, 539, 549, 8, 28, 78),
+    ("ros23", "robertson"): (177, 1, 101, 251, 275, 12, 40, 121),
+    ("ros23", "hires"): (1003, 1, 714, 1271, 1335, 32, 136, 386),
+    ("ros23", "linear"): (101, 1, 52, 123, 139, 8, 28, 78),
 }
 
 # (state dim, f, its VJP, the Jacobian, d/d(y, p) of u^T J v) per evaluation
@@ -65,14 +71,18 @@ def per_unit(method, system):
     return dict(zip(UNITS, PER_UNIT[(method, system)]))
 
 
-def record_flops(method, system, trials, accepted, side_steps):
+def record_flops(method, system, trials, accepted, side_steps, dense=False):
+    """side_steps: saves of nonzero offset from their base point (extra steps,
+    or with dense output, interpolated saves)."""
     u = per_unit(method, system)
-    return u["trial"] * trials + u["accept"] * accepted + u["side_fwd"] * side_steps
+    per_save = u["dense_fwd"] if dense else u["side_fwd"]
+    return u["trial"] * trials + u["accept"] * accepted + per_save * side_steps
 
 
-def adjoint_flops(method, system, accepted, side_steps, zero_sides):
+def adjoint_flops(method, system, accepted, side_steps, zero_sides, dense=False):
     u = per_unit(method, system)
-    return u["adj_step"] * accepted + u["adj_side"] * side_steps + u["adj_zero"] * zero_sides
+    per_save = u["dense_adj"] if dense else u["adj_side"]
+    return u["adj_step"] * accepted + per_save * side_steps + u["adj_zero"] * zero_sides
 
 
 # ------------------------------------------------------------ forward mode --

@@ -79,3 +79,9 @@ def test_explicit_counts_from_the_tableau_pattern(method, system):
     assert c["adj_step"] == adj
     assert c["adj_side"] == adj + update + 3 * d + d
     assert c["adj_zero"] == 3 * d + d
+    # dense save: the two end slopes, then per component the four weighted
+    # terms and their three additions plus the product by h (8); its reverse
+    # adds the cotangent (3d), the two weighted cotangents (2d), two VJPs,
+    # lo and hi (a product and an addition each: 4d) and their additions (2d)
+    assert c["dense_fwd"] == 2 * f + 8 * d
+    assert c["dense_adj"] == c["dense_fwd"] + 3 * d + 2 * d + 2 * v + 4 * d + 2 * d
