@@ -483,7 +483,12 @@ int launch_forward_body(const ens_problem* p, int mode, bool ckpt, const FwdArgs
       else
         return fail(ENS_EUNSUPPORTED, "dense output is not built for this mode");
       hipError_t e = hipGetLastError();
-      return e == hipSuccess ? ENS_OK : hip_fail(e, "dense forward launch");
+      if (e != hipSuccess) return hip_fail(e, "dense forward launch");
+      if (mode == MODE_SOLVE) return ENS_OK;
+      // the records note each save's step; the states come from its extension
+      hipLaunchKernelGGL((dense_saves_kernel<Sys, T>), g, b, 0, st, fa);
+      e = hipGetLastError();
+      return e == hipSuccess ? ENS_OK : hip_fail(e, "dense save-state launch");
     });
   }
   if (is_rtc(p->system))
@@ -754,6 +759,11 @@ int ensemble_mesh_export(const ens_record* r, double* h, int32_t* steps,
   return e == hipSuccess ? ENS_OK : hip_fail(e, "export launch");
 }
 
+// Dense output: the mesh point of each of the sweep's 2 n_save events, [2 n_save][n].
+size_t events_bytes(const ens_record* r) {
+  return align256((size_t)2 * r->n_save * r->n * sizeof(int32_t));
+}
+
 // The sweep's per-save cotangents for their base states, [n_save][dim][n].
 size_t contrib_bytes(const ens_record* r) {
   return align256((size_t)(r->dense ? 2 : 1) * r->n_save * r->dim * r->n * elem_size(r->dtype));
@@ -767,6 +777,7 @@ int ensemble_adjoint_workspace_bytes(const ens_record* r, size_t* bytes) {
   if (r->params_shared) b = partials_bytes(r->system, r->n, si.np, r->dtype);
   if (r->ckpt_every > 0) b += align256((size_t)r->n * r->page_steps * rec_bytes(r->dtype, r->dim));
   if (r->system != ENS_SYS_LV_UDE) b += contrib_bytes(r);
+  if (r->dense) b += events_bytes(r);
   *bytes = b;
   return ENS_OK;
 }
@@ -875,6 +886,8 @@ int adjoint_impl(const ens_problem* p, const ens_ivp* v, const ens_record* r,
     aa.scratch = ckpt ? w : nullptr;
     if (ckpt) w += align256((size_t)r->n * r->page_steps * rec_bytes(r->dtype, r->dim));
     aa.contrib = p->system != ENS_SYS_LV_UDE ? w : nullptr;
+    if (p->system != ENS_SYS_LV_UDE) w += contrib_bytes(r);
+    aa.events = r->dense ? (int32_t*)w : nullptr;
   }
   hipStream_t st = (hipStream_t)stream;
   if (p->system == ENS_SYS_LV_UDE) {

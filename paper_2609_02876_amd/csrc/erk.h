@@ -73,6 +73,8 @@ struct AdjArgs {
   void* workspace;        // shared parameters: [n_blocks][NP] partials
   void* scratch;          // checkpointed tape: [n][page_steps] step records
   void* contrib;          // [n_save][D][n]: each save's cotangent for its base state
+                          // (dense output: [2 n_save][D][n], one per event below)
+  int32_t* events;        // dense output: [2 n_save][n] mesh point of each cotangent
 };
 
 // ------------------------------------------------------------ one step --
@@ -570,10 +572,12 @@ __device__ __forceinline__ void hermite_state(const T* y0, const T* y1, const T*
 // parallel with the same step map: the same values, and a loop with fewer
 // iterations and less state.
 //
-// DENSE (dense output): no side steps either; each save time inside an
-// accepted step takes the step's continuous extension at once, from the
-// step's end states and slopes.  The record keeps both end states of the
-// step (save_base and save_base_hi) and its size (save_h) for the sweep.
+// DENSE (dense output): no side steps either.  A record notes, for each save
+// time inside an accepted step, both end states of the step (save_base and
+// save_base_hi), its size (save_h) and the save's offset; dense_saves_kernel
+// then forms the states from the step's continuous extension, and the sweep
+// reads the same notes.  The solve, which keeps nothing, takes the extension
+// at once in the loop.
 template <class Sys, class Tab, class T, int MODE, bool CKPT, bool DEFER = false,
           bool DENSE = false>
 __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block) {
@@ -867,8 +871,30 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         h = hh * fmax(0.2, fmin(prev_rej ? 1.0 : 10.0, fac0));
         prev_rej = false;
       }
-      if constexpr (DENSE) {
-        // saves inside this step: the step's continuous extension
+      if constexpr (DENSE && MODE != MODE_SOLVE) {
+        // saves inside this step: the step's end states, size and the save's
+        // offset are noted, and dense_saves_kernel forms the states from
+        // them afterwards, all (trajectory, save) pairs in parallel
+        while (ts < tnew) {
+          *sidx_out = S - 1;
+          *sdt_out = ts - t;
+          sidx_out += n;
+          sdt_out += n;
+          put_base(y, true);
+          put_dense(ynew, hh);
+          ys_out += ys_stride;
+          ++next_save;
+          ts = s_times[next_save];
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          y[c] = ynew[c];
+          if constexpr (Tab::FSAL) k1[c] = klast[c];
+        }
+        t = tnew;
+      } else if constexpr (DENSE) {
+        // the solve keeps nothing: saves inside this step take the step's
+        // continuous extension at once
         if (ts < tnew) {
           T f0[D], f1[D], yd[D];
           if constexpr (Tab::FSAL) {
@@ -1135,8 +1161,14 @@ __device__ __forceinline__ void save_steps_reverse(const AdjArgs& a, int64_t tr,
 // reverse of the extension.  With y(theta) = a0 y0 + a1 y1 + h (c0 f(y0) +
 // c1 f(y1)), the end states receive a0 w + f_y(y0)^T (h c0 w) and
 // a1 w + f_y(y1)^T (h c1 w), and g the parameter terms of both VJPs.  The
-// two cotangents go to a.contrib ([n_save][D][n], for y0) and to the half
-// after it (for y1); a save at the last mesh point gives w to y_S alone.
+// saves of one step are summed (from the last), and the step's two sums
+// become two events: (end point, sum for y1), then (start point, sum for
+// y0); a save at the last mesh point gives w to y_S alone.  Events are
+// written from the top slot of a.events / a.contrib down, so that their
+// mesh points increase with the slot, as the save bookkeeping's do; unused
+// slots carry point -1.  The sweep then takes them as it takes plain saves,
+// so at a mesh point the sums of the step that starts there are added
+// before those of the step that ends there.
 template <class Sys, class T>
 __device__ __forceinline__ void dense_saves_reverse(const AdjArgs& a, int64_t tr, const T* p,
                                                     T two_scale, T* g, double& loss) {
@@ -1144,24 +1176,34 @@ __device__ __forceinline__ void dense_saves_reverse(const AdjArgs& a, int64_t tr
   const RecView& R = a.rec;
   const int64_t n = a.ivp.n;
   T* cb = (T*)a.contrib;
-  T* cb_hi = cb + (int64_t)R.n_save * D * n;
+  int32_t* ev = a.events;
   const T* b0 = (const T*)R.save_base;
   const T* b1 = (const T*)R.save_base_hi;
+  int slot = 2 * R.n_save - 1;
+  auto emit = [&](int32_t point, const T* v) {
+    ev[(int64_t)slot * n + tr] = point;
+#pragma unroll
+    for (int c = 0; c < D; ++c) cb[((int64_t)slot * D + c) * n + tr] = v[c];
+    --slot;
+  };
+  T acc_lo[D], acc_hi[D];
+  int32_t gidx = -1;
+  double gh = 0.0;
   for (int ss = R.n_save - 1; ss >= 0; --ss) {
+    const int32_t idx = R.save_idx[(int64_t)ss * n + tr];
     const double dt = R.save_dt[(int64_t)ss * n + tr];
     const double hs = R.save_h[(int64_t)ss * n + tr];
-    T y0[D], y1[D], lo[D], hi[D];
+    T y0[D], lo[D], hi[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      y0[c] = b0[((int64_t)ss * D + c) * n + tr];
-      y1[c] = b1[((int64_t)ss * D + c) * n + tr];
-    }
+    for (int c = 0; c < D; ++c) y0[c] = b0[((int64_t)ss * D + c) * n + tr];
     if (hs == 0.0) {  // at the last mesh point: the state itself
       save_cotangent<T, D>(a, ss, tr, y0, two_scale, lo, loss);
 #pragma unroll
       for (int c = 0; c < D; ++c) hi[c] = T(0);
     } else {
-      T f0[D], f1[D], ys[D], w[D], v0[D], v1[D], g0[D], g1[D];
+      T y1[D], f0[D], f1[D], ys[D], w[D], v0[D], v1[D], g0[D], g1[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) y1[c] = b1[((int64_t)ss * D + c) * n + tr];
       Sys::rhs(y0, p, f0);
       Sys::rhs(y1, p, f1);
       hermite_state<T, D>(y0, y1, f0, f1, hs, dt, ys);
@@ -1180,12 +1222,32 @@ __device__ __forceinline__ void dense_saves_reverse(const AdjArgs& a, int64_t tr
         hi[c] = fmaT(T(hw.a1), w[c], g1[c]);
       }
     }
+    if (gidx >= 0 && idx != gidx) {  // the previous step's saves are complete
+      if (gh > 0.0) emit(gidx + 1, acc_hi);
+      emit(gidx, acc_lo);
+      gidx = -1;
+    }
+    if (gidx < 0) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      cb[((int64_t)ss * D + c) * n + tr] = lo[c];
-      cb_hi[((int64_t)ss * D + c) * n + tr] = hi[c];
+      for (int c = 0; c < D; ++c) {
+        acc_lo[c] = lo[c];
+        acc_hi[c] = hi[c];
+      }
+      gidx = idx;
+      gh = hs;
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        acc_lo[c] = acc_lo[c] + lo[c];
+        acc_hi[c] = acc_hi[c] + hi[c];
+      }
     }
   }
+  if (gidx >= 0) {
+    if (gh > 0.0) emit(gidx + 1, acc_hi);
+    emit(gidx, acc_lo);
+  }
+  for (; slot >= 0; --slot) ev[(int64_t)slot * n + tr] = -1;
 }
 
 // Slot (trajectory offset in the block) this lane sweeps.  The block's 256
@@ -1224,9 +1286,8 @@ __device__ __forceinline__ int sweep_slot(const RecView& R, int64_t base, int64_
 //
 // DENSE: the saves come from the continuous extension of the step holding
 // each one (dense_saves_reverse); each save's cotangent reaches both end
-// states of its step, so the loop takes two streams of cotangents: at mesh
-// point i, those of the saves whose step ends at i, then of the saves whose
-// step starts at i (each from the last save to the first).
+// states of its step, and the loop takes the resulting events (a mesh point
+// and a cotangent each) as it takes plain saves.
 template <class Sys, class Tab, class T, bool SHARED, bool CKPT, bool DENSE = false>
 __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block) {
   constexpr int D = Sys::D, NP = Sys::NP, SU = Tab::SU;
@@ -1275,8 +1336,9 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
 
   // Save bookkeeping, walked from the last save to the first: the save's
   // base index and its cotangent in a.contrib.
-  int s = R.n_save - 1;
-  const int32_t* sidx_p = R.save_idx + (int64_t)s * n + tr;
+  // (dense output: the events of dense_saves_reverse, in the same layout)
+  int s = (DENSE ? 2 * R.n_save : R.n_save) - 1;
+  const int32_t* sidx_p = (DENSE ? a.events : R.save_idx) + (int64_t)s * n + tr;
   const T* cb_p = (const T*)a.contrib + (int64_t)s * D * n + tr;
   int32_t sidx = *sidx_p;
   auto next_save = [&]() {
@@ -1310,24 +1372,8 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   };
   if (CKPT && S > 0) start_segment(slot + 1);
 
-  // dense output: the saves whose step ends at mesh point i (base index
-  // i - 1, and not at the last point), walked by a second cursor
-  int s_hi = R.n_save - 1;
-  int32_t sidx_hi = DENSE ? R.save_idx[(int64_t)s_hi * n + tr] : 0;
-  const T* cbh_p = (const T*)a.contrib + ((int64_t)R.n_save + s_hi) * D * n + tr;
   // the saves based at mesh point i, from the last: their cotangents into lam
   auto take_saves = [&]() {
-    if constexpr (DENSE) {
-      while (s_hi >= 0 && sidx_hi + 1 >= i) {
-        if (sidx_hi + 1 == i) {
-#pragma unroll
-          for (int c = 0; c < D; ++c) lam[c] = lam[c] + cbh_p[c * n];
-        }
-        --s_hi;
-        cbh_p -= D * n;
-        if (s_hi >= 0) sidx_hi = R.save_idx[(int64_t)s_hi * n + tr];
-      }
-    }
     while (s >= 0 && sidx == i) {
 #pragma unroll
       for (int c = 0; c < D; ++c) lam[c] = lam[c] + cb_p[c * n];
@@ -1539,6 +1585,40 @@ __global__ void __launch_bounds__(256) erk_saves_kernel(const FwdArgs a) {
     Sys::rhs(y, p, k0);
     step_push<Sys, Tab, T, SU, true, true, false>(y, k0, p, T(dt), Yd, ylast, klast, ys,
                                                   nullptr);
+#pragma unroll
+    for (int c = 0; c < D; ++c) ysv[((int64_t)s * D + c) * n + tr] = ys[c];
+  }
+}
+
+// Save states of a dense record: for each trajectory and each save noted
+// inside an accepted step (step size h > 0), the step's continuous extension
+// from the recorded end states, at the noted offset (saves at the last mesh
+// point were written by the record itself).
+template <class Sys, class T>
+__global__ void __launch_bounds__(256) dense_saves_kernel(const FwdArgs a) {
+  constexpr int D = Sys::D, NP = Sys::NP;
+  const int64_t n = a.ivp.n;
+  const int64_t tr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tr >= n) return;
+  const RecView& R = a.rec;
+  T p[NP];
+  load_params<T, NP>(a.ivp, tr, p);
+  T* ysv = (T*)a.y_save;
+  const T* b0 = (const T*)R.save_base;
+  const T* b1 = (const T*)R.save_base_hi;
+  for (int s = 0; s < a.ivp.n_save; ++s) {
+    const int32_t i = R.save_idx[(int64_t)s * n + tr];
+    const double hs = R.save_h[(int64_t)s * n + tr];
+    if (i < 0 || !(hs > 0.0)) continue;
+    T y0[D], y1[D], f0[D], f1[D], ys[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      y0[c] = b0[((int64_t)s * D + c) * n + tr];
+      y1[c] = b1[((int64_t)s * D + c) * n + tr];
+    }
+    Sys::rhs(y0, p, f0);
+    Sys::rhs(y1, p, f1);
+    hermite_state<T, D>(y0, y1, f0, f1, hs, R.save_dt[(int64_t)s * n + tr], ys);
 #pragma unroll
     for (int c = 0; c < D; ++c) ysv[((int64_t)s * D + c) * n + tr] = ys[c];
   }
