@@ -60,8 +60,13 @@ def parse():
                     help="no GPU run: turn the counter output of two rocprofv3 --pmc runs of this "
                          "script (FETCH_SIZE, then WRITE_SIZE, both with --copy-calibration) into "
                          "profiles/<workload>_traffic.json")
-    ap.add_argument("--serve-jobs", type=int, default=120,
+    ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs in the serving workload (--workload serve_mix)")
+    ap.add_argument("--serve-max-log2", type=int, default=18,
+                    help="job sizes are log-uniform in 2^8..2^this lanes")
+    ap.add_argument("--serve-repeat", type=int, default=3,
+                    help="the Poisson streams submit the job list this many times (each time "
+                         "in a new random order), so that a window lasts several seconds")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="offered loads (fractions of the one-shot capacity)")
     return ap.parse_args()
@@ -801,12 +806,17 @@ def forward_bench(args):
 
 def serve_bench(args):
     """Mixed ensemble-gradient jobs through the server (continuous batching)
-    against the same trajectories as one-shot launches, one per (system, rtol)
-    group, and as plain per-job launches.  Jobs: systems uniform over Lorenz,
-    Van der Pol (Tsit5), Robertson and HIRES (Rodas4); lanes 2^(8 + 8u);
+    against the same trajectories as one-shot launches (each (system, rtol)
+    group's trajectories in launches of up to 2^20) and as plain per-job
+    launches.  Jobs: systems uniform over Lorenz, Van der Pol (Tsit5),
+    Robertson and HIRES (Rodas4); lanes log-uniform in 2^8..2^max;
     rtol in {1e-4, 1e-6, 1e-8} (HIRES: 1e-4, 1e-6); atol = 1e-2 rtol
     (explicit) or 1e-4 rtol (stiff); loss = |y(t1)|^2; parameters seeded by
-    the job id; FP64."""
+    the job id; FP64.  Served passes: everything submitted at once (the
+    served capacity), then Poisson streams whose offered trajectory rate is a
+    fraction of the one-shot capacity; each stream submits the job list
+    --serve-repeat times, so that its window lasts repeat x total / (load x
+    capacity) seconds."""
     import numpy as np
     import torch
 
@@ -814,14 +824,18 @@ def serve_bench(args):
     from paper_2609_02876_amd import serving as SV
     from paper_2609_02876_amd import workloads as W
 
+    def note(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
     span = {"lorenz": 10.0, "vdp": 6.3, "robertson": 1e5, "hires": 321.8122}
     method = {"lorenz": "tsit5", "vdp": "tsit5", "robertson": "rodas4", "hires": "rodas4"}
     rng = np.random.default_rng(2026)
     dev = torch.device("cuda:0")
+    span_log2 = args.serve_max_log2 - 8
     jobs = []
     for k in range(args.serve_jobs):
         system = ["lorenz", "vdp", "robertson", "hires"][int(rng.integers(0, 4))]
-        n = int(round(2 ** (8 + 8 * rng.random())))
+        n = int(round(2 ** (8 + span_log2 * rng.random())))
         rtols = [1e-4, 1e-6] if system == "hires" else [1e-4, 1e-6, 1e-8]
         rtol = rtols[int(rng.integers(0, len(rtols)))]
         atol = rtol * (1e-2 if system in ("lorenz", "vdp") else 1e-4)
@@ -832,83 +846,138 @@ def serve_bench(args):
     groups = {}
     for j in jobs:
         groups.setdefault((j["system"], j["rtol"]), []).append(j)
+    total = sum(j["n"] for j in jobs)
+    note(f"{len(jobs)} jobs, {total} trajectories, {len(groups)} (system, rtol) groups")
 
-    # memory plan per group: a pilot record's longest trajectory, +20 %
+    # memory plan per group: the longest trajectory of a pilot record (up to
+    # 16384 trajectories of the group's largest job), +20 %
     hints = {}
     for (system, rtol), js in groups.items():
-        j = js[0]
-        h = B.ensemble_record(system, j["method"], j["y0"], j["p"], 0.0, span[system], rtol,
-                              j["atol"], steps_hint=4096)
+        j = max(js, key=lambda x: x["n"])
+        m = min(j["n"], 16384)
+        h = B.ensemble_record(system, j["method"], j["y0"][:, :m].contiguous(),
+                              j["p"][:, :m].contiguous(), 0.0, span[system], rtol, j["atol"],
+                              steps_hint=4096)
         hints[(system, rtol)] = int(h.steps().max().item() * 1.2) + 32
+        del h
     for j in jobs:
         j["hint"] = hints[(j["system"], j["rtol"])]
-    total = sum(j["n"] for j in jobs)
+    note("pilot plans done")
 
-    def run_plain(j):
+    def run_plain(j, keep=False):
         h = B.ensemble_record(j["system"], j["method"], j["y0"], j["p"], 0.0, span[j["system"]],
                               j["rtol"], j["atol"], steps_hint=j["hint"])
-        B.ensemble_adjoint(h, want_y0=True, want_loss=True)
-        return h
+        gp, gy, ll = B.ensemble_adjoint(h, want_y0=True, want_loss=True)
+        return (h.y_save, h.status, gp, gy, ll) if keep else None
 
-    # one-shot: all trajectories of a (system, rtol) group as one ensemble
-    cat = {key: dict(js[0], y0=torch.cat([j["y0"] for j in js], 1),
-                     p=torch.cat([j["p"] for j in js], 1), n=sum(j["n"] for j in js))
-           for key, js in groups.items()}
-    for c in cat.values():
-        run_plain(c)
+    # one-shot: each (system, rtol) group's trajectories as one ensemble, in
+    # launches of at most 2^20 trajectories.  Each group is run once untimed
+    # (which also leaves its record buffers in torch's cache) and then timed,
+    # so the timed launches allocate nothing; the cache is emptied between
+    # groups to bound the memory held.
+    chunk = 1 << 20
+    t_oneshot = 0.0
+    for key, js in groups.items():
+        y0 = torch.cat([j["y0"] for j in js], 1)
+        pp = torch.cat([j["p"] for j in js], 1)
+        parts = [dict(js[0], y0=y0[:, a:a + chunk].contiguous(), p=pp[:, a:a + chunk].contiguous())
+                 for a in range(0, y0.shape[1], chunk)]
+        del y0, pp
+        torch.cuda.empty_cache()
+        for c in parts:
+            run_plain(c)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for c in parts:
+            run_plain(c)
+        torch.cuda.synchronize()
+        t_oneshot += time.perf_counter() - t
+        del parts
+    torch.cuda.empty_cache()
+    cap = total / t_oneshot
+    note(f"one-shot: {t_oneshot:.2f} s, {cap:.4g} trajectory-gradients/s")
+
+    # plain per-job launches; the outputs of a sample of jobs are kept to
+    # check the served results against them
+    sample = sorted(set(int(x) for x in rng.choice(len(jobs), 16, replace=False)))
+    plain = {}
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for c in cat.values():
-        run_plain(c)
-    torch.cuda.synchronize()
-    t_oneshot = time.perf_counter() - t
-    t = time.perf_counter()
-    for j in jobs:
-        run_plain(j)
+    for k, j in enumerate(jobs):
+        out = run_plain(j, keep=k in sample)
+        if out is not None:
+            plain[k] = out
     torch.cuda.synchronize()
     t_perjob = time.perf_counter() - t
-    cap = total / t_oneshot
+    note(f"per-job launches: {t_perjob:.2f} s")
 
-    pool = max(sum(B.ensemble_record_bytes(j["system"], j["method"], j["n"], 0.0,
-                                           span[j["system"]], j["hint"]) for j in jobs) // 3,
-               4 << 30)
+    # the pool: a third of what all the jobs' records would take at once,
+    # at least 2.5 times the largest job, at most 96 GB
+    need = [B.ensemble_record_bytes(j["system"], j["method"], j["n"], 0.0, span[j["system"]],
+                                    j["hint"]) for j in jobs]
+    pool = int(min(max(sum(need) // 3, int(2.5 * max(need)), 4 << 30), 96e9))
+    torch.cuda.empty_cache()
 
-    def serve(load):
+    def serve(load, keep=(), repeat=1):
         srv = SV.Server(pool, n_slots=4)
-        arrive = np.cumsum(rng.exponential(total / len(jobs) / (load * cap), len(jobs))) \
-            if load else np.zeros(len(jobs))
+        seq = [k for _ in range(repeat) for k in rng.permutation(len(jobs))] if repeat > 1 \
+            else list(range(len(jobs)))
+        arrive = np.cumsum(rng.exponential(total / len(jobs) / (load * cap), len(seq))) \
+            if load else np.zeros(len(seq))
+        served = {}
         t0 = time.perf_counter()
-        for k, j in enumerate(jobs):
-            while time.perf_counter() - t0 < arrive[k]:
+        for a, k in zip(arrive, seq):
+            j = jobs[k]
+            while time.perf_counter() - t0 < a:
                 srv.progress()
-            srv.submit(j["system"], j["method"], j["y0"], j["p"], 0.0, span[j["system"]],
-                       j["rtol"], j["atol"], steps_hint=j["hint"])
+            sj = srv.submit(j["system"], j["method"], j["y0"], j["p"], 0.0, span[j["system"]],
+                            j["rtol"], j["atol"], steps_hint=j["hint"])
+            if k in keep:
+                served[k] = sj
         srv.drain()
         st = srv.stats()
+        st["window_s"] = float(arrive[-1])
         srv.close()
-        return st
+        return st, served
 
     serve(0)  # warm-up
-    sat = serve(0)   # everything submitted at once: the served capacity
+    sat, served = serve(0, keep=sample)   # everything submitted at once: the served capacity
+    same = all(torch.equal(served[k].y_save, plain[k][0]) and
+               torch.equal(served[k].status, plain[k][1]) and
+               torch.equal(served[k].grad_params, plain[k][2]) and
+               torch.equal(served[k].grad_y0, plain[k][3]) and
+               torch.equal(served[k].loss, plain[k][4]) for k in sample)
+    del served, plain
+    note(f"saturated: {sat['throughput']:.4g} trajectory-gradients/s, "
+         f"{sat['throughput'] / cap:.3f} of one-shot; sampled jobs equal per-job runs: {same}")
     loads = {}
     for x in [float(v) for v in args.serve_loads.split(",") if v]:
-        st = serve(x)
-        loads[str(x)] = {"p50_ms": st["p50_latency_s"] * 1e3, "p99_ms": st["p99_latency_s"] * 1e3,
-                         "throughput": st["throughput"], "retried": st["retried"],
+        st, _ = serve(x, repeat=args.serve_repeat)
+        loads[str(x)] = {"offered": x * cap, "window_s": st["window_s"], "busy_s": st["busy_s"],
+                         "throughput": st["throughput"],
+                         "throughput_over_offered": st["throughput"] / (x * cap),
+                         "p50_ms": st["p50_latency_s"] * 1e3, "p99_ms": st["p99_latency_s"] * 1e3,
+                         "mean_ms": st["mean_latency_s"] * 1e3,
+                         "jobs": int(st["completed"]), "retried": st["retried"],
                          "failed": st["failed"]}
+        note(f"load {x}: {loads[str(x)]}")
     out = {
         "metric": "served trajectory-gradients/s (mixed jobs, continuous batching)",
         "value": sat["throughput"], "unit": "trajectory-gradients/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": sat["busy_s"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "serve_mix", "jobs": len(jobs), "trajectories": total,
-                   "systems": ["lorenz", "vdp", "robertson", "hires"], "lanes": "2^(8+8u)",
-                   "rtol": [1e-4, 1e-6, 1e-8], "slots": 4, "pool_gb": pool / 1e9},
+                   "systems": ["lorenz", "vdp", "robertson", "hires"],
+                   "lanes": f"2^(8+{span_log2}u)", "rtol": [1e-4, 1e-6, 1e-8], "slots": 4,
+                   "pool_gb": pool / 1e9, "oneshot_launch_max": chunk,
+                   "poisson_repeat": args.serve_repeat},
         "oneshot_throughput": cap,
         "served_over_oneshot": sat["throughput"] / cap,
         "perjob_throughput": total / t_perjob,
         "saturated": {"p50_ms": sat["p50_latency_s"] * 1e3, "p99_ms": sat["p99_latency_s"] * 1e3,
-                      "retried": sat["retried"], "failed": sat["failed"]},
+                      "retried": sat["retried"], "failed": sat["failed"],
+                      "pool_peak_gb": sat["pool_peak"] / 1e9},
+        "sampled_jobs_equal_perjob": bool(same),
         "poisson_loads": loads,
     }
     print(json.dumps(out), flush=True)
