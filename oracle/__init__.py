@@ -76,7 +76,8 @@ def _load():
                                        I, _d, D, _d, _d, _d, I]
         lib.oracle_count_ops.argtypes = [I, I, _i64]
         lib.oracle_count_system.argtypes = [I, _i64]
-        for f in ("oracle_count_ops", "oracle_count_system", "oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp", "oracle_jac",
+        lib.oracle_count_lu.argtypes = [I, _i64]
+        for f in ("oracle_count_ops", "oracle_count_system", "oracle_count_lu", "oracle_dims", "oracle_erk_tableau", "oracle_rhs", "oracle_vjp", "oracle_jac",
                   "oracle_jac_vjp", "oracle_ros_tableau",
                   "oracle_record", "oracle_replay", "oracle_replay_dual",
                   "oracle_replay_complex", "oracle_adjoint"):
@@ -123,6 +124,17 @@ def count_ops(method, system):
     if _load().oracle_count_ops(method, system, _p(out, _i64)) != 0:
         raise ValueError(f"no counts for method {method} on system {system}")
     return dict(zip(COUNT_UNITS, (int(v) for v in out)))
+
+
+def count_lu(system):
+    """(factorisation, solve, transposed solve) operation counts of W =
+    I/(gamma h) - J at the counting point, operations on exact zeros left
+    out, and the number of rows the pivoting moved there (0: the zeros are
+    the Jacobian's structural zeros)."""
+    out = np.zeros(4, np.int64)
+    if _load().oracle_count_lu(system, _p(out, _i64)) != 0:
+        raise ValueError(f"no linear algebra for system {system}")
+    return tuple(int(v) for v in out)
 
 
 def count_system(system):

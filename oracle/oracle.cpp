@@ -75,20 +75,37 @@ inline double value_of(Cplx x) { return x.real(); }
 // min, max 1; sqrt, tanh and the controller's root 1; negation, abs and
 // comparisons 0).  Instantiating the step routines below on it counts the
 // work of one trial step, one reverse step, ... as this file performs it.
+//
+// Inside the linear algebra of W (factorisation and solves, marked by an
+// LuCount scope) an operation whose factor or term is exactly zero is not
+// counted, and an fma onto an exact zero counts as the product alone.  At the
+// counting point (a small step, so W is dominated by its diagonal and no rows
+// are interchanged) W's zeros are the structural zeros of the Jacobian, and
+// such operations only add or move a zero: the count is that of the sparse
+// factorisation.  The values computed are unchanged.
 thread_local int64_t g_ops = 0;
+thread_local int g_lu_scope = 0;
+struct LuCount {
+  LuCount() { ++g_lu_scope; }
+  ~LuCount() { --g_lu_scope; }
+};
 struct OpCount {
   double v;
   OpCount(double x = 0.0) : v(x) {}
 };
-inline OpCount operator+(OpCount a, OpCount b) { ++g_ops; return a.v + b.v; }
-inline OpCount operator-(OpCount a, OpCount b) { ++g_ops; return a.v - b.v; }
-inline OpCount operator*(OpCount a, OpCount b) { ++g_ops; return a.v * b.v; }
-inline OpCount operator/(OpCount a, OpCount b) { ++g_ops; return a.v / b.v; }
+inline bool lu_zero(double a, double b) { return g_lu_scope > 0 && (a == 0.0 || b == 0.0); }
+inline OpCount operator+(OpCount a, OpCount b) { g_ops += lu_zero(a.v, b.v) ? 0 : 1; return a.v + b.v; }
+inline OpCount operator-(OpCount a, OpCount b) { g_ops += lu_zero(a.v, b.v) ? 0 : 1; return a.v - b.v; }
+inline OpCount operator*(OpCount a, OpCount b) { g_ops += lu_zero(a.v, b.v) ? 0 : 1; return a.v * b.v; }
+inline OpCount operator/(OpCount a, OpCount b) { g_ops += lu_zero(a.v, 1.0) ? 0 : 1; return a.v / b.v; }
 inline OpCount operator-(OpCount a) { return -a.v; }
 inline OpCount& operator+=(OpCount& a, OpCount b) { a = a + b; return a; }
 inline bool operator==(OpCount a, OpCount b) { return a.v == b.v; }
 inline bool operator!=(OpCount a, OpCount b) { return a.v != b.v; }
-inline OpCount fma(OpCount a, OpCount b, OpCount c) { g_ops += 2; return std::fma(a.v, b.v, c.v); }
+inline OpCount fma(OpCount a, OpCount b, OpCount c) {
+  g_ops += lu_zero(a.v, b.v) ? 0 : lu_zero(c.v, 1.0) ? 1 : 2;
+  return std::fma(a.v, b.v, c.v);
+}
 inline OpCount tanh(OpCount a) { ++g_ops; return std::tanh(a.v); }
 inline double value_of(OpCount x) { return x.v; }
 
@@ -1214,6 +1231,7 @@ inline double absval(OpCount x) { return std::fabs(x.v); }
 // triangular solves multiply by it.
 template <class T>
 static void lu_factor(int d, T* W, int* perm) {
+  const LuCount scope;
   for (int i = 0; i < d; ++i) perm[i] = i;
   for (int k = 0; k < d; ++k) {
     int piv = k;
@@ -1238,6 +1256,7 @@ static void lu_factor(int d, T* W, int* perm) {
 // reciprocals of U's).
 template <class T>
 static void lu_solve(int d, const T* LU, const int* perm, const T* b, T* x) {
+  const LuCount scope;
   for (int i = 0; i < d; ++i) {
     T acc = b[perm[i]];
     for (int j = 0; j < i; ++j) acc = fma(-LU[i * d + j], x[j], acc);
@@ -1253,6 +1272,7 @@ static void lu_solve(int d, const T* LU, const int* perm, const T* b, T* x) {
 // Solve W^T z = b with the factors: U^T v = b, L^T w = v, z[perm[i]] = w[i].
 template <class T>
 static void lu_solve_t(int d, const T* LU, const int* perm, const T* b, T* z) {
+  const LuCount scope;
   T v[DMAX];
   for (int i = 0; i < d; ++i) {
     T acc = b[i];
@@ -1902,6 +1922,39 @@ int oracle_count_system(int sys, int64_t* out) {
     jac_vjp(sys, y, p.data(), w, f, gy, gp.data());
     out[3] = g_ops;
   }
+  return 0;
+}
+
+// Operations of the linear algebra of W = I/(gamma h) - J at the counting
+// point (h = 1e-3, gamma = 1/4): the factorisation, one solve and one
+// transposed solve, counted with the LU rule above.
+int oracle_count_lu(int sys, int64_t* out) {
+  const int d = sys_dim(sys), np = sys_np(sys);
+  if (d < 0 || !(sys == SYS_ROBERTSON || sys == SYS_HIRES || sys == SYS_LINEAR)) return -1;
+  std::vector<OpCount> p(np);
+  for (int c = 0; c < np; ++c) p[c] = OpCount(0.5 + 0.01 * c);
+  OpCount y[DMAX], b[DMAX], x[DMAX], LU[DMAX * DMAX];
+  for (int c = 0; c < d; ++c) {
+    y[c] = OpCount(0.3 + 0.1 * c);
+    b[c] = OpCount(1.0 + 0.1 * c);
+  }
+  int perm[DMAX];
+  jac(sys, y, p.data(), LU);
+  const OpCount dg = OpCount(1.0) / (OpCount(0.25) * OpCount(1e-3));
+  for (int i = 0; i < d * d; ++i) LU[i] = -LU[i];
+  for (int i = 0; i < d; ++i) LU[i * d + i] = LU[i * d + i] + dg;
+  g_ops = 0;
+  lu_factor(d, LU, perm);
+  out[0] = g_ops;
+  g_ops = 0;
+  lu_solve(d, LU, perm, b, x);
+  out[1] = g_ops;
+  g_ops = 0;
+  lu_solve_t(d, LU, perm, b, x);
+  out[2] = g_ops;
+  int swaps = 0;
+  for (int i = 0; i < d; ++i) swaps += perm[i] != i;
+  out[3] = swaps;
   return 0;
 }
 

@@ -85,3 +85,73 @@ def test_explicit_counts_from_the_tableau_pattern(method, system):
     # lo and hi (a product and an addition each: 4d) and their additions (2d)
     assert c["dense_fwd"] == 2 * f + 8 * d
     assert c["dense_adj"] == c["dense_fwd"] + 3 * d + 2 * d + 2 * v + 4 * d + 2 * d
+
+
+def _structural_lu_count(P):
+    """Hand count of the LU of a matrix with nonzero pattern P (diagonal
+    included), no interchanges: per column a reciprocal, per row below with a
+    nonzero in the column a multiplier and an fma (2) per nonzero right of
+    the column in the pivot row (a product alone (1) where the row held a
+    zero, which fills in); a solve is 2 per off-diagonal nonzero of L and U
+    plus d products by the diagonal's reciprocals."""
+    P = P.copy()
+    d = len(P)
+    fac = 0
+    for k in range(d):
+        fac += 1
+        for i in range(k + 1, d):
+            if not P[i, k]:
+                continue
+            fac += 1
+            for j in range(k + 1, d):
+                if P[k, j]:
+                    fac += 2 if P[i, j] else 1
+                    P[i, j] = True
+    solve = 2 * int(np.tril(P, -1).sum() + np.triu(P, 1).sum()) + d
+    return fac, solve
+
+
+@pytest.mark.parametrize("system", [O.ROBERTSON, O.HIRES, O.LINEAR])
+def test_lu_count_is_the_structural_count(system):
+    """The counter leaves out the operations on W's structural zeros (the
+    pattern taken from the oracle's Jacobian at a generic point, so from the
+    formulas of Appendix A): its LU counts equal the hand count of the sparse
+    factorisation, and no rows are interchanged at the counting point."""
+    d, npar = O.dims(system)
+    rng = np.random.default_rng(5)
+    J = O.jac(system, rng.uniform(0.2, 1.0, d), rng.uniform(0.2, 1.0, npar))
+    P = (J != 0) | np.eye(d, dtype=bool)
+    fac, solve = _structural_lu_count(P)
+    assert O.count_lu(system) == (fac, solve, solve, 0)
+
+
+def test_hires_dense_lu_would_count_more():
+    """The dense count for d = 8 (316 for the factorisation, 120 a solve)
+    against the sparse one: the structural zeros are a large part of it."""
+    dense_fac, dense_solve = _structural_lu_count(np.ones((8, 8), dtype=bool))
+    assert (dense_fac, dense_solve) == (316, 120)
+    fac, solve, _, _ = O.count_lu(O.HIRES)
+    assert fac < dense_fac // 4 and solve < dense_solve // 2
+
+
+def test_declared_jacobian_patterns_cover_the_jacobian():
+    """The device systems declare their Jacobian's pattern (JAC_ROWS), from
+    which the factorisation's skipped operations are found at compile time:
+    every entry that the oracle's Jacobian makes nonzero at random points
+    must be declared (a declared zero that is not one would drop a term)."""
+    import os
+    import re
+    src = open(os.path.join(os.path.dirname(__file__), "..", "paper_2609_02876_amd", "csrc",
+                            "systems.h")).read()
+    rng = np.random.default_rng(6)
+    for name, system in (("Robertson", O.ROBERTSON), ("Hires", O.HIRES)):
+        body = src[src.index(f"struct {name} {{"):]
+        rows = re.search(r"JAC_ROWS\[\d+\] = \{([^}]*)\}", body).group(1)
+        rows = [int(v.strip().rstrip("u"), 16) for v in rows.split(",")]
+        d, npar = O.dims(system)
+        seen = np.zeros((d, d), dtype=bool)
+        for _ in range(20):
+            seen |= O.jac(system, rng.uniform(0.1, 2.0, d), rng.uniform(0.1, 2.0, npar)) != 0
+        declared = np.array([[(rows[i] >> j) & 1 for j in range(d)] for i in range(d)], bool)
+        assert np.all(declared | ~seen), name
+        assert np.array_equal(declared, seen), name  # and no more than that
