@@ -1095,7 +1095,7 @@ __device__ __forceinline__ void save_step_reverse(const T* yb, const T* p, doubl
     T u[Tab::S][D];
     int piv[D];
     if constexpr (W_LDS) {
-      ros_step_lds<Sys, Tab, T, Tab::SU>(yb, p, T(hh), LdsMat<T>{sW}, piv, u, ys);
+      ros_step_lds<Sys, Tab, T, Tab::SU>(yb, p, T(hh), LdsMat<Sys, T>{sW}, piv, u, ys);
     } else {
       T W[D * D];
       ros_step<Sys, Tab, T, Tab::SU>(yb, p, T(hh), W, piv, u, ys);
@@ -1112,7 +1112,8 @@ __device__ __forceinline__ void save_step_reverse(const T* yb, const T* p, doubl
 #pragma unroll
       for (int q = 0; q < Tab::SU; ++q) opaque(u[q][c]);
     }
-    ros_step_vjp<Sys, Tab, T, LdsMat<T>>(ybo, p, T(hh), LdsMat<T>{sW}, piv, u, w, lin, g);
+    ros_step_vjp<Sys, Tab, T, LdsMat<Sys, T>>(ybo, p, T(hh), LdsMat<Sys, T>{sW}, piv, u, w, lin,
+                                              g);
   } else {
     T k0[D], Y[Tab::SU][D], ylast[D], klast[D];
     Sys::rhs(yb, p, k0);
@@ -1305,10 +1306,11 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   constexpr bool STAGE = CH <= 2;
   __shared__ uint4 s_rd[STAGE ? TAPE_GROUP * CH * 256 : 1];
   // Rosenbrock factors of d >= 6 held in LDS during the transposed solves
-  // (64 doubles a lane for d = 8 would otherwise push the reverse step past
-  // the register file into scratch); one wave per SIMD either way
+  // (their possible nonzeros, 52 doubles a lane for HIRES, would otherwise
+  // push the reverse step past the register file into scratch); one wave
+  // per SIMD either way
   constexpr bool W_LDS = Tab::ROS && D >= 6;
-  __shared__ T s_W[W_LDS ? D * D * 256 : 1];
+  __shared__ T s_W[W_LDS ? lu_nnz<Sys>() * 256 : 1];
   const RecView& R = a.rec;
   const bool ok = valid && R.status[tr] == LANE_OK;
   T* gpo = (T*)a.grad_p;
@@ -1437,7 +1439,7 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
     int piv[D];
     T Y[NY][D], ys[D];
     if constexpr (W_LDS) {
-      ros_step_lds<Sys, Tab, T, Tab::SU>(yb, p, T(hh), LdsMat<T>{s_W}, piv, u, ys);
+      ros_step_lds<Sys, Tab, T, Tab::SU>(yb, p, T(hh), LdsMat<Sys, T>{s_W}, piv, u, ys);
     } else if constexpr (Tab::ROS) {
       ros_step<Sys, Tab, T, Tab::SU>(yb, p, T(hh), W, piv, u, ys);
     } else {
@@ -1461,7 +1463,7 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
     // reverse through the stages: kbar_j = h (b_j w + sum_{l>j} a_lj Ybar_l)
     T lin[D];
     if constexpr (W_LDS) {
-      const LdsMat<T> Wl{s_W};
+      const LdsMat<Sys, T> Wl{s_W};
       // the reverse recomputes the stage states and Jacobian terms from
       // (y, u) rather than keeping the forward's copies live
 #pragma unroll
@@ -1470,7 +1472,7 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
 #pragma unroll
         for (int q = 0; q < (Tab::ROS ? Tab::SU : 0); ++q) opaque(u[q][c]);
       }
-      ros_step_vjp<Sys, Tab, T, LdsMat<T>>(yb, p, T(hh), Wl, piv, u, w, lin, gp);
+      ros_step_vjp<Sys, Tab, T, LdsMat<Sys, T>>(yb, p, T(hh), Wl, piv, u, w, lin, gp);
     } else if constexpr (Tab::ROS) {
       ros_step_vjp<Sys, Tab, T, T[NW]>(yb, p, T(hh), W, piv, u, w, lin, gp);
     } else {

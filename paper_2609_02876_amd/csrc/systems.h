@@ -90,6 +90,9 @@ struct Linear {
 //   f0 = b - a,  f1 = (a - b) - c,  f2 = c.
 struct Robertson {
   static constexpr int D = 3, NP = 3, ID = 3;
+  // nonzero pattern of the Jacobian, row i: bit j where dF_i/dy_j is not
+  // identically zero
+  static constexpr unsigned JAC_ROWS[3] = {0x7u, 0x7u, 0x2u};
   template <class T>
   __device__ static inline void rhs(const T* y, const T* p, T* f) {
     const T a = p[0] * y[0];
@@ -140,6 +143,9 @@ struct Robertson {
 // 0.69, 1.81); f7 = -f6 keeps y6 + y7 constant to the bit.
 struct Hires {
   static constexpr int D = 8, NP = 12, ID = 4;
+  // nonzero pattern of the Jacobian (as jac below writes it), row i: bit j
+  // where dF_i/dy_j is not identically zero
+  static constexpr unsigned JAC_ROWS[8] = {0x07u, 0x03u, 0x1Cu, 0x0Eu, 0x70u, 0xF8u, 0xE0u, 0xE0u};
   template <class T>
   __device__ static inline void rhs(const T* y, const T* p, T* f) {
     f[0] = fmaT(p[2], y[2], fmaT(p[1], y[1], fmaT(-p[0], y[0], p[3])));
