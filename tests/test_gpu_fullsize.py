@@ -107,7 +107,8 @@ def test_fp32_lorenz_headline_span_error():
     about e^(0.9 t) ~ 8e3 over the span, so the 1e-4 bar of the shorter
     FP32 cases does not hold for every trajectory here; the per-trajectory
     errors are reported (median, p99, max) and bounded as stated: median
-    below 1e-3, p99 below 1e-1."""
+    below 1e-4, p99 below 5e-4, every one below 1e-3 (measured: the largest
+    1.2e-4, in the parameter gradient)."""
     n = 1 << 20
     t1 = 10.0
     print(f"case fp32 lorenz headline span n={n}", flush=True)
@@ -132,7 +133,7 @@ def test_fp32_lorenz_headline_span_error():
     for k, v in e.items():
         print(f"  {k}: per-trajectory relative error median {np.median(v):.2e} "
               f"p99 {np.quantile(v, 0.99):.2e} max {v.max():.2e}", flush=True)
-        assert np.median(v) <= 1e-3 and np.quantile(v, 0.99) <= 1e-1
+        assert np.median(v) <= 1e-4 and np.quantile(v, 0.99) <= 5e-4 and v.max() <= 1e-3
 
 
 def test_ude_max_size_sampled():

@@ -181,3 +181,30 @@ def test_ros_full_size_sampled(meth, mo, system):
                    cfg["atol"], save_t=list(st))
     own_mesh_parity(hd, SYS_O[system], mo, y0, p, ref, TOL64, lanes=idx, gp=gp, gy=gy,
                     label="sampled ")
+
+
+@pytest.mark.parametrize("meth,mo", METHODS)
+@pytest.mark.parametrize("system,n", [("robertson", 500), ("hires", 300)])
+def test_ros_solve_matches_oracle(meth, mo, system, n):
+    """The forward-only solve (no record) against the oracle's adaptive
+    solve: per-trajectory normwise state error at 20 save times (the two
+    meshes may differ at the controller's noise floor, which these
+    contractive stiff flows do not amplify), and the same bits as the
+    record's save states."""
+    print(f"case {meth} solve {system} n={n}", flush=True)
+    y0, p = _gen(system)(n, 5)
+    t1 = T1[system]
+    st = list(W.save_times(0.0, t1, 20))
+    ref = O.record(SYS_O[system], mo, y0, p, 0.0, t1, 1e-6, 1e-10, save_t=st)
+    assert np.all(ref["status"] == O.ST_OK)
+    ys, status = B.ensemble_solve(system, meth, _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
+                                  save_times=st)
+    hd = B.ensemble_record(system, meth, _dev(y0.T), _dev(p.T), 0.0, t1, 1e-6, 1e-10,
+                           save_times=st, steps_hint=HINT[meth])
+    torch.cuda.synchronize()
+    assert np.all(status.cpu().numpy() == 0)
+    assert torch.equal(ys, hd.y_save) and torch.equal(status, hd.status)
+    e = _rel(ys.cpu().numpy(), np.transpose(ref["y_save"], (1, 2, 0)))
+    print(f"  per-trajectory state error median {np.median(e):.2e} p99 "
+          f"{np.quantile(e, 0.99):.2e} max {e.max():.2e}", flush=True)
+    assert e.max() <= 1e-9

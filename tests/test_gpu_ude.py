@@ -113,6 +113,31 @@ def test_ude_adaptive_record_states():
     assert abs(S_g.mean() - ref["S"].mean()) <= 0.05 * ref["S"].mean()
 
 
+def test_ude_solve_against_oracle():
+    """The forward-only solve of the UDE (no record) against the FP64
+    oracle's adaptive solve: per-trajectory normwise state error at the 20
+    save times within the FP32 bar, and the same bits as the record's save
+    states."""
+    n = 700
+    print(f"case ude solve n={n}", flush=True)
+    y0, th = _case(n, seed=4)
+    ref = O.record(O.LV_UDE, O.TSIT5, y0, th, 0.0, T1, 1e-6, 1e-6, save_t=ST, params_shared=True)
+    ys, status = B.ensemble_solve("ude", "tsit5", _dev(y0.T), _dev(th), 0.0, T1, 1e-6, 1e-6,
+                                  save_times=ST, params_shared=True)
+    hd = B.ensemble_record("ude", "tsit5", _dev(y0.T), _dev(th), 0.0, T1, 1e-6, 1e-6,
+                           save_times=ST, params_shared=True, steps_hint=256)
+    torch.cuda.synchronize()
+    assert np.all(status.cpu().numpy() == 0)
+    assert torch.equal(ys, hd.y_save)
+    ys_o = np.transpose(ref["y_save"], (1, 2, 0))
+    d = ys.double().cpu().numpy() - ys_o
+    e = np.linalg.norm(d.reshape(-1, n), axis=0) / np.maximum(
+        np.linalg.norm(ys_o.reshape(-1, n), axis=0), 1e-30)
+    print(f"  per-trajectory state error median {np.median(e):.2e} p99 "
+          f"{np.quantile(e, 0.99):.2e} max {e.max():.2e}", flush=True)
+    assert e.max() <= TOL32
+
+
 def test_ude_trajectory_independent_of_its_wavefront():
     """A trajectory's record and per-trajectory gradient do not depend on the
     trajectories sharing its wavefront (they share matrix-core operations)."""
