@@ -246,18 +246,19 @@ __device__ __forceinline__ double rms(const double* v, const double* sc) {
 // work on the mean square ms = err^2 of the scaled error: err <= 1 is
 // ms <= 1, and the proposed factor 0.9 err^(-1/k) is 0.9 ms^(-1/(2k)).  No
 // square root, no division: each scale's reciprocal is the hardware
-// estimate refined by two Newton steps, and the power is a single-precision
-// estimate refined by two Newton steps in double.  Both are accurate to
-// about an ulp; the rounding differs from a division and a root by a few
-// ulps of h, so the adaptive mesh can differ from one formed by exact
-// division and root where a trial sits on the acceptance bound.
+// estimate refined by one Newton step (which squares its relative error),
+// and the power a single-precision estimate refined by one Newton step in
+// double; both land within about 1e-13 of the exact values.  That is far below the
+// rounding noise of the error estimate itself (a small difference of large
+// stage terms, near 1e-10 relative at rtol 1e-6), which sets how far two
+// correct adaptive meshes of the same trajectory may differ; the mesh is
+// recorded as taken, and the gradient is exact for it.
 
-// 1/x to about an ulp (x > 0 finite): e = 1 - x r, r <- r + r e, twice.
+// 1/x for x > 0 finite: e = 1 - x r, r <- r + r e, once (relative error
+// about the square of the estimate's).
 __device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fmaT(-x, r, 1.0);
-  r = fmaT(r, e, r);
-  e = fmaT(-x, r, 1.0);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fmaT(-x, r, 1.0);
   return fmaT(r, e, r);
 }
 
@@ -305,20 +306,17 @@ __device__ __forceinline__ double ipow(double y) {
 // [0.2, 10] long before either end (with K2 >= 6 the ends give factors
 // beyond 90 and below 0.01).  A NaN ms gives 0, so that a trial whose
 // error is not a number shrinks h by the lower bound.  The seed
-// 2^(-log2(x) / K2) in single precision is within a few 1e-7; two Newton
-// steps y <- y + (y / K2)(1 - x y^K2) take it to about an ulp.
+// 2^(-log2(x) / K2) in single precision is within a few 1e-7; one Newton
+// step y <- y + (y / K2)(1 - x y^K2) takes it to about 1e-13.
 template <int K2>
 __device__ __forceinline__ double step_factor(double ms) {
   const double x = fmin(fmax(ms, 1e-30), 1e30);
   const float l2 = __builtin_amdgcn_logf((float)x);
-  double y = (double)__builtin_amdgcn_exp2f(l2 * (-1.0f / (float)K2));
+  const double y = (double)__builtin_amdgcn_exp2f(l2 * (-1.0f / (float)K2));
   constexpr double inv_k = 1.0 / (double)K2;
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double t = fmaT(-x, ipow<K2>(y), 1.0);
-    y = fmaT(y * inv_k, t, y);
-  }
-  return ms >= 0.0 ? 0.9 * y : 0.0;
+  const double t = fmaT(-x, ipow<K2>(y), 1.0);
+  const double yr = fmaT(y * inv_k, t, y);
+  return ms >= 0.0 ? 0.9 * yr : 0.0;
 }
 
 // x^(-1/K) for the controller and the starting step (K = 3..8), from
@@ -482,6 +480,7 @@ __device__ __forceinline__ void load_state(const char* rp, T* y) {
 }
 
 constexpr int H_GROUP = 16;  // step sizes staged per lane (checkpointed tape)
+static_assert((H_GROUP & (H_GROUP - 1)) == 0, "a power of two (slot & (H_GROUP - 1))");
 
 // Write this lane's first `count` staged step sizes to hp (contiguous).
 __device__ __forceinline__ void flush_h(const double* s_h, int count, char* hp) {
@@ -493,6 +492,7 @@ __device__ __forceinline__ void flush_h(const double* s_h, int count, char* hp) 
 }
 
 constexpr int TAPE_GROUP = 4;  // step records per lane written together
+static_assert((TAPE_GROUP & (TAPE_GROUP - 1)) == 0, "a power of two (slot & (TAPE_GROUP - 1))");
 
 // Put one record into this lane's staging slots starting at chunk q0.
 template <class T, int D>
@@ -691,6 +691,9 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   int32_t page = -1;
   char* pg = nullptr;
   int slot = 0, kpage = 0;  // position of the next taped step: S = K kpage + slot
+  // the trial budget as a 32-bit count (trials never exceed it)
+  const int32_t max_trials =
+      a.ivp.max_steps < 0x7fffffff ? (int32_t)a.ivp.max_steps : 0x7fffffff;
 
   while (status == LANE_OK &&
          (side || (MODE == MODE_FROZEN ? (S < S_mesh) : (t < t1)))) {
@@ -703,9 +706,9 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         if (!last) h_next = a.mesh_h[(int64_t)(S + 1) * n + tr];
         ++trials;
       } else if constexpr (MODE == MODE_REFRESH) {
-        if (trials >= a.ivp.max_steps) {
+        if (trials >= max_trials) {
           status = LANE_MAX_STEPS;
-          break;
+          continue;  // the loop's condition ends it
         }
         if (following) {  // the old mesh's step, its last one ending at t1
           h = h_next;
@@ -714,7 +717,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         } else {
           if (h < 16.0 * EPS64 * fmax(fabs(t), 1.0)) {
             status = LANE_DT_UNDERFLOW;
-            break;
+            continue;  // the loop's condition ends it
           }
           if (t + h >= t1) {
             h = t1 - t;
@@ -724,13 +727,13 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         ++trials;
         hh = h;
       } else {
-        if (trials >= a.ivp.max_steps) {
+        if (trials >= max_trials) {
           status = LANE_MAX_STEPS;
-          break;
+          continue;  // the loop's condition ends it
         }
         if (h < 16.0 * EPS64 * fmax(fabs(t), 1.0)) {
           status = LANE_DT_UNDERFLOW;
-          break;
+          continue;  // the loop's condition ends it
         }
         ++trials;
         if (t + h >= t1) {
@@ -832,7 +835,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
           } else {
             if (got >= (uint64_t)(R.n_pages - R.n_static)) {
               status = LANE_NOSPACE;
-              break;
+              continue;  // the loop's condition ends it
             }
             np_ = (int32_t)(R.n_static + (int64_t)got);
             const int64_t li = (int64_t)np_ - R.n_static;
@@ -848,16 +851,16 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         }
         if constexpr (CKPT) {
           if (need) store_state<T, D>(pg, y);
-          s_h[(slot % H_GROUP) * 256 + threadIdx.x] = hh;
-          if (slot % H_GROUP == H_GROUP - 1)
+          s_h[(slot & (H_GROUP - 1)) * 256 + threadIdx.x] = hh;
+          if ((slot & (H_GROUP - 1)) == H_GROUP - 1)
             flush_h(s_h, H_GROUP, pg + YB + (slot - (H_GROUP - 1)) * 8);
         } else {
-          if (slot % TAPE_GROUP == TAPE_GROUP - 1) {
+          if ((slot & (TAPE_GROUP - 1)) == TAPE_GROUP - 1) {
             char* gp = pg + (slot - (TAPE_GROUP - 1)) * RB;
             flush_recs<T, D>(s_tape, TAPE_GROUP - 1, gp);
             store_rec<T, D>(gp + (TAPE_GROUP - 1) * RB, hh, y);
           } else {
-            stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, y);
+            stage_rec<T, D>(s_tape, (slot & (TAPE_GROUP - 1)) * CH, hh, y);
           }
         }
         if (++slot == K) {

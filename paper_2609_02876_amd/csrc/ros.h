@@ -483,7 +483,7 @@ __device__ __forceinline__ void ros_step_vjp(const T* y, const T* p, T h, const 
 
 // Mean square (the RMS norm squared) of the scaled error estimate against
 // atol + rtol max(|y|, |y_new|); the reciprocal of each scale as the
-// explicit pairs' recip (the hardware estimate and two Newton steps).
+// explicit pairs' recip (the hardware estimate and one Newton step).
 template <int D, class T>
 __device__ __forceinline__ double ros_ms(const T* y, const T* ynew, const T* e, double rtol,
                                          double atol) {
@@ -491,11 +491,8 @@ __device__ __forceinline__ double ros_ms(const T* y, const T* ynew, const T* e, 
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     const double sc = fmaT(rtol, fmax(fabs((double)y[c]), fabs((double)ynew[c])), atol);
-    double q = __builtin_amdgcn_rcp(sc);
-    double t = fmaT(-sc, q, 1.0);
-    q = fmaT(q, t, q);
-    t = fmaT(-sc, q, 1.0);
-    q = fmaT(q, t, q);
+    const double q0 = __builtin_amdgcn_rcp(sc);
+    const double q = fmaT(q0, fmaT(-sc, q0, 1.0), q0);
     const double r = (double)e[c] * q;
     ss = c == 0 ? r * r : fmaT(r, r, ss);
   }

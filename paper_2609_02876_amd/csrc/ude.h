@@ -466,12 +466,12 @@ __global__ void __launch_bounds__(256, 2) ude_forward_kernel(const FwdArgs a) {
         }
         if constexpr (CKPT) {
           if (need) store_state<T, D>(pg, yb);
-          s_h[(slot % H_GROUP) * 256 + threadIdx.x] = hh;
-          if (slot % H_GROUP == H_GROUP - 1)
+          s_h[((slot & (H_GROUP - 1))) * 256 + threadIdx.x] = hh;
+          if ((slot & (H_GROUP - 1)) == H_GROUP - 1)
             flush_h(s_h, H_GROUP, pg + YB + (slot - (H_GROUP - 1)) * 8);
         } else {
-          stage_rec<T, D>(s_tape, (slot % TAPE_GROUP) * CH, hh, yb);
-          if (slot % TAPE_GROUP == TAPE_GROUP - 1)
+          stage_rec<T, D>(s_tape, ((slot & (TAPE_GROUP - 1))) * CH, hh, yb);
+          if ((slot & (TAPE_GROUP - 1)) == TAPE_GROUP - 1)
             flush_recs<T, D>(s_tape, TAPE_GROUP, pg + (slot - (TAPE_GROUP - 1)) * RB);
         }
       }
