@@ -34,10 +34,12 @@ def parse():
     ap.add_argument("--registered", action="store_true",
                     help="run the workload's system as a copy registered at run time from source "
                          "(ensemble_system_register; Lorenz and Robertson)")
-    ap.add_argument("--mode", choices=("reverse", "forward", "refresh"), default="reverse",
+    ap.add_argument("--mode", choices=("reverse", "forward", "refresh", "solve"),
+                    default="reverse",
                     help="gradient by the reverse sweep (default) or by forward-mode passes, "
                          "one per parameter, on the recorded mesh; refresh: the mesh-drift "
-                         "policy (an old record refreshed at moved parameters, then the sweep)")
+                         "policy (an old record refreshed at moved parameters, then the sweep); "
+                         "solve: the forward-only solve (states at the save times, no record)")
     ap.add_argument("--refresh-step", type=float, default=1e-3,
                     help="relative parameter change for --mode refresh (seeded normal)")
     ap.add_argument("--n", type=int, default=None, help="override the trajectory count")
@@ -251,7 +253,7 @@ def main():
     if args.write_traffic:
         from paper_2609_02876_amd import workloads as W
         n = args.n or W.WORKLOADS[args.workload]["n"]
-        key = args.workload + ("_forward" if args.mode == "forward" else "")
+        key = args.workload + {"forward": "_forward", "solve": "_solve"}.get(args.mode, "")
         return write_traffic(*args.write_traffic, key, n, args.copy_calibration or 1024)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ensemble "
@@ -270,6 +272,8 @@ def main():
         return forward_bench(args)
     if args.mode == "refresh":
         return refresh_bench(args)
+    if args.mode == "solve":
+        return solve_bench(args)
     cfg, y0, p, st = W.make(args.workload, n=args.n)
     torch.cuda.set_device(torch.device("cuda:0"))
     out = reverse_bench(cfg, y0, p, st, args.steps, args.warmup, workload=args.workload,
@@ -659,6 +663,127 @@ def refresh_bench(args):
         "context_same_step": {"fresh_record": ctx["record"],
                               "stale_mesh_replay_unchecked": ctx["stale_replay"]},
     }
+    print(json.dumps(out), flush=True)
+
+
+def solve_bench(args):
+    """The forward-only solve (`ensemble_solve`: the adaptive loop and the
+    states at the save times, no record, no gradient) on a workload: the
+    forward-only throughput of the paper's fused kernels (Section 4.1).  The
+    work counts come from one record of the same inputs outside the timed
+    steps (the solve takes the same steps, to the bit)."""
+    import numpy as np
+    import torch
+
+    from paper_2609_02876_amd import binding as B
+    from paper_2609_02876_amd import flops
+    from paper_2609_02876_amd import workloads as W
+
+    cfg, y0, p, st = W.make(args.workload, n=args.n)
+    n = cfg["n"]
+    shared = bool(cfg.get("shared"))
+    save = list(st) if cfg["n_save"] else None
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    f32 = cfg.get("dtype", "f64") == "f32"
+    tdt = torch.float32 if f32 else torch.float64
+    y0_d = torch.tensor(np.ascontiguousarray(y0.T), dtype=tdt, device=dev)
+    p_d = (torch.tensor(np.ascontiguousarray(p), dtype=tdt, device=dev) if shared else
+           torch.tensor(np.ascontiguousarray(p.T), dtype=tdt, device=dev))
+    args_common = (cfg["system"], cfg["method"], y0_d, p_d, cfg["t0"], cfg["t1"], cfg["rtol"],
+                   cfg["atol"])
+    # the work of the solve, from a record of the same inputs
+    m = min(n, 8192)
+    pilot = B.ensemble_record(cfg["system"], cfg["method"], y0_d[:, :m].contiguous(),
+                              p_d if shared else p_d[:, :m].contiguous(), cfg["t0"], cfg["t1"],
+                              cfg["rtol"], cfg["atol"], save_times=save, params_shared=shared,
+                              steps_hint=4096)
+    s_pilot = pilot.steps().double()
+    cap_cpu = int(s_pilot.max().item() * 1.5) + 64
+    hint = B.steps_hint_for(float(s_pilot.mean().item()), margin=1.12)
+    del pilot
+    rec = B.ensemble_record(*args_common, save_times=save, params_shared=shared, steps_hint=hint)
+    stats = B.ensemble_record_stats(rec)
+    ref_states = rec.y_save.clone()
+    del rec
+    stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        calibration_copy(args.copy_calibration, dev)
+
+    def step(events=None):
+        if events:
+            events[0].record(stream)
+        out = B.ensemble_solve(*args_common, save_times=save, params_shared=shared)
+        if events:
+            events[1].record(stream)
+        return out
+
+    for _ in range(args.warmup):
+        ys, status = step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ys, status = step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bad = int((status != 0).sum().item())
+    if bad:
+        raise RuntimeError(f"{bad} trajectories did not finish (status != OK)")
+    if not torch.equal(ys, ref_states):
+        raise RuntimeError("the solve's states differ from the record's")
+    solve_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    f_solve = flops.record_flops(cfg["method"], cfg["system"], stats["trials"],
+                                 stats["steps_accepted"], stats["side_steps"])
+    achieved = f_solve / (solve_ms * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
+    traffic = None
+    tr = load_traffic(args.traffic, args.workload + "_solve")
+    if tr is not None and tr.get("n") == n:
+        traffic = tr.get("record")
+    out = {
+        "metric": "trajectories/s (forward-only solve, states at the save times)",
+        "value": n * args.steps / wall, "unit": "trajectories/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if f32 else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "mode": "solve", "system": cfg["system"],
+                   "method": cfg["method"], "n": n, "t_span": [cfg["t0"], cfg["t1"]],
+                   "rtol": cfg["rtol"], "atol": cfg["atol"], "n_save": cfg["n_save"],
+                   "params_shared": shared},
+        "roofline": {"bound": "alu",
+                     "kernel": f"erk_forward_kernel ({cfg['system']}, {cfg['method']}, solve)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic},
+        "kernels_ms": {"solve": solve_ms},
+        "algorithmic_flop": {"solve": f_solve},
+        "record_stats": {"accepted_per_traj": stats["steps_accepted"] / n,
+                         "trials_per_traj": stats["trials"] / n},
+    }
+    if not args.no_cpu_baseline:
+        O = load_oracle()
+        so = {"lorenz": O.LORENZ, "vdp": O.VDP, "robertson": O.ROBERTSON, "hires": O.HIRES,
+              "linear": O.LINEAR, "ude": O.LV_UDE}[cfg["system"]]
+        mo = {"tsit5": O.TSIT5, "vern7": O.VERN7, "rodas4": O.RODAS, "ros23": O.ROS23}[cfg["method"]]
+
+        def run(mm):
+            t = time.perf_counter()
+            O.record(so, mo, y0[:mm], p if shared else p[:mm], cfg["t0"], cfg["t1"], cfg["rtol"],
+                     cfg["atol"], save_t=save, cap=cap_cpu, params_shared=shared)
+            return time.perf_counter() - t
+
+        m2 = 2048
+        dt2 = run(m2)
+        for _ in range(3):
+            if dt2 >= 0.7 * args.cpu_seconds or m2 >= n:
+                break
+            m2 = int(min(n, m2 * args.cpu_seconds / max(dt2, 1e-3)))
+            m2 = max(64, (m2 // 64) * 64)
+            dt2 = run(m2)
+        out["cpu_baseline"] = {
+            "value": m2 / dt2, "unit": "trajectories/s", **cpu_info(), "kind": "oracle",
+            "sample": f"first {m2} trajectories, the oracle's adaptive solve, {dt2:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

@@ -127,6 +127,14 @@ WORKLOADS = {
     "ude_2p16_full": dict(system="ude", method="tsit5", n=1 << 16, t0=0.0, t1=10.0,
                           rtol=1e-6, atol=1e-6, n_save=20, dtype="f32", shared=True,
                           loss="mse", ckpt_every=0),
+    # the paper's forward-only timing (Section 4.1, Appendix A): Lorenz with
+    # sigma = 10, beta = 8/3, rho ~ U[0, 21], y0 = (1, 0, 0), t in [0, 1],
+    # Tsit5, rtol 1e-6, atol 1e-9, 2^20 trajectories, to the final state
+    "lorenz_paper_fwd_2p20": dict(system="lorenz", method="tsit5", n=1 << 20, t0=0.0, t1=1.0,
+                                  rtol=1e-6, atol=1e-9, n_save=0, gen="lorenz_paper_timing"),
+    "lorenz_paper_fwd_2p20_f32": dict(system="lorenz", method="tsit5", n=1 << 20, t0=0.0,
+                                      t1=1.0, rtol=1e-6, atol=1e-9, n_save=0, dtype="f32",
+                                      gen="lorenz_paper_timing"),
 }
 
 GENERATORS = {"lorenz": lorenz, "vdp": vdp, "robertson": robertson, "hires": hires,
@@ -138,7 +146,8 @@ def make(name, n=None, seed=0):
     cfg = dict(WORKLOADS[name])
     if n is not None:
         cfg["n"] = n
-    gen = GENERATORS[cfg["system"]]
+    gen = {"lorenz_paper_timing": lorenz_paper_timing}[cfg["gen"]] if "gen" in cfg else \
+        GENERATORS[cfg["system"]]
     y0, p = gen(cfg["n"], seed)
     st = save_times(cfg["t0"], cfg["t1"], cfg["n_save"]) if cfg["n_save"] else np.array([cfg["t1"]])
     return cfg, y0, p, st
