@@ -93,6 +93,42 @@ __device__ __forceinline__ uint64_t wave_bump(unsigned long long* counter,
   return base + (uint64_t)rank_below(mask);
 }
 
+// Sum over the 64 lanes of a wavefront, by butterfly exchanges: within quads
+// (DPP quad_perm, partners lane ^ 1 and lane ^ 2), within rows (DPP
+// row_half_mirror, then row_mirror: each exchanges a lane's half-row, then
+// its half of the row, with the mirrored one) and across the four rows
+// (lane ^ 16 and lane ^ 32).  At every stage a lane and its partner add the
+// same two values, so every lane ends with the same, order-fixed sum.  Every
+// lane of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = dpp_i32<CTRL>(__double2loint(x));
+  const int hi = dpp_i32<CTRL>(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(x)));
+}
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+  constexpr int QUAD_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+  constexpr int QUAD_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+  constexpr int ROW_HALF_MIRROR = 0x141;
+  constexpr int ROW_MIRROR = 0x140;
+  x = x + dpp_move<QUAD_XOR1>(x);
+  x = x + dpp_move<QUAD_XOR2>(x);
+  x = x + dpp_move<ROW_HALF_MIRROR>(x);
+  x = x + dpp_move<ROW_MIRROR>(x);
+  x = x + __shfl_xor(x, 16);
+  x = x + __shfl_xor(x, 32);
+  return x;
+}
+
 // ----------------------------------------------------------- record view --
 // Device view of a record (see ens_record in ensode.h for the meaning).
 struct RecView {

@@ -1511,19 +1511,21 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
       a.loss_out[tr] = !ok ? NAN : (a.loss_kind == LOSS_COTANGENT ? 0.0 : loss);
   }
   if constexpr (SHARED) {
-    // shared parameters: fixed-order tree over the block's trajectories in
-    // index order (failed ones contribute nothing), one partial per block
-    __shared__ T red[256];
+    // shared parameters: each wavefront sums its lanes by cross-lane
+    // exchanges (wave_sum; a failed trajectory contributes nothing), then
+    // the block's four wavefront sums are added in wavefront order: one
+    // partial per block, in a fixed order
+    __shared__ T red[4][NP];
+    const int wave = (int)threadIdx.x >> 6;
 #pragma unroll
     for (int c = 0; c < NP; ++c) {
-      red[slot_in_block] = ok ? gp[c] : T(0);
-      __syncthreads();
-      for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) ((T*)a.workspace)[block * NP + c] = red[0];
-      __syncthreads();
+      const T sw = wave_sum<T>(ok ? gp[c] : T(0));
+      if (lane_id() == 0) red[wave][c] = sw;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NP) {
+      const int c = (int)threadIdx.x;
+      ((T*)a.workspace)[block * NP + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
     }
   }
 }
