@@ -342,6 +342,13 @@ int ensemble_jvp(const ens_problem* prob, const ens_ivp* ivp, const ens_record* 
  * synchronisation, atomics or thread and block indices -- data-dependent
  * control flow is refused (ENS_EINVAL, as is a source that does not
  * compile; ensemble_last_error gives the reason and the compiler's log).
+ * A system with a Jacobian may also declare
+ *   static constexpr unsigned JAC_ROWS[dim] = {...};
+ * bit j of row i set where dF_i/dy_j can be nonzero: the Rosenbrock
+ * factorisation and solves then leave out the structural zeros (the fill over
+ * every pivot order is found at compile time; the results are the dense
+ * factorisation's).  A bit declared zero must be zero for every input, or the
+ * results are wrong; without the declaration the pattern is dense.
  * dim in [1, ENS_USER_MAX_DIM], nparams in [1, ENS_USER_MAX_PARAMS].  On
  * success *system receives the id to use in ens_problem.system.  The Tsit5
  * kernels in F64 (and Rodas4 with a Jacobian) are compiled here; the others

@@ -197,3 +197,28 @@ def test_registered_systems_are_not_served():
     with pytest.raises(A.EnsembleError, match="not served"):
         srv.submit(_name("rtc_lorenz"), "tsit5", _dev(y0.T), _dev(p.T), 0.0, 1.0, 1e-6, 1e-8)
     srv.close()
+
+
+@pytest.mark.parametrize("method", ["rodas4", "ros23"])
+def test_registered_jacobian_pattern(method):
+    """A registered system may declare its Jacobian's nonzero pattern
+    (JAC_ROWS); the Rosenbrock factorisation then skips the structural
+    zeros.  A registered Robertson with its pattern gives the same bits as
+    the built-in one (which declares the same) and as a registered copy
+    without it (the dense factorisation)."""
+    print(f"case registered robertson with JAC_ROWS, {method}", flush=True)
+    if "rtc_robertson_pattern" not in A.SYSTEMS:
+        src = U.ROBERTSON.replace("struct System {",
+                                  "struct System {\n  static constexpr unsigned JAC_ROWS[3] = "
+                                  "{0x7u, 0x7u, 0x2u};", 1)
+        B.register_system("rtc_robertson_pattern", src, 3, 3, jacobian=True)
+    n = 300
+    y0, p = W.robertson(n, seed=12)
+    st = list(W.save_times(0.0, 1e5, 10))
+    pat = _run("rtc_robertson_pattern", method, y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
+    built = _run("robertson", method, y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
+    dense = _run(_name("rtc_robertson"), method, y0, p, 1e5, 1e-6, 1e-10, st, torch.float64)
+    for a, b, c in zip(pat, built, dense):
+        if a is None:
+            continue
+        assert torch.equal(a, b) and torch.equal(a, c)
