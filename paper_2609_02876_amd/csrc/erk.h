@@ -515,6 +515,101 @@ __device__ __forceinline__ void flush_recs(const uint4* stage, int count, char* 
   for (int q = 0; q < count * CH; ++q) dst[q] = stage[q * 256 + threadIdx.x];
 }
 
+// Wave-cooperative tape writes (full-tape records of the explicit pairs).
+// Every record of a group waits in LDS; chunk c of lane l sits at
+// c * 256 + (l ^ (c & 7)), so that the eight chunks of one lane, read by
+// eight neighbouring lanes, fall in distinct 16-byte bank groups.  At the end
+// of each loop iteration the groups that the wavefront's lanes completed are
+// written out together: each group (TAPE_GROUP * CH chunks, one whole cache
+// line for 32-byte records) by as many consecutive lanes, so that one store
+// instruction writes whole lines, where a lane writing its own group issues
+// TAPE_GROUP * CH stores that each touch one line per active lane.
+template <class T, int D>
+__device__ __forceinline__ void stage_rec_sw(uint4* stage, int q0, double h, const T* y) {
+  constexpr int CH = TapeRec<T, D>::BYTES / 16;
+  RecBuf<T, D> b;
+  b.h = h;
+#pragma unroll
+  for (int c = 0; c < D; ++c) b.y[c] = y[c];
+  const uint4* src = reinterpret_cast<const uint4*>(&b);
+  const int l = (int)threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < CH; ++q) {
+    const int c = q0 + q;
+    stage[c * 256 + (l ^ (c & 7))] = src[q];
+  }
+}
+
+template <class T, int D>
+__device__ __forceinline__ void flush_recs_sw(const uint4* stage, int count, char* rp) {
+  constexpr int CH = TapeRec<T, D>::BYTES / 16;
+  uint4* dst = reinterpret_cast<uint4*>(__builtin_assume_aligned(rp, 16));
+  const int l = (int)threadIdx.x;
+  for (int c = 0; c < count * CH; ++c) dst[c] = stage[c * 256 + (l ^ (c & 7))];
+}
+
+// The lanes' parts in flush_groups_wave, fixed for a wavefront whose lanes
+// all run the loop: with `per` groups written per store instruction, lane
+// rank r among the live lanes writes chunk c = r mod G of the (r / G)-th
+// group of a round (G chunks a group); lanes past per * G only wait.
+struct WaveFlush {
+  int per;      // groups per round (0: each lane writes its own)
+  bool helper;  // r < per * G
+  int gj;       // r / G: this lane's group in a round
+  int qi;       // its queue entry in the first round: wavefront base + gj
+  int c;        // r mod G: its chunk
+};
+
+template <class T, int D>
+__device__ __forceinline__ WaveFlush wave_flush_parts() {
+  constexpr int G = TAPE_GROUP * (TapeRec<T, D>::BYTES / 16);
+  const uint64_t live = __ballot(1);
+  const int r = rank_below(live);
+  WaveFlush f;
+  f.per = __popcll(live) / G;
+  f.helper = r < f.per * G;
+  f.gj = r / G;
+  f.qi = ((int)threadIdx.x & ~63) + f.gj;
+  f.c = r % G;
+  return f;
+}
+
+// Called by every lane of the wavefront that has not returned (the lanes of
+// `f`); `gp` is the address of the lane's completed group or null, and is
+// cleared.  `queue` holds 64 16-byte entries per wavefront: (address, thread)
+// of each completed group in lane order.
+template <class T, int D>
+__device__ __forceinline__ void flush_groups_wave(const uint4* stage, uint4* queue,
+                                                  const WaveFlush& f, char*& gp) {
+  const uint64_t need = __ballot(gp != nullptr);
+  if (need == 0) return;
+  if (f.per == 0) {
+    if (gp != nullptr) flush_recs_sw<T, D>(stage, TAPE_GROUP, gp);
+    gp = nullptr;
+    return;
+  }
+  const int cnt = __popcll(need);
+  if (gp != nullptr) {
+    const uint64_t ad = (uint64_t)gp;
+    queue[((int)threadIdx.x & ~63) + rank_below(need)] =
+        make_uint4((uint32_t)ad, (uint32_t)(ad >> 32), threadIdx.x, 0u);
+  }
+  // the entries, and the staged records, were written by other lanes of
+  // this wavefront; a wavefront's LDS accesses complete in order
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int c = f.c;
+  for (int b = 0; b < cnt; b += f.per) {
+    if (f.helper && b + f.gj < cnt) {
+      const uint4 e = queue[f.qi + b];
+      uint4* dst = reinterpret_cast<uint4*>(((uint64_t)e.y << 32) | (uint64_t)e.x);
+      dst[c] = stage[c * 256 + ((int)e.z ^ (c & 7))];
+    }
+  }
+  gp = nullptr;
+}
+
 template <class T, int D>
 __device__ __forceinline__ void load_rec(const char* rp, double& h, T* y) {
   constexpr int RB = TapeRec<T, D>::BYTES;
@@ -593,12 +688,21 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   // save times in LDS (lane-varying index, short latency); slot n_save holds
   // +inf so that "no save left" needs no branch
   __shared__ double s_times[65];
-  // Tape staging: each lane collects the first GROUP - 1 step records of a
-  // group here and writes them, together with the last one straight from
-  // registers, as whole cache lines.  Chunk-major layout (chunk, lane) keeps
-  // the 16-byte LDS accesses free of bank conflicts.
+  // Tape staging.  COOP (full-tape records of the explicit pairs): every
+  // record of a group waits here, and the wavefront writes the completed
+  // groups together (flush_groups_wave).  Otherwise each lane collects the
+  // first GROUP - 1 step records of a group here and writes them, together
+  // with the last one straight from registers, as one whole cache line; the
+  // Rosenbrock records and the given-mesh modes keep that (their loops hold
+  // more state, and the cooperative writes measured slower there).
+  // Chunk-major layouts (chunk, lane) keep the 16-byte LDS accesses free of
+  // bank conflicts.
   constexpr int CH = TapeRec<T, D>::BYTES / 16;
-  __shared__ uint4 s_tape[(MODE == MODE_SOLVE || CKPT) ? 1 : (TAPE_GROUP - 1) * CH * 256];
+  constexpr bool COOP = MODE == MODE_RECORD && !CKPT && !Tab::ROS;
+  __shared__ uint4 s_tape[(MODE == MODE_SOLVE || CKPT) ? 1
+                                                    : (TAPE_GROUP - (COOP ? 0 : 1)) * CH * 256];
+  __shared__ uint4 s_wq[COOP ? 256 : 1];
+  char* flush_gp = nullptr;  // COOP: this lane's group completed in this iteration
   // checkpointed tape: step sizes staged H_GROUP at a time (one 128-byte line)
   __shared__ double s_h[CKPT ? H_GROUP * 256 : 1];
   if (threadIdx.x < 65)
@@ -695,8 +799,11 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
   const int32_t max_trials =
       a.ivp.max_steps < 0x7fffffff ? (int32_t)a.ivp.max_steps : 0x7fffffff;
 
-  while (status == LANE_OK &&
-         (side || (MODE == MODE_FROZEN ? (S < S_mesh) : (t < t1)))) {
+  // one iteration of a lane's loop (a `return` ends the iteration)
+  auto live = [&]() {
+    return status == LANE_OK && (side || (MODE == MODE_FROZEN ? (S < S_mesh) : (t < t1)));
+  };
+  auto iteration = [&]() {
     double hh;
     bool last = false;
     if (!side) {
@@ -708,7 +815,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       } else if constexpr (MODE == MODE_REFRESH) {
         if (trials >= max_trials) {
           status = LANE_MAX_STEPS;
-          continue;  // the loop's condition ends it
+          return;  // the lane's loop ends here
         }
         if (following) {  // the old mesh's step, its last one ending at t1
           h = h_next;
@@ -717,7 +824,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         } else {
           if (h < 16.0 * EPS64 * fmax(fabs(t), 1.0)) {
             status = LANE_DT_UNDERFLOW;
-            continue;  // the loop's condition ends it
+            return;  // the lane's loop ends here
           }
           if (t + h >= t1) {
             h = t1 - t;
@@ -729,11 +836,11 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       } else {
         if (trials >= max_trials) {
           status = LANE_MAX_STEPS;
-          continue;  // the loop's condition ends it
+          return;  // the lane's loop ends here
         }
         if (h < 16.0 * EPS64 * fmax(fabs(t), 1.0)) {
           status = LANE_DT_UNDERFLOW;
-          continue;  // the loop's condition ends it
+          return;  // the lane's loop ends here
         }
         ++trials;
         if (t + h >= t1) {
@@ -808,7 +915,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         }
         t = tn;
       }
-      continue;
+      return;
     }
 
     // proposed factor 0.9 err^(-1/(q+1)), formed once for both outcomes
@@ -820,7 +927,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
         kept = S;
         h = hh * fmax(0.2, fac0);
         prev_rej = true;
-        continue;
+        return;
       }
     }
     if (MODE == MODE_FROZEN || (MODE == MODE_REFRESH && following) || err <= 1.0) {
@@ -835,7 +942,7 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
           } else {
             if (got >= (uint64_t)(R.n_pages - R.n_static)) {
               status = LANE_NOSPACE;
-              continue;  // the loop's condition ends it
+              return;  // the lane's loop ends here
             }
             np_ = (int32_t)(R.n_static + (int64_t)got);
             const int64_t li = (int64_t)np_ - R.n_static;
@@ -855,7 +962,11 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
           if ((slot & (H_GROUP - 1)) == H_GROUP - 1)
             flush_h(s_h, H_GROUP, pg + YB + (slot - (H_GROUP - 1)) * 8);
         } else {
-          if ((slot & (TAPE_GROUP - 1)) == TAPE_GROUP - 1) {
+          if constexpr (COOP) {
+            stage_rec_sw<T, D>(s_tape, (slot & (TAPE_GROUP - 1)) * CH, hh, y);
+            if ((slot & (TAPE_GROUP - 1)) == TAPE_GROUP - 1)
+              flush_gp = pg + (slot - (TAPE_GROUP - 1)) * RB;
+          } else if ((slot & (TAPE_GROUP - 1)) == TAPE_GROUP - 1) {
             char* gp = pg + (slot - (TAPE_GROUP - 1)) * RB;
             flush_recs<T, D>(s_tape, TAPE_GROUP - 1, gp);
             store_rec<T, D>(gp + (TAPE_GROUP - 1) * RB, hh, y);
@@ -973,6 +1084,19 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       h = hh * fmax(0.2, fac0);
       prev_rej = true;
     }
+  };
+  if constexpr (COOP) {
+    // the loop runs while any lane of the wavefront is live: lanes that are
+    // done stay to help write the groups
+    const WaveFlush wf = wave_flush_parts<T, D>();
+    for (;;) {
+      const bool act = live();
+      if (!__any(act)) break;
+      if (act) iteration();
+      flush_groups_wave<T, D>(s_tape, s_wq, wf, flush_gp);
+    }
+  } else {
+    while (live()) iteration();
   }
 
   // records of an unfinished group (S = K kpage + slot; groups never
@@ -983,7 +1107,11 @@ __device__ __forceinline__ void erk_forward_body(const FwdArgs& a, int64_t block
       if (rem > 0 && pg != nullptr) flush_h(s_h, rem, pg + YB + (slot - rem) * 8);
     } else {
       const int rem = S % TAPE_GROUP;
-      if (rem > 0 && pg != nullptr) flush_recs<T, D>(s_tape, rem, pg + (slot - rem) * RB);
+      if constexpr (COOP) {
+        if (rem > 0 && pg != nullptr) flush_recs_sw<T, D>(s_tape, rem, pg + (slot - rem) * RB);
+      } else {
+        if (rem > 0 && pg != nullptr) flush_recs<T, D>(s_tape, rem, pg + (slot - rem) * RB);
+      }
     }
   }
 
@@ -1546,11 +1674,10 @@ __global__ void __launch_bounds__(256, (FwdBlocks<Sys, Tab, T>::value))
 }
 
 // Full-tape record whose save states are formed afterwards by
-// erk_saves_kernel (explicit pairs).  Without the side steps' state the FP64
-// Lorenz / Tsit5 record needs 118 VGPRs at four blocks per CU.  Five fit
-// (96 VGPRs, one spill on the overflow-page path) but ran no faster: 2^20
-// trajectories are 16 waves per SIMD, four full rounds at four blocks and a
-// lone last round at five.
+// erk_saves_kernel (explicit pairs), with wave-cooperative tape writes.  The
+// FP64 Lorenz / Tsit5 record needs 114 VGPRs at four blocks per CU; its 37 KB
+// of LDS (a whole group of records per lane and the write queue) admit no
+// more.  2^20 trajectories are 16 waves per SIMD: four full rounds.
 template <class Sys, class Tab, class T>
 struct DeferBlocks {
   static constexpr int value =
