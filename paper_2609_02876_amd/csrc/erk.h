@@ -548,6 +548,9 @@ __device__ __forceinline__ void flush_recs_sw(const uint4* stage, int count, cha
   for (int c = 0; c < count * CH; ++c) dst[c] = stage[c * 256 + (l ^ (c & 7))];
 }
 
+typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) U32x4 GlobalU32x4;
+
 // The lanes' parts in flush_groups_wave, fixed for a wavefront whose lanes
 // all run the loop: with `per` groups written per store instruction, lane
 // rank r among the live lanes writes chunk c = r mod G of the (r / G)-th
@@ -603,8 +606,11 @@ __device__ __forceinline__ void flush_groups_wave(const uint4* stage, uint4* que
   for (int b = 0; b < cnt; b += f.per) {
     if (f.helper && b + f.gj < cnt) {
       const uint4 e = queue[f.qi + b];
-      uint4* dst = reinterpret_cast<uint4*>(((uint64_t)e.y << 32) | (uint64_t)e.x);
-      dst[c] = stage[c * 256 + ((int)e.z ^ (c & 7))];
+      // a global-memory pointer: a generic (flat) store would also count
+      // against the LDS wait of the next round's reads
+      GlobalU32x4* dst = (GlobalU32x4*)(((uint64_t)e.y << 32) | (uint64_t)e.x);
+      const uint4 v = stage[c * 256 + ((int)e.z ^ (c & 7))];
+      dst[c] = U32x4{v.x, v.y, v.z, v.w};
     }
   }
   gp = nullptr;
