@@ -100,13 +100,15 @@ def load_traffic(path, workload):
     return tr
 
 
-def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
+def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None, solve=False):
     """HBM bytes per launch of the record and the sweep kernel, from rocprofv3
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch).  Each counter is scaled by
     known / counted for the calibration copy of `mib` MiB (the device copy
     kernel with the largest count); the full-size dispatches of each kernel
     (the largest grid: the pool-sizing pilot is smaller; the instantiation
-    dispatched most often) are averaged."""
+    dispatched most often) are averaged.  `solve`: the forward-only solve
+    kernel alone, as "record" (the record of the same inputs that counts the
+    work runs once, outside the timed steps)."""
     import csv
     import glob
 
@@ -126,9 +128,11 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None):
         out = {}
         # a part's kernels: the explicit pairs' full-tape record is two
         # launches (the loop, then the save states), each counted once
-        for part, keys in (("record", ("_forward_kernel<", "erk_record_deferred_kernel<",
-                                       "erk_saves_kernel<")),
-                           ("adjoint", ("_adjoint_kernel<",)), ("jvp", ("jvp_kernel<",))):
+        parts = ((("record", ("_forward_kernel<",)),) if solve else
+                 (("record", ("_forward_kernel<", "erk_record_deferred_kernel<",
+                              "erk_saves_kernel<")),
+                  ("adjoint", ("_adjoint_kernel<",)), ("jvp", ("jvp_kernel<",))))
+        for part, keys in parts:
             ks = [r for r in rows if any(k in r["Kernel_Name"] for k in keys)]
             if not ks:
                 if part == "record":
@@ -254,7 +258,8 @@ def main():
         from paper_2609_02876_amd import workloads as W
         n = args.n or W.WORKLOADS[args.workload]["n"]
         key = args.workload + {"forward": "_forward", "solve": "_solve"}.get(args.mode, "")
-        return write_traffic(*args.write_traffic, key, n, args.copy_calibration or 1024)
+        return write_traffic(*args.write_traffic, key, n, args.copy_calibration or 1024,
+                             solve=args.mode == "solve")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the ensemble "
               "shards by trajectory with no exchange, so more GPUs are not exercised here.",
