@@ -127,10 +127,11 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None, solve=False
                              f"{mib << 10} KiB: no calibration copy of {mib} MiB in this run")
         out = {}
         # a part's kernels: the explicit pairs' full-tape record is two
-        # launches (the loop, then the save states), each counted once
+        # launches (the loop, then the save states; the dense record's loop,
+        # then the states from the continuous extension), each counted once
         parts = ((("record", ("_forward_kernel<",)),) if solve else
                  (("record", ("_forward_kernel<", "erk_record_deferred_kernel<",
-                              "erk_saves_kernel<")),
+                              "erk_saves_kernel<", "dense_saves_kernel<")),
                   ("adjoint", ("_adjoint_kernel<",)), ("jvp", ("jvp_kernel<",))))
         for part, keys in parts:
             ks = [r for r in rows if any(k in r["Kernel_Name"] for k in keys)]
@@ -258,6 +259,7 @@ def main():
         from paper_2609_02876_amd import workloads as W
         n = args.n or W.WORKLOADS[args.workload]["n"]
         key = args.workload + {"forward": "_forward", "solve": "_solve"}.get(args.mode, "")
+        key += ("_dense" if args.dense else "") + ("_registered" if args.registered else "")
         return write_traffic(*args.write_traffic, key, n, args.copy_calibration or 1024,
                              solve=args.mode == "solve")
     if args.gpus != 1:
@@ -393,7 +395,10 @@ def reverse_bench(cfg, y0, p, st, steps, warmup, workload, dense=False, register
     f_dom, ms_dom = (f_adj, adj_ms) if dominant == "adjoint" else (f_rec, rec_ms)
     achieved = f_dom / (ms_dom * 1e-3) / 1e12
     traffic = None
-    tr = load_traffic(traffic_path, workload)
+    # measured bytes belong to the kernels they were taken on: the dense and
+    # the registered records have files of their own
+    tr = load_traffic(traffic_path, workload + ("_dense" if dense else "") +
+                      ("_registered" if registered else ""))
     if tr is not None and tr.get("n") == n:
         traffic = tr.get(dominant)
     if cfg["system"] == "ude":
