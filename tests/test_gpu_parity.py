@@ -219,6 +219,43 @@ def test_mesh_roundtrip_and_determinism():
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("system,method,dtype,n", [
+    ("lorenz", "tsit5", "f64", 1), ("lorenz", "tsit5", "f64", 7), ("lorenz", "tsit5", "f64", 65),
+    ("lorenz", "tsit5", "f32", 71), ("vdp", "vern7", "f64", 136), ("linear", "tsit5", "f32", 9)])
+def test_cooperative_tape_small_wavefronts(system, method, dtype, n):
+    """The explicit pairs' record writes its tape a wavefront at a time, eight
+    lanes to a group of four records; a wavefront with fewer live lanes than a
+    group has chunks (n mod 64 < 8 in the last one) writes each lane's groups
+    itself.  At such sizes the tape must hold exactly the record's mesh and
+    base states: replaying the exported mesh (whose tape each lane writes on
+    its own) gives the same save states and gradients to the bit, and in FP64
+    the oracle on the GPU's mesh agrees within 1e-11."""
+    print(f"case cooperative tape {system} {method} {dtype} n={n}", flush=True)
+    y0, p = _case(system, n, seed=n)
+    t1 = {"lorenz": 10.0, "vdp": 6.3, "linear": 8.0}[system]
+    st = list(W.save_times(0.0, t1, 20))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    hd = _gpu_record(system, method, y0, p, t1, 1e-6, 1e-8, st, dtype=tdt)
+    gp, gy, ll = B.ensemble_adjoint(hd, want_loss=True)
+    h, S = B.ensemble_mesh_export(hd)
+    hr = B.ensemble_replay_mesh(system, method, _dev(y0.T, tdt), _dev(p.T, tdt), 0.0, t1, h, S,
+                                save_times=st)
+    gp2, gy2, ll2 = B.ensemble_adjoint(hr, want_loss=True)
+    torch.cuda.synchronize()
+    assert np.all(hd.status.cpu().numpy() == 0) and np.all(hr.status.cpu().numpy() == 0)
+    assert torch.equal(hd.y_save, hr.y_save)
+    assert torch.equal(gp, gp2) and torch.equal(gy, gy2) and torch.equal(ll, ll2)
+    if dtype == "f64":
+        so, mo = SYS_O[system], MET_O[method]
+        gm = oracle_mesh(hd)
+        ys_g = O.replay(so, mo, y0, p, gm)
+        gp_g, gy_g, _ = O.adjoint(so, mo, y0, p, gm)
+        e = (_rel(hd.y_save.cpu().numpy(), np.transpose(ys_g, (1, 2, 0))).max(),
+             _rel(gp.cpu().numpy(), gp_g.T).max(), _rel(gy.cpu().numpy(), gy_g.T).max())
+        print(f"  own mesh vs oracle: states {e[0]:.2e} grad_p {e[1]:.2e} grad_y0 {e[2]:.2e}")
+        assert max(e) <= TOL64
+
+
 def test_loss_kinds_match_oracle():
     n, t1 = 300, 3.0
     y0, p = _case("lorenz", n, seed=4)
