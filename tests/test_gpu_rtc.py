@@ -222,3 +222,45 @@ def test_registered_jacobian_pattern(method):
         if a is None:
             continue
         assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def _chain16_source():
+    """A 16-dimensional linear chain written out term by term (no loops in a
+    registered source): f_i = -p_(i mod 4) y_i + y_(i+1 mod 16)."""
+    d = 16
+    rhs = "\n".join(f"    f[{i}] = fmaT(-p[{i % 4}], y[{i}], y[{(i + 1) % d}]);" for i in range(d))
+    gy = "\n".join(f"    gy[{i}] = fmaT(-p[{i % 4}], w[{i}], w[{(i - 1) % d}]);" for i in range(d))
+    gp = "\n".join(f"    gp[{k}] = gp[{k}] - (" + " + ".join(f"y[{i}] * w[{i}]" for i in range(k, d, 4))
+                   + ");" for k in range(4))
+    return ("struct System {\n  template <class T>\n  __device__ static void rhs(const T* y, const T* p, T* f) {\n"
+            + rhs + "\n  }\n  template <class T>\n"
+            "  __device__ static void vjp(const T* y, const T* p, const T* w, T* gy, T* gp) {\n"
+            + gy + "\n" + gp + "\n  }\n};\n")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_registered_wide_system_tape(dtype):
+    """The widest registered state (16 components: 136-byte FP64 records, a group
+    of four records is 34 chunks of 16 bytes, one group per cooperative write
+    round and 152 KB of LDS a block): replaying the exported mesh, whose tape
+    each lane writes on its own, gives the record's save states and gradients
+    to the bit."""
+    if "rtc_chain16" not in A.SYSTEMS:
+        B.register_system("rtc_chain16", _chain16_source(), 16, 4)
+    n, t1 = 200, 4.0
+    rng = np.random.default_rng(16)
+    y0 = rng.standard_normal((n, 16))
+    p = 0.5 + rng.random((n, 4))
+    st = [1.0, 2.0, 2.5, 4.0]
+    print(f"case registered chain16 {dtype} n={n}", flush=True)
+    h = B.ensemble_record("rtc_chain16", "tsit5", _dev(y0.T, dtype), _dev(p.T, dtype), 0.0, t1,
+                          1e-6, 1e-8, save_times=st, steps_hint=256)
+    gp, gy, ll = B.ensemble_adjoint(h)
+    hm, S = B.ensemble_mesh_export(h)
+    r = B.ensemble_replay_mesh("rtc_chain16", "tsit5", _dev(y0.T, dtype), _dev(p.T, dtype), 0.0,
+                               t1, hm, S, save_times=st)
+    gp2, gy2, ll2 = B.ensemble_adjoint(r)
+    torch.cuda.synchronize()
+    assert np.all(h.status.cpu().numpy() == 0) and int(S.min().item()) > 8
+    assert torch.equal(h.y_save, r.y_save)
+    assert torch.equal(gp, gp2) and torch.equal(gy, gy2) and torch.equal(ll, ll2)
