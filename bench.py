@@ -411,8 +411,7 @@ def reverse_bench(cfg, y0, p, st, steps, warmup, workload, dense=False, register
         kname = f"ude_{'adjoint' if dominant == 'adjoint' else 'forward'}_kernel (f32)"
     else:
         bound, peak = "alu", (PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS)
-        deferred = (cfg["method"] in ("tsit5", "vern7") and not ckpt and not registered
-                    and not dense)
+        deferred = cfg["method"] in ("tsit5", "vern7") and not ckpt and not dense
         kname = ("erk_adjoint_kernel" if dominant == "adjoint" else
                  # explicit pairs' full-tape record: the loop, then the save states
                  "erk_record_deferred_kernel + erk_saves_kernel" if deferred else

@@ -491,9 +491,18 @@ int launch_forward_body(const ens_problem* p, int mode, bool ckpt, const FwdArgs
       return e == hipSuccess ? ENS_OK : hip_fail(e, "dense save-state launch");
     });
   }
-  if (is_rtc(p->system))
+  if (is_rtc(p->system)) {
+    if (mode == MODE_RECORD && !ckpt && (p->method == ENS_TSIT5 || p->method == ENS_VERN7)) {
+      // the explicit pairs' full-tape record forms its save states afterwards
+      const int rc = rtc_launch(p->system, p->method, p->dtype,
+                                deferred_expr(p->method, p->dtype), grid_of(fa.ivp.n), fa, st);
+      if (rc != ENS_OK) return rc;
+      return rtc_launch(p->system, p->method, p->dtype, saves_expr(p->method, p->dtype),
+                        grid_of(fa.ivp.n), fa, st);
+    }
     return rtc_launch(p->system, p->method, p->dtype, fwd_expr(p->method, p->dtype, mode, ckpt),
                       grid_of(fa.ivp.n), fa, st);
+  }
   return with_kernels(p->system, p->method, p->dtype, [&](auto s, auto m, auto t) {
     using Sys = decltype(s);
     using Tab = decltype(m);

@@ -128,6 +128,11 @@ std::vector<std::string> rtc_exprs(int method, int dtype) {
     for (const char* ck : {"false", "true"})
       v.push_back("ens::erk_adjoint_kernel<" + pre + ", " + sh + ", " + ck + ">");
   v.push_back("ens::jvp_kernel<" + pre + ">");
+  if (method == ENS_TSIT5 || method == ENS_VERN7) {
+    // the explicit pairs' full-tape record: the loop, then the save states
+    v.push_back("ens::erk_record_deferred_kernel<" + pre + ">");
+    v.push_back("ens::erk_saves_kernel<" + pre + ">");
+  }
   return v;
 }
 
@@ -140,6 +145,14 @@ std::string adj_expr(int method, int dtype, bool shared, bool ckpt) {
   return std::string("ens::erk_adjoint_kernel<ens::RtcSys, ") + tab_name(method) + ", " +
          (dtype == ENS_F64 ? "double" : "float") + ", " + (shared ? "true" : "false") + ", " +
          (ckpt ? "true" : "false") + ">";
+}
+std::string deferred_expr(int method, int dtype) {
+  return std::string("ens::erk_record_deferred_kernel<ens::RtcSys, ") + tab_name(method) + ", " +
+         (dtype == ENS_F64 ? "double" : "float") + ">";
+}
+std::string saves_expr(int method, int dtype) {
+  return std::string("ens::erk_saves_kernel<ens::RtcSys, ") + tab_name(method) + ", " +
+         (dtype == ENS_F64 ? "double" : "float") + ">";
 }
 std::string jvp_expr(int method, int dtype) {
   return std::string("ens::jvp_kernel<ens::RtcSys, ") + tab_name(method) + ", " +
