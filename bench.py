@@ -29,9 +29,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    # six warm-ups: after the set-up's idle spell (the pool's allocation) the
-    # GPU's clock needs about 50 ms of load to settle; with three, the first
-    # two timed steps of the headline run 20 % and 8 % slow
+    # six warm-ups: the GPU's clock needs sustained load to settle (after the
+    # set-up's idle spell, three warm-ups leave the first two timed steps of
+    # the headline 20 % and 8 % slow; a cold GPU needs longer still)
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="lorenz_2p20_t10")
     ap.add_argument("--registered", action="store_true",
