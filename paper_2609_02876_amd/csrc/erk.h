@@ -1529,14 +1529,35 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   constexpr bool AT_END = Tab::ROS && Tab::SU >= 6;
   if constexpr (AT_END) take_saves();
 
+  // CKPT: a wave-uniform loop (the wavefront leaves it when no lane is
+  // live).  A lane replaying and a lane reversing then take one step each
+  // per trip; with a per-lane loop the compiler made the replay a loop of its
+  // own, and a lane reversing waited for every other lane's whole segment.
+  bool live = true;
   while (true) {
+    if constexpr (CKPT) {
+      if (!__any(live)) break;
+      if (!live) continue;
+    }
     if constexpr (!AT_END) {
       if (!rebuild) {
         take_saves();
-        if (i == 0) break;
+        if (i == 0) {
+          if constexpr (CKPT) {
+            live = false;
+            continue;
+          }
+          break;
+        }
       }
     } else {
-      if (i == 0) break;
+      if (i == 0) {
+        if constexpr (CKPT) {
+          live = false;
+          continue;
+        }
+        break;
+      }
     }
 
     T yb[D];

@@ -108,6 +108,10 @@ WORKLOADS = {
                            rtol=1e-6, atol=1e-8, n_save=0),
     "lorenz_2p20_t10": dict(system="lorenz", method="tsit5", n=1 << 20, t0=0.0, t1=10.0,
                             rtol=1e-6, atol=1e-8, n_save=20),
+    # the same with a checkpointed tape: a state every 64 steps and the step
+    # sizes, the segments replayed in the sweep
+    "lorenz_2p20_t10_ckpt64": dict(system="lorenz", method="tsit5", n=1 << 20, t0=0.0,
+                                   t1=10.0, rtol=1e-6, atol=1e-8, n_save=20, ckpt_every=64),
     # stiff: Rodas4, FP64, rtol 1e-6, atol 1e-10, loss on 20 save states
     "robertson_2p18_t1e5": dict(system="robertson", method="rodas4", n=1 << 18, t0=0.0,
                                 t1=1e5, rtol=1e-6, atol=1e-10, n_save=20),
