@@ -1502,8 +1502,13 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   T y_rb[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) y_rb[c] = T(0);
+  // the next replay step's size, loaded one step ahead so that its latency
+  // hides behind the current step
+  double h_rb = 0.0;
   auto start_segment = [&](int len) {
-    load_state<T, D>(R.pages + (int64_t)page * R.page_bytes, y_rb);
+    const char* pgp = R.pages + (int64_t)page * R.page_bytes;
+    load_state<T, D>(pgp, y_rb);
+    h_rb = ((const double*)(pgp + YB))[0];
     rebuild = true;
     j_rb = 0;
     seg_len = len;
@@ -1564,7 +1569,9 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
     double hh;
     {
       if (CKPT && rebuild) {
-        hh = ((const double*)(R.pages + (int64_t)page * R.page_bytes + YB))[j_rb];
+        hh = h_rb;
+        if (j_rb + 1 < seg_len)
+          h_rb = ((const double*)(R.pages + (int64_t)page * R.page_bytes + YB))[j_rb + 1];
 #pragma unroll
         for (int c = 0; c < D; ++c) yb[c] = y_rb[c];
       } else if constexpr (!STAGE) {
@@ -1607,8 +1614,20 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
                                                     nullptr);
     }
     if (CKPT && rebuild) {
-      // one replay step of the segment: keep its record, move on
-      store_rec<T, D>(scr + j_rb * RB, hh, yb);
+      // one replay step of the segment: keep its record, move on.  Records
+      // of up to 32 bytes wait in this lane's group slots (free while it
+      // replays) and go out a whole group (one cache line) at a time; the
+      // segment's last group stays there for the reverse steps that follow.
+      if constexpr (STAGE) {
+        const int q = j_rb & (TAPE_GROUP - 1);
+        stage_rec<T, D>(s_rd, q * CH, hh, yb);
+        if (q == TAPE_GROUP - 1 || j_rb + 1 == seg_len) {
+          flush_recs<T, D>(s_rd, q + 1, scr + (j_rb - q) * RB);
+          if (j_rb + 1 == seg_len) grp = j_rb - q;
+        }
+      } else {
+        store_rec<T, D>(scr + j_rb * RB, hh, yb);
+      }
 #pragma unroll
       for (int c = 0; c < D; ++c) y_rb[c] = ys[c];
       if (++j_rb == seg_len) rebuild = false;
