@@ -77,13 +77,16 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash():
+def kernel_source_hash(forward=False):
     """Hash of the HIP sources: measured traffic is used only for the build it
-    was measured on."""
+    was measured on.  The forward-mode kernel's own source counts only for
+    forward-mode traffic, the one measurement that runs it."""
     import hashlib
     d = os.path.join(ROOT, "paper_2609_02876_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
+        if f == "jvp.h" and not forward:
+            continue
         if f.endswith((".h", ".hip")):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
@@ -98,7 +101,7 @@ def load_traffic(path, workload):
     if not os.path.exists(path):
         return None
     tr = json.load(open(path))
-    if tr.get("source_hash") != kernel_source_hash():
+    if tr.get("source_hash") != kernel_source_hash(workload.endswith("_forward")):
         return None
     return tr
 
@@ -161,7 +164,8 @@ def write_traffic(fetch_dir, write_dir, workload, n, mib, path=None, solve=False
 
     fe, ff = read(fetch_dir, "FETCH_SIZE")
     wr, wf = read(write_dir, "WRITE_SIZE")
-    tr = {"workload": workload, "n": n, "source_hash": kernel_source_hash(),
+    tr = {"workload": workload, "n": n,
+          "source_hash": kernel_source_hash(workload.endswith("_forward")),
           "calibration": {"copy_mib": mib, "fetch_factor": ff, "write_factor": wf}}
     for part in [q for q in ("record", "adjoint", "jvp") if q in fe and q in wr]:
         fb, wb = fe[part]["kib"] * 1024 * ff, wr[part]["kib"] * 1024 * wf
