@@ -125,10 +125,15 @@ __device__ __forceinline__ void jvp_phi(const DT* y, const DT* p, double h, DT* 
 //   MSE_TARGET: 2 scale sum (y - target) . ydot
 //   COTANGENT:  sum c . ydot
 // A trajectory whose record failed gets NaN tangents.
-// (The FP64 Lorenz / Tsit5 pass holds 220 registers, two waves per SIMD;
-// asking for three spills 64 bytes a lane and runs 9 % slower.)
+// The FP64 Lorenz / Tsit5 pass is held to 128 VGPRs, four waves per SIMD.
 template <class Sys, class Tab, class T>
-__global__ void __launch_bounds__(256) jvp_kernel(const JvpArgs a) {
+struct JvpBlocks {
+  static constexpr int value =
+      (Sys::ID == 1 && Tab::ORDER == 5 && !Tab::ROS && sizeof(T) == 8) ? 4 : 1;
+};
+
+template <class Sys, class Tab, class T>
+__global__ void __launch_bounds__(256, (JvpBlocks<Sys, Tab, T>::value)) jvp_kernel(const JvpArgs a) {
   using DT = Dual<T>;
   constexpr int D = Sys::D, NP = Sys::NP;
   const int64_t n = a.ivp.n;
@@ -163,19 +168,33 @@ __global__ void __launch_bounds__(256) jvp_kernel(const JvpArgs a) {
   int s = 0;
   int32_t sidx = R.save_idx[tr];
   double sdt = R.save_dt[tr];
-  for (int32_t i = 0;; ++i) {
-    // saves whose base is y_i: one step of size t_s - t_i
-    while (s < ns && sidx == i) {
-      DT ys[D];
-      jvp_phi<Sys, Tab, DT>(y, p, sdt, ys);
+  // One step of the dual-number map a trip: a save step (size t_s - t_i from
+  // y_i, whose state is an output) while a save's base is y_i, else mesh step
+  // i.  Taking either kind through the same call keeps the lanes of a
+  // wavefront in one step evaluation whichever kind each needs; a save step
+  // taken as a second call beside the mesh step would cost the wavefront two
+  // evaluations on nearly every trip, since some lane saves on most of them.
+  int32_t i = 0;
+  for (;;) {
+    const bool save = s < ns && sidx == i;
+    if (!save && i >= S) break;
+    double hh = sdt;
+    if (!save) {
+      const int slot = i % K;
+      if (i > 0 && slot == 0) page = next_page(R, tr, page);
+      hh = *(const double*)(R.pages + (int64_t)page * R.page_bytes + a.h_off + slot * a.rec_b);
+    }
+    DT yn[D];
+    jvp_phi<Sys, Tab, DT>(y, p, hh, yn);
+    if (save) {
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        if (ysd) ysd[((int64_t)s * D + c) * n + tr] = ys[c].d;
-        const double dv = (double)ys[c].d;
+        if (ysd) ysd[((int64_t)s * D + c) * n + tr] = yn[c].d;
+        const double dv = (double)yn[c].d;
         if (a.loss_kind == LOSS_SUMSQ) {
-          ldot = fmaT((double)ys[c].v, dv, ldot);
+          ldot = fmaT((double)yn[c].v, dv, ldot);
         } else if (a.loss_kind == LOSS_MSE_TARGET) {
-          const T r = ys[c].v - data[((int64_t)s * D + c) * n + tr];
+          const T r = yn[c].v - data[((int64_t)s * D + c) * n + tr];
           ldot = fmaT((double)r, dv, ldot);
         } else if (a.loss_kind == LOSS_COTANGENT) {
           ldot = fmaT((double)data[((int64_t)s * D + c) * n + tr], dv, ldot);
@@ -186,16 +205,11 @@ __global__ void __launch_bounds__(256) jvp_kernel(const JvpArgs a) {
         sidx = R.save_idx[(int64_t)s * n + tr];
         sdt = R.save_dt[(int64_t)s * n + tr];
       }
-    }
-    if (i >= S) break;
-    const int slot = i % K;
-    if (i > 0 && slot == 0) page = next_page(R, tr, page);
-    const double h =
-        *(const double*)(R.pages + (int64_t)page * R.page_bytes + a.h_off + slot * a.rec_b);
-    DT yn[D];
-    jvp_phi<Sys, Tab, DT>(y, p, h, yn);
+    } else {
 #pragma unroll
-    for (int c = 0; c < D; ++c) y[c] = yn[c];
+      for (int c = 0; c < D; ++c) y[c] = yn[c];
+      ++i;
+    }
   }
   if (a.loss_dot)
     a.loss_dot[tr] = a.loss_kind == LOSS_COTANGENT ? ldot : 2.0 * a.scale * ldot;
