@@ -152,6 +152,42 @@ def test_forward_passes_equal_reverse_gradient(system, method, t1):
         assert err <= 1e-9
 
 
+@pytest.mark.parametrize("system,method,t1,st,cluster", [
+    # a save at t0, a repeated save time, four saves inside one step, one at t1
+    ("lorenz", "tsit5", 3.0, [0.0, 0.5, 0.5, 1.0, 1.0 + 1e-4, 1.0 + 2e-4, 1.0 + 3e-4, 3.0], 3),
+    ("robertson", "rodas4", 1e5, [0.0, 1e-3, 1e-3, 10.0, 4e4, 4e4 + 1.0, 4e4 + 2.0, 1e5], 4),
+])
+def test_jvp_save_order_edges(system, method, t1, st, cluster):
+    """Save steps and mesh steps share the pass's loop, one step a trip:
+    saves whose base is the same mesh point (a save at t0, repeated and
+    clustered save times) are taken in save order before the next mesh
+    step, and saves at t1 after the last one."""
+    n = 200 if system == "lorenz" else 129
+    print(f"case jvp save edges {system} {method} n={n}", flush=True)
+    y0, p = GEN[system](n, seed=12)
+    dy, dp = _tangents(y0, p, seed=13)
+    rtol, atol = TOL[system]
+    h = B.ensemble_record(system, method, _dev(y0.T), _dev(p.T), 0.0, t1, rtol, atol,
+                          save_times=st, steps_hint=512)
+    ysd, ld = B.ensemble_jvp(h, _dev(dy.T), _dev(dp.T))
+    torch.cuda.synchronize()
+    assert np.all(h.status.cpu().numpy() == 0)
+    rec, ys_o, dys_o = _oracle(system, method, y0, p, dy, dp, h)
+    si = rec["save_idx"]
+    # the cases this test is for occur: a save at t0 (base index 0, offset 0),
+    # saves sharing a base point, and saves at t1 (base index S)
+    assert np.all(si[:, 0] == 0) and np.all(rec["save_dt"][:, 0] == 0.0)
+    assert np.all(si[:, 1] == si[:, 2])
+    assert np.mean(si[:, cluster] == si[:, cluster + 2]) > 0.5
+    assert np.all(si[:, -1] == rec["S"])
+    e = _rel(ysd.cpu().numpy(), np.transpose(dys_o, (1, 2, 0))).max()
+    print(f"  state tangents vs oracle: {e:.2e}")
+    assert e <= 1e-11
+    l_ref = 2.0 * np.sum(ys_o * dys_o, axis=(1, 2))
+    mag = 2.0 * np.sum(np.abs(ys_o * dys_o), axis=(1, 2))
+    assert (np.abs(ld.cpu().numpy() - l_ref) / np.maximum(mag, 1e-300)).max() <= 1e-13
+
+
 def test_jvp_checkpointed_tape_and_failed_lanes():
     n = 700
     y0, p = W.lorenz(n, seed=6)
