@@ -129,6 +129,14 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
+// Largest value over the 64 lanes of a wavefront, by butterfly exchanges
+// (lane ^ 1, ^ 2, ..., ^ 32); every lane of the wavefront must be active.
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) x = max(x, __shfl_xor(x, m));
+  return x;
+}
+
 // ----------------------------------------------------------- record view --
 // Device view of a record (see ens_record in ensode.h for the meaning).
 struct RecView {

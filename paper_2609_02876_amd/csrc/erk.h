@@ -1420,7 +1420,8 @@ __device__ __forceinline__ int sweep_slot(const RecView& R, int64_t base, int64_
 // sweep first replays each segment forward into this trajectory's scratch
 // page (full step records, the same arithmetic as the record, so the same
 // bits), then walks it backward.  Replay steps and reverse steps share one
-// loop iteration so that lanes at different phases do not serialize.
+// loop iteration so that lanes at different phases do not serialize, and the
+// lanes of a wavefront are aligned by segment (first_gap below).
 //
 // DENSE: the saves come from the continuous extension of the step holding
 // each one (dense_saves_reverse); each save's cotangent reaches both end
@@ -1450,6 +1451,30 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   __shared__ T s_W[W_LDS ? lu_nnz<Sys>() * 256 : 1];
   const RecView& R = a.rec;
   const bool ok = valid && R.status[tr] == LANE_OK;
+  // CKPT: lanes of a wavefront aligned by segment.  A lane's first segment
+  // (the last of its tape) holds r = (S - 1) mod K + 1 steps, its F others K
+  // each.  Each lane waits first_gap = L - r trips before replaying its first
+  // segment and as many again after reversing it; from then on all its
+  // lanes replay their K-step segments in the same trips and reverse them in
+  // the same trips, so a replay trip skips the reverse step's work for the
+  // whole wavefront.  L = r_max, the wavefront's longest first segment, when
+  // that adds no trips to the unaligned 2 S_max (2 (r_max + K F_max) =
+  // 2 S_max: the step counts do not straddle a multiple of K); else L = K
+  // when the 2 K (F_max + 1) trips that takes are at most a quarter more
+  // (half of them replay trips); else the lanes are left unaligned.  (Every
+  // lane of the wavefront is here.)
+  int first_gap = 0;
+  if constexpr (CKPT) {
+    const int S0 = ok ? R.steps[tr] : 0;
+    const int r = S0 > 0 ? (S0 - 1) % K + 1 : 0;
+    const int r_max = wave_max(r);
+    const int F_max = wave_max(S0 > 0 ? (S0 - r) / K : 0);
+    const int S_max = wave_max(S0);
+    if (r_max + K * F_max <= S_max)
+      first_gap = r_max - r;
+    else if (4 * (int64_t)K * (F_max + 1) <= 5 * (int64_t)S_max)
+      first_gap = K - r;
+  }
   T* gpo = (T*)a.grad_p;
   T* gyo = (T*)a.grad_y0;
   T lam[D], gp[NP];
@@ -1539,10 +1564,15 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
   // per trip; with a per-lane loop the compiler made the replay a loop of its
   // own, and a lane reversing waited for every other lane's whole segment.
   bool live = true;
+  int wait = first_gap;  // trips this lane idles before its next replay
   while (true) {
     if constexpr (CKPT) {
       if (!__any(live)) break;
       if (!live) continue;
+      if (wait > 0) {
+        --wait;
+        continue;
+      }
     }
     if constexpr (!AT_END) {
       if (!rebuild) {
@@ -1664,7 +1694,11 @@ __device__ __forceinline__ void erk_adjoint_body(const AdjArgs& a, int64_t block
       page = prev_page(R, page);
       slot = K - 1;
       grp = -1;
-      if (CKPT) start_segment(K);
+      if (CKPT) {
+        start_segment(K);
+        wait = first_gap;
+        first_gap = 0;
+      }
     }
   }
 
