@@ -78,7 +78,7 @@ def expected_order(s, k):
     return out
 
 
-@pytest.mark.parametrize("k", [1, 4, 16, 64, 256])
+@pytest.mark.parametrize("k", [16, 32, 64, 128, 256])   # the segment lengths the library takes
 def test_schedule_order_alignment_and_trips(k):
     rng = np.random.default_rng(k)
     for trial in range(60):

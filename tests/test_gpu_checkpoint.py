@@ -95,3 +95,58 @@ def test_checkpoint_pool_overflow_pages():
     assert B.ensemble_record_stats(ck)["overflow_pages_used"] > 0
     for a, b in zip(g_full, g_ck):
         assert torch.equal(a, b)
+
+
+def _align_mode(steps, k):
+    """Which of the sweep's lane alignments a wavefront takes (restated from
+    the sweep's source): 'r_max', 'k' (first segments padded to K) or None."""
+    r = [(s - 1) % k + 1 for s in steps]
+    f = [(s - q) // k for s, q in zip(steps, r)]
+    if max(r) + k * max(f) <= max(steps):
+        return "r_max"
+    if 4 * k * (max(f) + 1) <= 5 * max(steps):
+        return "k"
+    return None
+
+
+@pytest.mark.parametrize("k", [16, 32, 64, 128, 256])
+def test_checkpoint_alignment_on_given_meshes(k):
+    """Step counts chosen so that the checkpointed sweep's lane alignment
+    takes each of its forms (at K = 64 one wavefront is left unaligned, one
+    aligned to its longest first segment and two padded to K): the sweep
+    equals the full tape's bit for bit and the oracle's on the same mesh."""
+    n = 256
+    lane = np.arange(64)
+    steps = np.concatenate([250 + lane % 13, 300 + lane % 11, 60 + lane % 11,
+                            np.random.default_rng(5).integers(5, 400, 64)]).astype(np.int32)
+    # the sweep takes a block's lanes in step-count order, so wavefront w
+    # holds the counts of rank 64 w .. 64 w + 63 of the block (one block here)
+    srt = sorted(int(s) for s in steps)
+    modes = [_align_mode(srt[w * 64:(w + 1) * 64], k) for w in range(4)]
+    print(f"case ckpt alignment k={k} modes={modes}", flush=True)
+    if k == 64:
+        assert set(modes) == {"r_max", "k", None}
+    t1 = 2.0
+    cap = int(steps.max())
+    h = np.zeros((cap, n))
+    for l in range(n):
+        h[:steps[l], l] = t1 / steps[l]
+    y0, p = W.damped_rotation(n, seed=8)
+    st = list(W.save_times(0.0, t1, 20))
+    args = ("linear", "tsit5", _dev(y0.T), _dev(p.T), 0.0, t1, _dev(h),
+            torch.tensor(steps, device="cuda"))
+    full = B.ensemble_replay_mesh(*args, save_times=st)
+    ck = B.ensemble_replay_mesh(*args, save_times=st, ckpt_every=k)
+    g_full = B.ensemble_adjoint(full)
+    g_ck = B.ensemble_adjoint(ck)
+    torch.cuda.synchronize()
+    assert bool((ck.status == 0).all()) and torch.equal(full.steps(), ck.steps())
+    assert torch.equal(full.y_save, ck.y_save)
+    for a, b in zip(g_full, g_ck):
+        assert torch.equal(a, b)
+    gp_o, gy_o, _ = O.adjoint(O.LINEAR, O.TSIT5, y0, p, oracle_mesh(ck))
+    for got, ref in ((g_ck[0].cpu().numpy(), gp_o.T), (g_ck[1].cpu().numpy(), gy_o.T)):
+        # per-lane normwise relative error (lanes last)
+        err = (np.linalg.norm(got - ref, axis=0) /
+               np.maximum(np.linalg.norm(ref, axis=0), 1e-300)).max()
+        assert err <= 1e-11, err
