@@ -117,6 +117,12 @@ WORKLOADS = {
                                 t1=1e5, rtol=1e-6, atol=1e-10, n_save=20),
     "hires_2p18": dict(system="hires", method="rodas4", n=1 << 18, t0=0.0, t1=321.8122,
                        rtol=1e-6, atol=1e-10, n_save=20),
+    # the same two with checkpointed tapes (a state every 64 steps)
+    "robertson_2p18_t1e5_ckpt64": dict(system="robertson", method="rodas4", n=1 << 18,
+                                       t0=0.0, t1=1e5, rtol=1e-6, atol=1e-10, n_save=20,
+                                       ckpt_every=64),
+    "hires_2p18_ckpt64": dict(system="hires", method="rodas4", n=1 << 18, t0=0.0,
+                              t1=321.8122, rtol=1e-6, atol=1e-10, n_save=20, ckpt_every=64),
     # the same two with Rosenbrock23 (order 2, three stages in a trial step)
     "robertson_ros23_2p18_t1e5": dict(system="robertson", method="ros23", n=1 << 18, t0=0.0,
                                       t1=1e5, rtol=1e-6, atol=1e-10, n_save=20),
